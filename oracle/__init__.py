@@ -1,0 +1,215 @@
+"""TPFA flux oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper around ``libtpfa_oracle.so`` (built from ``tpfa_oracle.cpp``
+with g++, no GPU code). Only the test suite, the smoke entry point and the
+CPU-baseline leg of the benchmark may import this package; the GPU library
+never does, and this package never imports the GPU library.
+
+Everything is FP64 on host numpy arrays of shape (nz, ny, nx), x fastest.
+``grid`` is any object with nx, ny, nz, dx, dy, dz, gk and ``fluid`` any object
+with rho0, cf, p0, mu (the ``geomodel`` dataclasses fit).
+
+See ``tpfa_oracle.cpp`` for the equations followed (paper Sec. 3, Eqs. 3-5,
+Algorithm 1) and the readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tpfa_oracle.cpp")
+LIB = os.path.join(HERE, "libtpfa_oracle.so")
+
+# Plain build: no fast-math, no FMA contraction, so every operation is the
+# IEEE-rounded operation written in the source.
+BUILD_CMD = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-Wall", "-Wextra", SRC, "-o", LIB]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = BUILD_CMD[:-1] + [tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("gk", C.c_double)]
+
+
+class _Fluid(C.Structure):
+    _fields_ = [("rho_ref", C.c_double), ("cf", C.c_double), ("p_ref", C.c_double),
+                ("mu", C.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        lib = C.CDLL(LIB)
+        vp = C.c_void_p
+        lib.oracle_eval.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, vp, vp,
+                                    C.c_double, C.c_double, vp, vp, vp, vp, vp, vp, vp,
+                                    vp, vp, vp]
+        lib.oracle_rows.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, vp, vp,
+                                    C.c_double, C.c_double, vp, vp, vp, vp, C.c_int64,
+                                    vp, vp, vp]
+        lib.oracle_eval_ld.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                       C.c_double, C.c_double, vp, vp, vp, vp]
+        lib.oracle_eval_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                       C.c_double, C.c_double, vp, vp, vp, vp,
+                                       C.c_double, vp, vp]
+        lib.oracle_hydrostatic.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid),
+                                           C.c_double, vp]
+        for fn in ("oracle_eval", "oracle_rows", "oracle_eval_ld", "oracle_eval_cs",
+                   "oracle_hydrostatic"):
+            getattr(lib, fn).restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _g(grid) -> _Grid:
+    return _Grid(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.dx),
+                 float(grid.dy), float(grid.dz), float(grid.gk))
+
+
+def _f(fluid) -> _Fluid:
+    return _Fluid(float(fluid.rho0), float(fluid.cf), float(fluid.p0), float(fluid.mu))
+
+
+def _arr(a, dtype, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None and a.size != int(np.prod(shape)):
+        raise ValueError(f"array of size {a.size} does not match {shape}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def evaluate(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None, ky=None, kz=None,
+             w=None, force=None, want=("r", "J")) -> dict:
+    """Residual and any of: J [7, nz, ny, nx], grad_p, grad_logk (need w),
+    scale [2, ...] (sum |F|, sum |dF/dp_K|), dphi [3, ...] (face potential
+    differences, NaN where no face). ``force`` is an int8 [3, ...] upwind
+    override per face (+1 lower cell, -1 upper cell, 0 rule)."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    n = int(np.prod(shape))
+    kx = _arr(kx, np.float64, shape)
+    p = _arr(p, np.float64, shape)
+    ky = _arr(ky, np.float64, shape)
+    kz = _arr(kz, np.float64, shape)
+    seal = _arr(seal, np.uint8, shape)
+    w = _arr(w, np.float64, shape)
+    force = _arr(force, np.int8, (3,) + shape)
+    out = {}
+    bufs = {}
+    for key, sh in (("r", shape), ("J", (7,) + shape), ("grad_p", shape),
+                    ("grad_logk", shape), ("scale", (2,) + shape), ("dphi", (3,) + shape)):
+        bufs[key] = np.empty(sh, np.float64) if key in want else None
+    rc = _load().oracle_eval(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), _ptr(ky),
+                             _ptr(kz), float(ry), float(rz), _ptr(seal), _ptr(p),
+                             _ptr(force), _ptr(w), _ptr(bufs["r"]), _ptr(bufs["J"]),
+                             _ptr(bufs["grad_p"]), _ptr(bufs["grad_logk"]),
+                             _ptr(bufs["scale"]), _ptr(bufs["dphi"]))
+    if rc != 0:
+        raise ValueError("oracle_eval rejected its arguments")
+    for key in want:
+        out[key] = bufs[key]
+    assert n > 0
+    return out
+
+
+def rows(grid, fluid, kx, p, cells, *, ry=1.0, rz=1.0, seal=None, ky=None, kz=None,
+         force=None):
+    """(r[n], J[7, n], scale[2, n]) for the listed linear cell indices."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx = _arr(kx, np.float64, shape)
+    p = _arr(p, np.float64, shape)
+    ky = _arr(ky, np.float64, shape)
+    kz = _arr(kz, np.float64, shape)
+    seal = _arr(seal, np.uint8, shape)
+    force = _arr(force, np.int8, (3,) + shape)
+    cells = np.ascontiguousarray(cells, dtype=np.int64).ravel()
+    n = cells.size
+    r = np.empty(n)
+    J = np.empty((7, n))
+    s = np.empty((2, n))
+    rc = _load().oracle_rows(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), _ptr(ky),
+                             _ptr(kz), float(ry), float(rz), _ptr(seal), _ptr(p),
+                             _ptr(force), _ptr(cells), n, _ptr(r), _ptr(J), _ptr(s))
+    if rc != 0:
+        raise ValueError("oracle_rows rejected its arguments")
+    return r, J, s
+
+
+def evaluate_ld(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None):
+    """Residual and Jacobian in long double (x87 80-bit on x86-64)."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx = _arr(kx, np.float64, shape)
+    p = _arr(p, np.float64, shape)
+    seal = _arr(seal, np.uint8, shape)
+    r = np.empty(shape, np.longdouble)
+    J = np.empty((7,) + shape, np.longdouble)
+    rc = _load().oracle_eval_ld(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx),
+                                float(ry), float(rz), _ptr(seal), _ptr(p), _ptr(r), _ptr(J))
+    if rc != 0:
+        raise ValueError("oracle_eval_ld rejected its arguments")
+    return r, J
+
+
+def evaluate_cs(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None, vp=None, vm=None,
+                h=1e-20):
+    """Complex-step residual: returns (Re r, Im r / h) for the perturbation
+    p + i h vp, ln kx + i h vm."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx = _arr(kx, np.float64, shape)
+    p = _arr(p, np.float64, shape)
+    seal = _arr(seal, np.uint8, shape)
+    vp = _arr(vp, np.float64, shape)
+    vm = _arr(vm, np.float64, shape)
+    re = np.empty(shape)
+    im = np.empty(shape)
+    rc = _load().oracle_eval_cs(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx),
+                                float(ry), float(rz), _ptr(seal), _ptr(p), _ptr(vp),
+                                _ptr(vm), float(h), _ptr(re), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_eval_cs rejected its arguments")
+    return re, im / h
+
+
+def hydrostatic(grid, fluid, p_top: Optional[float] = None) -> np.ndarray:
+    """Discrete hydrostatic reference profile pref[nz] (FP64)."""
+    pref = np.empty(int(grid.nz))
+    top = float(fluid.p0 if p_top is None else p_top)
+    rc = _load().oracle_hydrostatic(C.byref(_g(grid)), C.byref(_f(fluid)), top, _ptr(pref))
+    if rc != 0:
+        raise ValueError("oracle_hydrostatic rejected its arguments")
+    return pref
+
+
+def pressure(geo, r: int = 0) -> np.ndarray:
+    """Pressure field r of a geomodel: hydrostatic reference plus noise."""
+    pref = hydrostatic(geo.grid, geo.fluid, geo.p_top)
+    return pref[:, None, None] + geo.noise[r]
+
+
+def widen_fp32(dp32: np.ndarray, pref: np.ndarray) -> np.ndarray:
+    """FP64 pressure seen by the precision form: pref[k] + (double) dp."""
+    return pref[:, None, None] + dp32.astype(np.float64)

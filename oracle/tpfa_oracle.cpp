@@ -1,0 +1,422 @@
+// TPFA flux oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, obviously correct CPU reference for the flux part of the
+// finite-volume residual of compressible single-phase Darcy flow, used to
+// check the GPU library. Only the test suite, the smoke entry point and the
+// CPU-baseline leg of the benchmark load it; it shares no source, header or
+// helper with the GPU library.
+//
+// What it computes (paper, Sec. 3 "Finite Volume for Geologic Carbon Storage
+// Simulation"):
+//   rho_K      = rho_ref * exp(c_f * (p_K - p_ref))                   Eq. (5)
+//   F_KL       = Ups_KL * lambda_upw * dPhi_KL                        Eq. (3a)
+//   dPhi_KL    = (p_K - p_L) + rho_avg * g * (zeta_L - zeta_K)        Eq. (3b), read as Phi_K - Phi_L
+//   rho_avg    = (rho_K + rho_L) / 2                                  "the average" of the two densities
+//   lambda_upw = rho_K / mu if dPhi_KL > 0, else rho_L / mu           Eq. (4), tie -> lower index
+//   r_K        = sum over the neighbours L of K of F_KL                Algorithm 1 / Eq. (2) flux sum
+// evaluated exactly as Algorithm 1 orders it: an outer loop over cells K, an
+// inner loop over the neighbours L of K, both densities evaluated for every
+// (K, L) pair, and the flux added to r_K.
+//
+// Readings where the paper is silent or inconsistent (each one is listed in
+// the design notes of the repository):
+//  * Orientation of dPhi: Eq. (3b) as printed is Phi_L - Phi_K, which makes
+//    Eq. (4) pick the downstream cell; F_KL is taken as the outflow of K, i.e.
+//    dPhi_KL = Phi_K - Phi_L, so the upwind cell is the higher-potential one.
+//  * zeta is the cell-centre coordinate along +k and g (grid.gk) the gravity
+//    component along +k: with k pointing down, gk = +9.81 and hydrostatic
+//    pressure grows with k.
+//  * Ups_KL (no formula in the paper) is the two-point harmonic
+//    transmissibility a_d * 2 k_K k_L / (k_K + k_L) with a_x = dy dz / dx,
+//    a_y = dx dz / dy, a_z = dx dy / dz and the directional permeability;
+//    a sealed face, or k_K + k_L = 0, has Ups = 0.
+//  * Ties dPhi_KL = 0: the lower linear index is upwind, so that both sides of
+//    a face make the same choice (the flux is 0 either way).
+//  * Domain boundary: no-flow; boundary cells simply have fewer neighbours.
+//  * The accumulation term of Eq. (2) is excluded, as in the paper.
+//
+// Jacobian: the 7-point derivative of r with respect to p, stored as seven
+// planes [diag, -x, +x, -y, +y, -z, +z]; plane 1+n holds dr_K/dp_L for the
+// neighbour n of K (0 where that neighbour does not exist).
+//
+// Vector-Jacobian product with cotangent w: grad_p = J^T w and
+// grad_logk[j] = sum_K w_K d r_K / d ln(kx_j), where ky = ry kx and kz = rz kx
+// follow kx (ratios, not separate arrays).
+//
+// Parity pins (tests/test_oracle_*.py): closed-form two-cell fluxes, the
+// continuous hydrostatic column, the c_f = 0 graph Laplacian built by SciPy,
+// complex-step derivatives for J and for the log-permeability gradient, a
+// long-double evaluation, conservation, equilibria and scaling invariants.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdlib>
+
+extern "C" {
+
+typedef struct {
+  int64_t nx, ny, nz;
+  double dx, dy, dz;
+  double gk;  // gravity component along +k (m/s^2)
+} oracle_grid;
+
+typedef struct {
+  double rho_ref, cf, p_ref, mu;
+} oracle_fluid;
+
+}  // extern "C"
+
+namespace {
+
+using cplx = std::complex<double>;
+
+inline double real_part(double v) { return v; }
+inline double real_part(long double v) { return (double)v; }
+inline double real_part(const cplx& v) { return v.real(); }
+
+template <class S>
+struct Problem {
+  const oracle_grid* g;
+  const oracle_fluid* f;
+  const S* p;                  // pressure per cell (Pa)
+  const S* kx;                 // permeability along x (m^2)
+  const S* ky;                 // NULL -> ry * kx
+  const S* kz;                 // NULL -> rz * kx
+  double ry, rz;
+  const uint8_t* seal;         // NULL or bit a set: face towards +a neighbour closed
+  const int8_t* force;         // NULL or [3][N]: +1 / -1 forces the lower / upper cell upwind
+  int64_t ncell() const { return g->nx * g->ny * g->nz; }
+};
+
+// Eq. (5)
+template <class S>
+S density(const S& p, const oracle_fluid& f) {
+  using std::exp;
+  return S(f.rho_ref) * exp(S(f.cf) * (p - S(f.p_ref)));
+}
+
+template <class S>
+S perm(const Problem<S>& pb, int axis, int64_t c) {
+  if (axis == 0) return pb.kx[c];
+  if (axis == 1) return pb.ky ? pb.ky[c] : S(pb.ry) * pb.kx[c];
+  return pb.kz ? pb.kz[c] : S(pb.rz) * pb.kx[c];
+}
+
+// face area over centre-to-centre distance for a face normal to `axis`
+double geom_factor(const oracle_grid& g, int axis) {
+  if (axis == 0) return g.dy * g.dz / g.dx;
+  if (axis == 1) return g.dx * g.dz / g.dy;
+  return g.dx * g.dy / g.dz;
+}
+
+// Neighbour n of a cell, n = 0..5 -> (-x, +x, -y, +y, -z, +z).
+struct Nb {
+  bool exists;
+  int64_t L;
+  int axis;
+  int side;  // -1 or +1
+};
+
+Nb neighbour(const oracle_grid& g, int64_t i, int64_t j, int64_t k, int n) {
+  Nb nb;
+  nb.axis = n / 2;
+  nb.side = (n % 2) ? 1 : -1;
+  int64_t ii = i, jj = j, kk = k;
+  if (nb.axis == 0) ii += nb.side;
+  if (nb.axis == 1) jj += nb.side;
+  if (nb.axis == 2) kk += nb.side;
+  nb.exists = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+  nb.L = nb.exists ? ii + g.nx * (jj + g.ny * kk) : -1;
+  return nb;
+}
+
+template <class S>
+struct FluxKL {
+  S F;        // F_KL, outflow of K towards L
+  S dF_dpK;   // dF_KL / dp_K
+  S dF_dpL;   // dF_KL / dp_L
+  S T;        // transmissibility
+  S kK, kL;   // directional permeabilities of K and L
+  S dPhi;     // potential difference Phi_K - Phi_L
+};
+
+// One flux of the inner loop of Algorithm 1, seen from cell K.
+template <class S>
+FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
+  const oracle_grid& g = *pb.g;
+  const oracle_fluid& f = *pb.f;
+  FluxKL<S> out;
+  const int64_t lo = side > 0 ? K : L;  // lower-index cell of the face
+
+  // transmissibility (harmonic two-point form, closed if sealed)
+  out.kK = perm(pb, axis, K);
+  out.kL = perm(pb, axis, L);
+  const bool sealed = pb.seal && ((pb.seal[lo] >> axis) & 1u);
+  const S ksum = out.kK + out.kL;
+  if (sealed || real_part(ksum) == 0.0)
+    out.T = S(0);
+  else
+    out.T = S(geom_factor(g, axis)) * ((S(2) * (out.kK * out.kL)) / ksum);
+
+  // densities in K and L (Eq. 5), their average and pressure derivatives
+  const S pK = pb.p[K], pL = pb.p[L];
+  const S rhoK = density(pK, f), rhoL = density(pL, f);
+  const S rho_avg = S(0.5) * (rhoK + rhoL);
+  const S drhoK = S(f.cf) * rhoK, drhoL = S(f.cf) * rhoL;
+
+  // elevation difference zeta_L - zeta_K along +k
+  const double dzeta = axis == 2 ? side * g.dz : 0.0;
+
+  // potential difference (Eq. 3b, outflow orientation)
+  out.dPhi = (pK - pL) + (rho_avg * S(g.gk)) * S(dzeta);
+  const S dPhi_dpK = S(1) + (S(0.5) * drhoK * S(g.gk)) * S(dzeta);
+  const S dPhi_dpL = S(-1) + (S(0.5) * drhoL * S(g.gk)) * S(dzeta);
+
+  // single-point upwinding (Eq. 4); a tie goes to the lower index
+  bool upK;
+  const int8_t forced = pb.force ? pb.force[(int64_t)axis * pb.ncell() + lo] : 0;
+  if (forced != 0) {
+    upK = (forced > 0) == (K == lo);
+  } else {
+    const double d = real_part(out.dPhi);
+    upK = d > 0.0 || (d == 0.0 && K < L);
+  }
+  const S lamK = rhoK / S(f.mu), lamL = rhoL / S(f.mu);
+  const S dlamK = drhoK / S(f.mu), dlamL = drhoL / S(f.mu);
+  const S lam = upK ? lamK : lamL;
+
+  // flux (Eq. 3a) and its derivatives
+  out.F = (out.T * lam) * out.dPhi;
+  out.dF_dpK = out.T * ((upK ? dlamK * out.dPhi : S(0)) + lam * dPhi_dpK);
+  out.dF_dpL = out.T * ((upK ? S(0) : dlamL * out.dPhi) + lam * dPhi_dpL);
+  return out;
+}
+
+struct Outputs {
+  void* r = nullptr;       // [N]
+  void* J = nullptr;       // [7][N]
+  const double* w = nullptr;
+  void* grad_p = nullptr;  // [N]
+  void* grad_m = nullptr;  // [N] gradient with respect to ln kx
+  double* scale = nullptr; // [2][N]: sum |F_KL|, sum |dF_KL/dp_K|
+  double* dphi = nullptr;  // [3][N]: dPhi of the face (c, c + e_a) seen from c; NaN if absent
+};
+
+template <class S>
+void assemble(const Problem<S>& pb, const Outputs& o) {
+  const oracle_grid& g = *pb.g;
+  const int64_t N = pb.ncell();
+  S* r = static_cast<S*>(o.r);
+  S* J = static_cast<S*>(o.J);
+  S* gp = static_cast<S*>(o.grad_p);
+  S* gm = static_cast<S*>(o.grad_m);
+
+  // r := 0 (Algorithm 1), and the other accumulators
+  for (int64_t c = 0; c < N; ++c) {
+    if (r) r[c] = S(0);
+    if (J)
+      for (int e = 0; e < 7; ++e) J[e * N + c] = S(0);
+    if (gp) gp[c] = S(0);
+    if (gm) gm[c] = S(0);
+    if (o.scale) o.scale[c] = o.scale[N + c] = 0.0;
+    if (o.dphi)
+      for (int a = 0; a < 3; ++a) o.dphi[a * N + c] = NAN;
+  }
+
+  // for each cell K, for each neighbour L of K (Algorithm 1)
+  for (int64_t k = 0; k < g.nz; ++k)
+    for (int64_t j = 0; j < g.ny; ++j)
+      for (int64_t i = 0; i < g.nx; ++i) {
+        const int64_t K = i + g.nx * (j + g.ny * k);
+        for (int n = 0; n < 6; ++n) {
+          const Nb nb = neighbour(g, i, j, k, n);
+          if (!nb.exists) continue;
+          const FluxKL<S> fl = flux(pb, K, nb.L, nb.axis, nb.side);
+          if (r) r[K] += fl.F;
+          if (J) {
+            J[K] += fl.dF_dpK;
+            J[(1 + n) * N + K] = fl.dF_dpL;
+          }
+          if (o.w) {
+            const S wK = S(o.w[K]);
+            if (gp) {
+              gp[K] += wK * fl.dF_dpK;
+              gp[nb.L] += wK * fl.dF_dpL;
+            }
+            // dUps/d ln k_K = Ups * k_L / (k_K + k_L); the ratios ry, rz cancel
+            if (gm && real_part(fl.T) != 0.0) {
+              const S ksum = fl.kK + fl.kL;
+              gm[K] += wK * (fl.F * fl.kL / ksum);
+              gm[nb.L] += wK * (fl.F * fl.kK / ksum);
+            }
+          }
+          if (o.scale) {
+            o.scale[K] += std::abs(real_part(fl.F));
+            o.scale[N + K] += std::abs(real_part(fl.dF_dpK));
+          }
+          if (o.dphi && nb.side > 0) o.dphi[nb.axis * N + K] = real_part(fl.dPhi);
+        }
+      }
+}
+
+// Rows of r and J for a list of cells, same inner loop as assemble().
+void rows(const Problem<double>& pb, const int64_t* cells, int64_t n, double* r,
+          double* J, double* scale) {
+  const oracle_grid& g = *pb.g;
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t K = cells[q];
+    const int64_t i = K % g.nx, j = (K / g.nx) % g.ny, k = K / (g.nx * g.ny);
+    double rK = 0.0, s0 = 0.0, s1 = 0.0;
+    double row[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int e = 0; e < 6; ++e) {
+      const Nb nb = neighbour(g, i, j, k, e);
+      if (!nb.exists) continue;
+      const FluxKL<double> fl = flux(pb, K, nb.L, nb.axis, nb.side);
+      rK += fl.F;
+      row[0] += fl.dF_dpK;
+      row[1 + e] = fl.dF_dpL;
+      s0 += std::abs(fl.F);
+      s1 += std::abs(fl.dF_dpK);
+    }
+    if (r) r[q] = rK;
+    if (J)
+      for (int e = 0; e < 7; ++e) J[e * n + q] = row[e];
+    if (scale) {
+      scale[q] = s0;
+      scale[n + q] = s1;
+    }
+  }
+}
+
+bool valid(const oracle_grid* g, const oracle_fluid* f, const void* p, const void* kx) {
+  return g && f && p && kx && g->nx > 0 && g->ny > 0 && g->nz > 0 && g->dx > 0 &&
+         g->dy > 0 && g->dz > 0 && f->mu > 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// r, J, grad_p, grad_logk, scale and dphi are each optional (NULL = not wanted);
+// grad_p / grad_logk need w. ky/kz NULL means ry*kx / rz*kx. Returns 0, or -1 on
+// invalid arguments.
+int oracle_eval(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                const double* ky, const double* kz, double ry, double rz,
+                const uint8_t* seal, const double* p, const int8_t* force,
+                const double* w, double* r, double* J, double* grad_p,
+                double* grad_logk, double* scale, double* dphi) {
+  if (!valid(g, f, p, kx)) return -1;
+  if ((grad_p || grad_logk) && !w) return -1;
+  if (grad_logk && (ky || kz)) return -1;
+  Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
+  Outputs o;
+  o.r = r;
+  o.J = J;
+  o.w = w;
+  o.grad_p = grad_p;
+  o.grad_m = grad_logk;
+  o.scale = scale;
+  o.dphi = dphi;
+  assemble(pb, o);
+  return 0;
+}
+
+// r and the 7 Jacobian entries of the listed cells only (J as [7][n]).
+int oracle_rows(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                const double* ky, const double* kz, double ry, double rz,
+                const uint8_t* seal, const double* p, const int8_t* force,
+                const int64_t* cells, int64_t n, double* r, double* J, double* scale) {
+  if (!valid(g, f, p, kx) || (n > 0 && !cells)) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  for (int64_t q = 0; q < n; ++q)
+    if (cells[q] < 0 || cells[q] >= N) return -1;
+  Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
+  rows(pb, cells, n, r, J, scale);
+  return 0;
+}
+
+// The same residual and Jacobian evaluated in long double (inputs widened).
+int oracle_eval_ld(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                   double ry, double rz, const uint8_t* seal, const double* p,
+                   long double* r, long double* J) {
+  if (!valid(g, f, p, kx)) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  long double* pl = (long double*)std::malloc(sizeof(long double) * N);
+  long double* kl = (long double*)std::malloc(sizeof(long double) * N);
+  if (!pl || !kl) {
+    std::free(pl);
+    std::free(kl);
+    return -1;
+  }
+  for (int64_t c = 0; c < N; ++c) {
+    pl[c] = p[c];
+    kl[c] = kx[c];
+  }
+  Problem<long double> pb{g, f, pl, kl, nullptr, nullptr, ry, rz, seal, nullptr};
+  Outputs o;
+  o.r = r;
+  o.J = J;
+  assemble(pb, o);
+  std::free(pl);
+  std::free(kl);
+  return 0;
+}
+
+// Complex-step evaluation: p -> p + i h vp and ln kx -> ln kx + i h vm (either
+// direction may be NULL). Writes Re r and Im r; Im r / h is the directional
+// derivative of r along (vp, vm) to machine precision away from upwind switches.
+int oracle_eval_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                   double ry, double rz, const uint8_t* seal, const double* p,
+                   const double* vp, const double* vm, double h, double* r_re,
+                   double* r_im) {
+  if (!valid(g, f, p, kx) || !r_re || !r_im) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  cplx* pc = new cplx[N];
+  cplx* kc = new cplx[N];
+  cplx* rc = new cplx[N];
+  for (int64_t c = 0; c < N; ++c) {
+    pc[c] = cplx(p[c], vp ? h * vp[c] : 0.0);
+    // exp(ln kx + i h vm) = kx * exp(i h vm)
+    kc[c] = vm ? kx[c] * std::exp(cplx(0.0, h * vm[c])) : cplx(kx[c], 0.0);
+  }
+  Problem<cplx> pb{g, f, pc, kc, nullptr, nullptr, ry, rz, seal, nullptr};
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t c = 0; c < N; ++c) {
+    r_re[c] = rc[c].real();
+    r_im[c] = rc[c].imag();
+  }
+  delete[] pc;
+  delete[] kc;
+  delete[] rc;
+  return 0;
+}
+
+// Discrete hydrostatic column: pref[0] = p_top and, for every k,
+// pref[k+1] - pref[k] = (rho(pref[k]) + rho(pref[k+1])) / 2 * gk * dz, so that the
+// potential difference of the vertical face between two reference cells is zero.
+// Solved level by level with Newton's method until the iterate stops changing.
+int oracle_hydrostatic(const oracle_grid* g, const oracle_fluid* f, double p_top,
+                       double* pref) {
+  if (!g || !f || !pref || g->nz <= 0) return -1;
+  const double G = g->gk * g->dz;
+  pref[0] = p_top;
+  for (int64_t k = 0; k + 1 < g->nz; ++k) {
+    const double pk = pref[k];
+    const double rk = density(pk, *f);
+    double x = pk + rk * G;
+    for (int it = 0; it < 100; ++it) {
+      const double rx = density(x, *f);
+      const double res = x - pk - 0.5 * (rk + rx) * G;
+      const double der = 1.0 - 0.5 * f->cf * rx * G;
+      const double xn = x - res / der;
+      if (xn == x) break;
+      x = xn;
+    }
+    pref[k + 1] = x;
+  }
+  return 0;
+}
+
+}  // extern "C"
