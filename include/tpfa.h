@@ -1,0 +1,195 @@
+/*
+ * tpfa.h -- C ABI of libtpfa.so: the TPFA flux residual, its 7-point Jacobian
+ * and its vector-Jacobian product on a 3-D Cartesian grid, on one AMD MI355X
+ * (gfx950) GPU.
+ *
+ * What is computed (paper "Massively Distributed Finite-Volume Flux
+ * Computation", Sec. 3):
+ *   rho_K      = rho0 * exp(cf * (p_K - p0))                        Eq. (5)
+ *   lambda_K   = rho_K / mu                                         mobility, constant mu
+ *   Ups_KL     = a_d * 2 k_K k_L / (k_K + k_L)                       two-point harmonic transmissibility
+ *                (a_x = dy dz/dx, a_y = dx dz/dy, a_z = dx dy/dz; directional k;
+ *                 0 on a sealed face or when k_K + k_L = 0)
+ *   dPhi_KL    = (p_K - p_L) + (rho_K + rho_L)/2 * gk * (zeta_L - zeta_K)
+ *                                                                    Eq. (3b), outflow orientation
+ *   F_KL       = Ups_KL * lambda_up * dPhi_KL, lambda_up = lambda_K if
+ *                dPhi_KL > 0, lambda_L if < 0, the lower index on a tie  Eqs. (3a), (4)
+ *   r_K        = sum over the (up to six) face neighbours L of F_KL     Algorithm 1
+ * zeta is the cell-centre coordinate along +k and gk the gravity component
+ * along +k (k pointing down: gk = +9.81). Domain boundaries are no-flow. The
+ * accumulation term of the backward-Euler residual, Eq. (2), is not included.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are contiguous structure-of-arrays with x fastest:
+ *    idx = i + nx * (j + ny * k).
+ *  - Array pointers are DEVICE pointers (hipMalloc'ed or torch CUDA tensors)
+ *    owned by the caller, unless stated otherwise. Structs are read on the host
+ *    during the call and may be freed when it returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *    enqueue work and return without synchronising; they allocate nothing.
+ *  - Precision: TPFA_FP64 -> every array (p, kx, r, J, w, grads) is double.
+ *    TPFA_FP32 -> the "precision form": p holds FP32 offsets dp from an FP64
+ *    reference profile pref[nz] (p_K = pref[k] + dp_K in FP64), kx and outputs
+ *    are float; the potential difference and the residual / diagonal / gradient
+ *    accumulations are carried in FP64 and rounded once on store.
+ *  - Return value: TPFA_OK (0) or a negative TPFA_ERR_* code; the detail is in
+ *    tpfa_last_error() (thread-local). No C++ exception crosses the ABI.
+ *    Argument errors are detected on the host before anything is enqueued.
+ *    Data values are never inspected: NaNs propagate, kx >= 0 is the caller's
+ *    contract.
+ */
+#ifndef TPFA_H
+#define TPFA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPFA_OK 0
+#define TPFA_ERR_NULL (-1)        /* a required pointer is NULL */
+#define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, or nx*ny*nz overflows */
+#define TPFA_ERR_PARAM (-3)       /* mu <= 0, cell size <= 0, negative ratio, non-finite constant */
+#define TPFA_ERR_UNSUPPORTED (-4) /* unsupported combination (see each call) */
+#define TPFA_ERR_HIP (-5)         /* HIP runtime error, detail in tpfa_last_error() */
+#define TPFA_ERR_TILE (-6)        /* unknown tile id or z-chunk out of range */
+
+typedef enum { TPFA_FP64 = 0, TPFA_FP32 = 1 } tpfa_precision_t;
+
+/* Grid: cell counts, cell sizes (m), gravity component along +k (m/s^2). */
+typedef struct {
+  int64_t nx, ny, nz;
+  double dx, dy, dz;
+  double gk;
+} tpfa_grid_t;
+
+/* Fluid, Eq. (5) and constant viscosity (SI): rho0 (kg/m^3), cf (1/Pa),
+   p0 (Pa), mu (Pa s). */
+typedef struct {
+  double rho0, cf, p0, mu;
+} tpfa_fluid_t;
+
+/* Rock: kx (m^2, dtype of the precision) is required. ky and kz must be NULL:
+   the y and z permeabilities are ry*kx and rz*kx (ry, rz >= 0). seal may be
+   NULL; bit a (0, 1, 2 = x, y, z) of seal[idx] closes the face between the
+   cell and its +a neighbour (bits on domain-boundary faces are ignored). */
+typedef struct {
+  const void *kx, *ky, *kz;
+  double ry, rz;
+  const uint8_t *seal;
+} tpfa_rock_t;
+
+/* State: TPFA_FP64 -> p is absolute pressure (double, Pa), pref ignored.
+   TPFA_FP32 -> p is the float offset dp and pref (double[nz], device) is
+   required. */
+typedef struct {
+  const void *p;
+  const double *pref;
+} tpfa_state_t;
+
+/* Optional launch shape (pass NULL for the defaults): tile = id from
+   tpfa_tile_shape(), or -1; kz_chunk = z planes marched by one workgroup
+   (0 = default); flags bit 0 disables the XCD-aware workgroup order. */
+typedef struct {
+  int tile;
+  int kz_chunk;
+  int flags;
+} tpfa_launch_t;
+
+#define TPFA_LAUNCH_NO_XCD_REMAP 1
+
+/* Residual r[ncell] (paper Algorithm 1 with the Eq. (3)-(5) flux). */
+int tpfa_residual(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                  const tpfa_rock_t *rock, const tpfa_state_t *state,
+                  tpfa_precision_t prec, void *r, const tpfa_launch_t *launch,
+                  void *stream);
+
+/* Residual (r may be NULL) and Jacobian J[7][ncell]: plane 0 = dr_K/dp_K,
+   planes 1..6 = dr_K/dp_L for the -x, +x, -y, +y, -z, +z neighbour L (0 where
+   that neighbour does not exist). The paper names the flux derivatives with
+   respect to the state as a key step of the simulator (Sec. 2) but computes
+   only the residual; the derivative here is the exact derivative of the
+   residual above on the side of each upwind switch that the choice took. */
+int tpfa_jacobian(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                  const tpfa_rock_t *rock, const tpfa_state_t *state,
+                  tpfa_precision_t prec, void *r, void *J,
+                  const tpfa_launch_t *launch, void *stream);
+
+/* Vector-Jacobian product of the residual with the cotangent w[ncell]:
+   grad_p = J^T w (with respect to p, i.e. to dp in the precision form) and
+   grad_logk[j] = sum_K w_K d r_K / d ln(kx_j), ky = ry kx and kz = rz kx
+   following kx. The upwind choice is recomputed, not stored. Either output may
+   be NULL (not both). Unsupported (TPFA_ERR_UNSUPPORTED) with ky/kz arrays. */
+int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                      const tpfa_rock_t *rock, const tpfa_state_t *state,
+                      tpfa_precision_t prec, const void *w, void *grad_p,
+                      void *grad_logk, const tpfa_launch_t *launch, void *stream);
+
+/* Discrete hydrostatic reference column (double pref[nz], device): pref[0] =
+   p_top and pref[k+1] - pref[k] = (rho(pref[k]) + rho(pref[k+1]))/2 * gk * dz,
+   i.e. the profile whose vertical potential differences (Eq. 3b) vanish. The
+   offset reference of the precision form. One small kernel on `stream`. */
+int tpfa_hydrostatic(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, double p_top,
+                     double *pref, void *stream);
+
+/* Precision-form state from an FP64 pressure: dp[idx] = (float)(p[idx] - pref[k]). */
+int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double *pref,
+                         float *dp, void *stream);
+
+/* ---- Batched ensemble: many independent grids in one persistent launch ---- */
+
+/* One member of an ensemble. All pointers are device pointers that must stay
+   valid while the batch is used; r may be NULL; J is required for
+   TPFA_BATCH_JACOBIAN and ignored for TPFA_BATCH_RESIDUAL. launch.tile must be
+   one of the 256-thread tiles (tpfa_tile_shape reports the thread count). */
+typedef struct {
+  tpfa_grid_t grid;
+  tpfa_fluid_t fluid;
+  tpfa_rock_t rock;
+  tpfa_state_t state;
+  void *r;
+  void *J;
+  tpfa_launch_t launch;
+} tpfa_model_t;
+
+typedef enum { TPFA_BATCH_RESIDUAL = 0, TPFA_BATCH_JACOBIAN = 1 } tpfa_batch_mode_t;
+
+typedef struct tpfa_batch tpfa_batch_t; /* opaque */
+
+/* Builds the work list (one item per tile and z-chunk of every model, in
+   descending cost order) and the model table on the device (the batch owns
+   these two device buffers and a work counter), and captures one persistent
+   kernel launch into a HIP graph. `stream` orders the uploads. */
+int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
+                      tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream);
+
+/* Replays the captured graph on `stream`: all models, one persistent launch. */
+int tpfa_batch_run(tpfa_batch_t *batch, void *stream);
+
+/* The same persistent kernel launched directly, without the graph. */
+int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream);
+
+/* Number of work items and of persistent workgroups of a batch. */
+int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgroups);
+
+/* Frees the batch's device buffers and graph (synchronises its work first).
+   NULL is accepted. */
+void tpfa_batch_destroy(tpfa_batch_t *batch);
+
+/* ---- Introspection ---- */
+
+/* Number of compiled tile shapes; shape of tile `id`: TX x TY cells per
+   workgroup plane and the workgroup size in threads. */
+int tpfa_num_tiles(void);
+int tpfa_tile_shape(int id, int *tx, int *ty, int *threads);
+
+const char *tpfa_strerror(int code);
+const char *tpfa_last_error(void);
+int tpfa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPFA_H */

@@ -66,7 +66,7 @@ def _load():
                                     vp, vp, vp]
         lib.oracle_rows.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, vp, vp,
                                     C.c_double, C.c_double, vp, vp, vp, vp, C.c_int64,
-                                    vp, vp, vp]
+                                    vp, vp, vp, vp]
         lib.oracle_eval_ld.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                        C.c_double, C.c_double, vp, vp, vp, vp]
         lib.oracle_eval_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
@@ -137,8 +137,10 @@ def evaluate(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None, ky=None, kz=None,
 
 
 def rows(grid, fluid, kx, p, cells, *, ry=1.0, rz=1.0, seal=None, ky=None, kz=None,
-         force=None):
-    """(r[n], J[7, n], scale[2, n]) for the listed linear cell indices."""
+         force=None, with_dphi=False):
+    """(r[n], J[7, n], scale[2, n]) for the listed linear cell indices, plus
+    dphi[6, n] (face potential differences seen from each cell, NaN where no
+    face) when ``with_dphi``."""
     shape = (grid.nz, grid.ny, grid.nx)
     kx = _arr(kx, np.float64, shape)
     p = _arr(p, np.float64, shape)
@@ -151,11 +153,14 @@ def rows(grid, fluid, kx, p, cells, *, ry=1.0, rz=1.0, seal=None, ky=None, kz=No
     r = np.empty(n)
     J = np.empty((7, n))
     s = np.empty((2, n))
+    d = np.empty((6, n)) if with_dphi else None
     rc = _load().oracle_rows(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), _ptr(ky),
                              _ptr(kz), float(ry), float(rz), _ptr(seal), _ptr(p),
-                             _ptr(force), _ptr(cells), n, _ptr(r), _ptr(J), _ptr(s))
+                             _ptr(force), _ptr(cells), n, _ptr(r), _ptr(J), _ptr(s), _ptr(d))
     if rc != 0:
         raise ValueError("oracle_rows rejected its arguments")
+    if with_dphi:
+        return r, J, s, d
     return r, J, s
 
 

@@ -261,7 +261,7 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
 
 // Rows of r and J for a list of cells, same inner loop as assemble().
 void rows(const Problem<double>& pb, const int64_t* cells, int64_t n, double* r,
-          double* J, double* scale) {
+          double* J, double* scale, double* dphi) {
   const oracle_grid& g = *pb.g;
   for (int64_t q = 0; q < n; ++q) {
     const int64_t K = cells[q];
@@ -270,6 +270,7 @@ void rows(const Problem<double>& pb, const int64_t* cells, int64_t n, double* r,
     double row[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int e = 0; e < 6; ++e) {
       const Nb nb = neighbour(g, i, j, k, e);
+      if (dphi) dphi[e * n + q] = NAN;
       if (!nb.exists) continue;
       const FluxKL<double> fl = flux(pb, K, nb.L, nb.axis, nb.side);
       rK += fl.F;
@@ -277,6 +278,7 @@ void rows(const Problem<double>& pb, const int64_t* cells, int64_t n, double* r,
       row[1 + e] = fl.dF_dpL;
       s0 += std::abs(fl.F);
       s1 += std::abs(fl.dF_dpK);
+      if (dphi) dphi[e * n + q] = fl.dPhi;
     }
     if (r) r[q] = rK;
     if (J)
@@ -321,17 +323,20 @@ int oracle_eval(const oracle_grid* g, const oracle_fluid* f, const double* kx,
   return 0;
 }
 
-// r and the 7 Jacobian entries of the listed cells only (J as [7][n]).
+// r and the 7 Jacobian entries of the listed cells only (J as [7][n]); dphi
+// (optional, [6][n]) receives the potential difference of each of the cell's
+// six faces seen from the cell (NaN where the neighbour does not exist).
 int oracle_rows(const oracle_grid* g, const oracle_fluid* f, const double* kx,
                 const double* ky, const double* kz, double ry, double rz,
                 const uint8_t* seal, const double* p, const int8_t* force,
-                const int64_t* cells, int64_t n, double* r, double* J, double* scale) {
+                const int64_t* cells, int64_t n, double* r, double* J, double* scale,
+                double* dphi) {
   if (!valid(g, f, p, kx) || (n > 0 && !cells)) return -1;
   const int64_t N = g->nx * g->ny * g->nz;
   for (int64_t q = 0; q < n; ++q)
     if (cells[q] < 0 || cells[q] >= N) return -1;
   Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
-  rows(pb, cells, n, r, J, scale);
+  rows(pb, cells, n, r, J, scale, dphi);
   return 0;
 }
 

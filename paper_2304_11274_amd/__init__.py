@@ -1,0 +1,11 @@
+"""MI355X-native TPFA flux residual / Jacobian / adjoint (arXiv 2304.11274, Sec. 3).
+
+The numerical work runs in libtpfa.so (hand-written HIP for gfx950); this
+package only marshals torch tensors into its C ABI (include/tpfa.h).
+"""
+from ._lib import LIB_PATH, TpfaError, load  # noqa: F401
+from .api import (Ensemble, TPFAResidual, hydrostatic, jacobian, offset_pressure,  # noqa: F401
+                  residual, residual_vjp, tile_shapes)
+
+__all__ = ["Ensemble", "TPFAResidual", "hydrostatic", "jacobian", "offset_pressure",
+           "residual", "residual_vjp", "tile_shapes", "load", "TpfaError", "LIB_PATH"]

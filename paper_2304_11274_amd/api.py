@@ -1,0 +1,266 @@
+"""Python binding of libtpfa.so: argument marshalling only.
+
+Device memory comes from torch CUDA tensors (ROCm) and work is enqueued on
+torch's current stream; every computation runs in the library's HIP kernels.
+The precision is chosen by the dtype of ``p``: float64 -> the FP64 path,
+float32 -> the precision form (``p`` holds offsets from ``pref``).
+Tensors use the (nz, ny, nx) shape, x fastest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _grid(g) -> L.Grid:
+    return L.Grid(int(g.nx), int(g.ny), int(g.nz), float(g.dx), float(g.dy), float(g.dz),
+                  float(g.gk))
+
+
+def _fluid(f) -> L.Fluid:
+    return L.Fluid(float(f.rho0), float(f.cf), float(f.p0), float(f.mu))
+
+
+def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap: bool):
+    if tile is None and kz_chunk is None and xcd_remap:
+        return None
+    return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
+                    0 if xcd_remap else L.TPFA_LAUNCH_NO_XCD_REMAP)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _prec(p: torch.Tensor) -> int:
+    if p.dtype == torch.float64:
+        return L.TPFA_FP64
+    if p.dtype == torch.float32:
+        return L.TPFA_FP32
+    raise TypeError(f"p must be float64 or float32, got {p.dtype}")
+
+
+def _need(t, name, dtype, n, device):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor, got {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _inputs(grid, kx, p, seal, pref):
+    n = int(grid.nx) * int(grid.ny) * int(grid.nz)
+    prec = _prec(p)
+    dt = p.dtype
+    dev = p.device
+    _need(p, "p", dt, n, None)
+    _need(kx, "kx", dt, n, dev)
+    _need(seal, "seal", torch.uint8, n, dev)
+    if prec == L.TPFA_FP32:
+        if pref is None:
+            raise ValueError("the FP32 precision form needs pref (float64[nz])")
+        _need(pref, "pref", torch.float64, int(grid.nz), dev)
+    return n, prec, dt, dev
+
+
+def _rock(kx, seal, ry, rz) -> L.Rock:
+    return L.Rock(_ptr(kx), None, None, float(ry), float(rz), _ptr(seal))
+
+
+def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+             tile=None, kz_chunk=None, xcd_remap=True) -> torch.Tensor:
+    """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+    _need(r, "out", dt, n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_residual(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                              C.byref(_rock(kx, seal, ry, rz)),
+                              C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
+                              _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+    return r
+
+
+def _launch_ref(tile, kz_chunk, xcd_remap):
+    ln = _launch(tile, kz_chunk, xcd_remap)
+    return None if ln is None else C.byref(ln)
+
+
+def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r=True,
+             r_out=None, J_out=None, tile=None, kz_chunk=None, xcd_remap=True):
+    """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
+    [diag, -x, +x, -y, +y, -z, +z]."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    r = None
+    if want_r:
+        r = r_out if r_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+        _need(r, "r_out", dt, n, dev)
+    J = J_out if J_out is not None else torch.empty((7,) + tuple(p.shape), dtype=dt, device=dev)
+    _need(J, "J_out", dt, 7 * n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_jacobian(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                              C.byref(_rock(kx, seal, ry, rz)),
+                              C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
+                              _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+    return r, J
+
+
+def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
+                 want_p=True, want_logk=True, gp_out=None, gm_out=None, tile=None,
+                 kz_chunk=None, xcd_remap=True):
+    """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    _need(w, "w", dt, n, dev)
+    gp = gm = None
+    if want_p:
+        gp = gp_out if gp_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+        _need(gp, "gp_out", dt, n, dev)
+    if want_logk:
+        gm = gm_out if gm_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+        _need(gm, "gm_out", dt, n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_residual_vjp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                                  C.byref(_rock(kx, seal, ry, rz)),
+                                  C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w),
+                                  _ptr(gp), _ptr(gm), _launch_ref(tile, kz_chunk, xcd_remap),
+                                  _stream(dev)), lib)
+    return gp, gm
+
+
+def hydrostatic(grid, fluid, p_top: Optional[float] = None, device=None) -> torch.Tensor:
+    """Discrete hydrostatic reference column pref[nz] (float64, on the GPU)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda",
+                                                                       torch.cuda.current_device())
+    pref = torch.empty(int(grid.nz), dtype=torch.float64, device=dev)
+    lib = L.load()
+    top = float(fluid.p0 if p_top is None else p_top)
+    L.check(lib.tpfa_hydrostatic(C.byref(_grid(grid)), C.byref(_fluid(fluid)), top, _ptr(pref),
+                                 _stream(dev)), lib)
+    return pref
+
+
+def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torch.Tensor:
+    """FP32 offsets dp = (float)(p - pref[k]) of an FP64 pressure field."""
+    n = int(grid.nx) * int(grid.ny) * int(grid.nz)
+    _need(p, "p", torch.float64, n, None)
+    _need(pref, "pref", torch.float64, int(grid.nz), p.device)
+    dp = out if out is not None else torch.empty(p.shape, dtype=torch.float32, device=p.device)
+    _need(dp, "out", torch.float32, n, p.device)
+    lib = L.load()
+    L.check(lib.tpfa_offset_pressure(C.byref(_grid(grid)), _ptr(p), _ptr(pref), _ptr(dp),
+                                     _stream(p.device)), lib)
+    return dp
+
+
+def tile_shapes():
+    """[(tx, ty, threads)] of the compiled tiles, indexed by tile id."""
+    lib = L.load()
+    out = []
+    for t in range(lib.tpfa_num_tiles()):
+        tx, ty, th = C.c_int(), C.c_int(), C.c_int()
+        L.check(lib.tpfa_tile_shape(t, C.byref(tx), C.byref(ty), C.byref(th)), lib)
+        out.append((tx.value, ty.value, th.value))
+    return out
+
+
+class Ensemble:
+    """Many independent grids run by one persistent kernel replayed from a
+    HIP graph. ``members`` is a sequence of dicts with keys grid, fluid, kx,
+    p, and optionally seal, pref, ry, rz, tile, kz_chunk. Outputs are
+    allocated here (``r[m]``, ``J[m]``) and overwritten by every run."""
+
+    def __init__(self, members: Sequence[dict], *, mode: str = "jacobian", want_r: bool = True):
+        if not members:
+            raise ValueError("an ensemble needs at least one member")
+        self.mode = {"jacobian": L.TPFA_BATCH_JACOBIAN, "residual": L.TPFA_BATCH_RESIDUAL}[mode]
+        self.members = list(members)
+        self.r, self.J = [], []
+        arr = (L.Model * len(members))()
+        prec = None
+        for m, d in enumerate(self.members):
+            g, p = d["grid"], d["p"]
+            n, pr, dt, dev = _inputs(g, d["kx"], p, d.get("seal"), d.get("pref"))
+            if prec is None:
+                prec, self.device = pr, dev
+            elif pr != prec or dev != self.device:
+                raise ValueError("all ensemble members need the same precision and device")
+            r = torch.empty(p.shape, dtype=dt, device=dev) if (
+                want_r or self.mode == L.TPFA_BATCH_RESIDUAL) else None
+            J = torch.empty((7,) + tuple(p.shape), dtype=dt, device=dev) if (
+                self.mode == L.TPFA_BATCH_JACOBIAN) else None
+            self.r.append(r)
+            self.J.append(J)
+            arr[m] = L.Model(_grid(g), _fluid(d["fluid"]),
+                             _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
+                             L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
+                             L.Launch(int(d.get("tile", -1)), int(d.get("kz_chunk", 0)), 0))
+        self.prec = prec
+        self._handle = C.c_void_p()
+        self._lib = L.load()
+        L.check(self._lib.tpfa_batch_create(arr, len(self.members), prec, self.mode,
+                                            C.byref(self._handle), _stream(self.device)),
+                self._lib)
+
+    def run(self, graph: bool = True):
+        fn = self._lib.tpfa_batch_run if graph else self._lib.tpfa_batch_run_eager
+        L.check(fn(self._handle, _stream(self.device)), self._lib)
+
+    def info(self):
+        n = C.c_int64()
+        wg = C.c_int()
+        L.check(self._lib.tpfa_batch_info(self._handle, C.byref(n), C.byref(wg)), self._lib)
+        return n.value, wg.value
+
+    def close(self):
+        if self._handle:
+            self._lib.tpfa_batch_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TPFAResidual(torch.autograd.Function):
+    """r(p, ln kx) with a hand-written adjoint.
+
+    forward: kx = exp(logk) (the log-permeability parameterisation), then the
+    residual kernel; backward: the vector-Jacobian kernel, which recomputes the
+    upwind choices, returns (J^T w, d(w.r)/d ln kx). Non-tensor arguments:
+    grid, fluid, seal, pref, ry, rz."""
+
+    @staticmethod
+    def forward(ctx, p, logk, grid, fluid, seal=None, pref=None, ry=1.0, rz=1.0):
+        kx = torch.exp(logk)
+        r = residual(grid, fluid, kx, p, seal=seal, pref=pref, ry=ry, rz=rz)
+        ctx.save_for_backward(p, kx)
+        ctx.cfg = (grid, fluid, seal, pref, ry, rz)
+        return r
+
+    @staticmethod
+    def backward(ctx, w):
+        p, kx = ctx.saved_tensors
+        grid, fluid, seal, pref, ry, rz = ctx.cfg
+        gp, gm = residual_vjp(grid, fluid, kx, p, w.contiguous(), seal=seal, pref=pref, ry=ry,
+                              rz=rz, want_p=ctx.needs_input_grad[0],
+                              want_logk=ctx.needs_input_grad[1])
+        return gp, gm, None, None, None, None, None, None

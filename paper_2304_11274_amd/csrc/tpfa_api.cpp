@@ -1,0 +1,447 @@
+// C-ABI layer of libtpfa.so: argument validation, launch-shape selection and
+// the batched-ensemble object. Every argument error is detected here, on the
+// host, before anything is enqueued; HIP errors are reported with their text.
+// No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tpfa.h"
+#include "tpfa_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return TPFA_OK;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int check_grid(const tpfa_grid_t *g) {
+  if (!g) return fail(TPFA_ERR_NULL, "grid is NULL");
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0)
+    return fail(TPFA_ERR_SHAPE, "grid dimensions must be positive");
+  const int64_t lim = std::numeric_limits<int32_t>::max();
+  if (g->nx > lim || g->ny > lim || g->nz > lim)
+    return fail(TPFA_ERR_SHAPE, "each grid dimension must fit in 32 bits");
+  if (g->nx > std::numeric_limits<int64_t>::max() / g->ny ||
+      g->nx * g->ny > std::numeric_limits<int64_t>::max() / 8 / 7 / g->nz)
+    return fail(TPFA_ERR_SHAPE, "nx*ny*nz overflows");
+  if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !is_finite(g->dx) || !is_finite(g->dy) ||
+      !is_finite(g->dz))
+    return fail(TPFA_ERR_PARAM, "cell sizes must be positive and finite");
+  if (!is_finite(g->gk)) return fail(TPFA_ERR_PARAM, "gk must be finite");
+  return TPFA_OK;
+}
+
+int check_fluid(const tpfa_fluid_t *f) {
+  if (!f) return fail(TPFA_ERR_NULL, "fluid is NULL");
+  if (!(f->mu > 0) || !is_finite(f->mu)) return fail(TPFA_ERR_PARAM, "mu must be positive");
+  if (!is_finite(f->rho0) || !is_finite(f->cf) || !is_finite(f->p0))
+    return fail(TPFA_ERR_PARAM, "rho0, cf and p0 must be finite");
+  return TPFA_OK;
+}
+
+int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t *rk,
+                 const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if ((rc = check_fluid(f))) return rc;
+  if (!rk) return fail(TPFA_ERR_NULL, "rock is NULL");
+  if (!st) return fail(TPFA_ERR_NULL, "state is NULL");
+  if (prec != TPFA_FP64 && prec != TPFA_FP32)
+    return fail(TPFA_ERR_PARAM, "unknown precision");
+  if (!rk->kx) return fail(TPFA_ERR_NULL, "rock.kx is NULL");
+  if (rk->ky || rk->kz)
+    return fail(TPFA_ERR_UNSUPPORTED, "ky/kz arrays are not supported; use ry/rz ratios");
+  if (!(rk->ry >= 0) || !(rk->rz >= 0) || !is_finite(rk->ry) || !is_finite(rk->rz))
+    return fail(TPFA_ERR_PARAM, "ry and rz must be finite and >= 0");
+  if (!st->p) return fail(TPFA_ERR_NULL, "state.p is NULL");
+  if (prec == TPFA_FP32 && !st->pref)
+    return fail(TPFA_ERR_UNSUPPORTED, "the FP32 precision form needs state.pref");
+  if (launch) {
+    if (launch->tile < -1 || launch->tile >= tpfa::kNumTiles)
+      return fail(TPFA_ERR_TILE, "unknown tile id");
+    if (launch->kz_chunk < 0) return fail(TPFA_ERR_TILE, "kz_chunk must be >= 0");
+  }
+  return TPFA_OK;
+}
+
+int default_tile(const tpfa_grid_t &g) {
+  if (g.nx <= 16) return 2;
+  if (g.nx <= 32) return 1;
+  return tpfa::kDefaultTile;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(TPFA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+namespace tpfa {
+
+void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
+               const tpfa_state_t &st, int tile, int kz_chunk, int flags) {
+  std::memset(&a, 0, sizeof(a));
+  const TileShape ts = kTiles[tile];
+  a.nx = (int32_t)g.nx;
+  a.ny = (int32_t)g.ny;
+  a.nz = (int32_t)g.nz;
+  a.kz_chunk = (int32_t)std::min<int64_t>(kz_chunk, g.nz);
+  a.ntx = (int32_t)((g.nx + ts.tx - 1) / ts.tx);
+  a.nty = (int32_t)((g.ny + ts.ty - 1) / ts.ty);
+  a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
+  a.remap = (flags & TPFA_LAUNCH_NO_XCD_REMAP) ? 0 : 1;
+  a.tile = tile;
+  a.plane = g.nx * g.ny;
+  a.nblocks = (int64_t)a.ntx * a.nty * a.nzc;
+  // face area over centre distance, per direction
+  a.ax = g.dy * g.dz / g.dx;
+  a.ay = g.dx * g.dz / g.dy;
+  a.az = g.dx * g.dy / g.dz;
+  a.ry = rk.ry;
+  a.rz = rk.rz;
+  a.gk = g.gk;
+  a.dz = g.dz;
+  a.rho0 = f.rho0;
+  a.cf = f.cf;
+  a.p0 = f.p0;
+  a.mu = f.mu;
+  a.ax2f = (float)(2.0 * a.ax);
+  a.ay2f = (float)(2.0 * a.ay * rk.ry);
+  a.az2f = (float)(2.0 * a.az * rk.rz);
+  a.rho0f = (float)f.rho0;
+  a.cff = (float)f.cf;
+  a.inv_muf = (float)(1.0 / f.mu);
+  a.gdzf = (float)(g.gk * g.dz);
+  a.p = st.p;
+  a.pref = st.pref;
+  a.kx = rk.kx;
+  a.seal = rk.seal;
+}
+
+}  // namespace tpfa
+
+namespace {
+
+int resolve_launch(const tpfa_grid_t &g, const tpfa_launch_t *launch, int &tile, int &kz,
+                   int &flags) {
+  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g);
+  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : tpfa::kDefaultKzChunk;
+  flags = launch ? launch->flags : 0;
+  return TPFA_OK;
+}
+
+int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t *rk,
+        const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
+        tpfa::Args &a, void *stream) {
+  int tile, kz, flags;
+  resolve_launch(*g, launch, tile, kz, flags);
+  // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
+  tpfa::Args b;
+  tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
+  b.r = a.r;
+  b.J = a.J;
+  b.w = a.w;
+  b.gp = a.gp;
+  b.gm = a.gm;
+  if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
+    return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
+  const hipError_t e =
+      tpfa::launch_march(prec, mode, tile, b, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpfa_residual(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
+                  const tpfa_state_t *state, tpfa_precision_t prec, void *r,
+                  const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!r) return fail(TPFA_ERR_NULL, "r is NULL");
+    tpfa::Args a{};
+    a.r = r;
+    return run(tpfa::MODE_RESIDUAL, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_jacobian(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
+                  const tpfa_state_t *state, tpfa_precision_t prec, void *r, void *J,
+                  const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!J) return fail(TPFA_ERR_NULL, "J is NULL");
+    tpfa::Args a{};
+    a.r = r;
+    a.J = J;
+    return run(tpfa::MODE_JACOBIAN, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                      const tpfa_rock_t *rock, const tpfa_state_t *state,
+                      tpfa_precision_t prec, const void *w, void *grad_p, void *grad_logk,
+                      const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!w) return fail(TPFA_ERR_NULL, "w is NULL");
+    if (!grad_p && !grad_logk) return fail(TPFA_ERR_NULL, "grad_p and grad_logk are both NULL");
+    tpfa::Args a{};
+    a.w = w;
+    a.gp = grad_p;
+    a.gm = grad_logk;
+    return run(tpfa::MODE_VJP, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_hydrostatic(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, double p_top,
+                     double *pref, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if ((rc = check_fluid(fluid))) return rc;
+  if (!pref) return fail(TPFA_ERR_NULL, "pref is NULL");
+  if (!is_finite(p_top)) return fail(TPFA_ERR_PARAM, "p_top must be finite");
+  const hipError_t e =
+      tpfa::launch_hydrostatic(*grid, *fluid, p_top, pref, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hydrostatic launch");
+  return ok();
+}
+
+int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double *pref,
+                         float *dp, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!p || !pref || !dp) return fail(TPFA_ERR_NULL, "p, pref and dp are required");
+  const hipError_t e =
+      tpfa::launch_offset(*grid, p, pref, dp, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "offset launch");
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble
+// ---------------------------------------------------------------------------
+
+struct tpfa_batch {
+  tpfa_precision_t prec;
+  tpfa::Mode mode;
+  tpfa::Args *d_models = nullptr;
+  tpfa::WorkItem *d_items = nullptr;
+  unsigned int *d_counter = nullptr;
+  int64_t n_items = 0;
+  int n_wg = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(tpfa_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_models) (void)hipFree(b->d_models);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  delete b;
+}
+
+int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
+                      tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream) {
+  try {
+    if (!out) return fail(TPFA_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (!models) return fail(TPFA_ERR_NULL, "models is NULL");
+    if (n_models <= 0) return fail(TPFA_ERR_SHAPE, "n_models must be positive");
+    if (mode != TPFA_BATCH_RESIDUAL && mode != TPFA_BATCH_JACOBIAN)
+      return fail(TPFA_ERR_PARAM, "unknown batch mode");
+    std::vector<tpfa::Args> args(n_models);
+    struct Item {
+      tpfa::WorkItem w;
+      int64_t cells;
+    };
+    std::vector<Item> items;
+    for (int m = 0; m < n_models; ++m) {
+      const tpfa_model_t &md = models[m];
+      int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
+      if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
+      if (mode == TPFA_BATCH_JACOBIAN && !md.J)
+        return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": J is NULL");
+      if (mode == TPFA_BATCH_RESIDUAL && !md.r)
+        return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": r is NULL");
+      int tile, kz, flags;
+      resolve_launch(md.grid, &md.launch, tile, kz, flags);
+      if (tpfa::kTiles[tile].threads != 256)
+        return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
+                                       ": batched tiles must be 256-thread tiles");
+      tpfa::make_args(args[m], md.grid, md.fluid, md.rock, md.state, tile, kz, flags);
+      args[m].r = md.r;
+      args[m].J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
+      const tpfa::Args &a = args[m];
+      const tpfa::TileShape ts = tpfa::kTiles[tile];
+      for (int bz = 0; bz < a.nzc; ++bz)
+        for (int by = 0; by < a.nty; ++by)
+          for (int bx = 0; bx < a.ntx; ++bx) {
+            const int64_t cx = std::min<int64_t>(ts.tx, a.nx - (int64_t)bx * ts.tx);
+            const int64_t cy = std::min<int64_t>(ts.ty, a.ny - (int64_t)by * ts.ty);
+            const int64_t cz = std::min<int64_t>(a.kz_chunk, a.nz - (int64_t)bz * a.kz_chunk);
+            items.push_back({{m, bx, by, bz * a.kz_chunk}, cx * cy * cz});
+          }
+    }
+    if (items.size() > (size_t)std::numeric_limits<uint32_t>::max() / 2)
+      return fail(TPFA_ERR_SHAPE, "too many work items");
+    // largest items first, so the shortest ones fill the tail
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &x, const Item &y) { return x.cells > y.cells; });
+    std::vector<tpfa::WorkItem> wl(items.size());
+    for (size_t q = 0; q < items.size(); ++q) wl[q] = items[q].w;
+
+    tpfa_batch *b = new tpfa_batch;
+    b->prec = prec;
+    b->mode = mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN : tpfa::MODE_RESIDUAL;
+    b->n_items = (int64_t)wl.size();
+    const int wg = tpfa::persistent_workgroups(prec, b->mode);
+    if (wg <= 0) {
+      batch_free(b);
+      return fail(TPFA_ERR_HIP, "could not query the device occupancy");
+    }
+    b->n_wg = (int)std::min<int64_t>(wg, b->n_items);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = hipMalloc(&b->d_models, sizeof(tpfa::Args) * args.size())) != hipSuccess ||
+        (e = hipMalloc(&b->d_items, sizeof(tpfa::WorkItem) * wl.size())) != hipSuccess ||
+        (e = hipMalloc(&b->d_counter, 2 * sizeof(unsigned int))) != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "batch allocation");
+    }
+    if ((e = hipMemcpyAsync(b->d_models, args.data(), sizeof(tpfa::Args) * args.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->d_items, wl.data(), sizeof(tpfa::WorkItem) * wl.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemsetAsync(b->d_counter, 0, 2 * sizeof(unsigned int), st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "batch upload");
+    }
+    // capture the persistent launch into a graph on a private stream
+    hipStream_t cs = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "capture stream");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t le = tpfa::launch_persistent(prec, b->mode, b->d_models, b->d_items,
+                                                    b->n_items, b->d_counter, b->n_wg, cs);
+      e = hipStreamEndCapture(cs, &b->graph);
+      if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "graph capture");
+    }
+    *out = b;
+    return ok();
+  } catch (const std::bad_alloc &) {
+    return fail(TPFA_ERR_HIP, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_batch_run(tpfa_batch_t *batch, void *stream) {
+  if (!batch || !batch->exec) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
+  const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return ok();
+}
+
+int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream) {
+  if (!batch || !batch->d_items) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
+  const hipError_t e =
+      tpfa::launch_persistent(batch->prec, batch->mode, batch->d_models, batch->d_items,
+                              batch->n_items, batch->d_counter, batch->n_wg,
+                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "persistent launch");
+  return ok();
+}
+
+int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgroups) {
+  if (!batch) return fail(TPFA_ERR_NULL, "batch is NULL");
+  if (n_items) *n_items = batch->n_items;
+  if (n_workgroups) *n_workgroups = batch->n_wg;
+  return ok();
+}
+
+void tpfa_batch_destroy(tpfa_batch_t *batch) {
+  if (!batch) return;
+  (void)hipDeviceSynchronize();
+  batch_free(batch);
+}
+
+int tpfa_num_tiles(void) { return tpfa::kNumTiles; }
+
+int tpfa_tile_shape(int id, int *tx, int *ty, int *threads) {
+  if (id < 0 || id >= tpfa::kNumTiles) return fail(TPFA_ERR_TILE, "unknown tile id");
+  if (tx) *tx = tpfa::kTiles[id].tx;
+  if (ty) *ty = tpfa::kTiles[id].ty;
+  if (threads) *threads = tpfa::kTiles[id].threads;
+  return ok();
+}
+
+const char *tpfa_strerror(int code) {
+  switch (code) {
+    case TPFA_OK: return "success";
+    case TPFA_ERR_NULL: return "a required pointer is NULL";
+    case TPFA_ERR_SHAPE: return "invalid grid shape";
+    case TPFA_ERR_PARAM: return "invalid parameter";
+    case TPFA_ERR_UNSUPPORTED: return "unsupported combination of arguments";
+    case TPFA_ERR_HIP: return "HIP runtime error";
+    case TPFA_ERR_TILE: return "unknown tile or z-chunk";
+    default: return "unknown error code";
+  }
+}
+
+const char *tpfa_last_error(void) { return g_last_error.c_str(); }
+
+int tpfa_version(void) { return 10000; }
+
+}  // extern "C"

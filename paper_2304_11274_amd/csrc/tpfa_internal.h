@@ -1,0 +1,76 @@
+// Internal interface between the C-ABI layer (tpfa_api.cpp) and the HIP
+// kernels (tpfa_kernels.hip, tpfa_batch.hip). Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpfa.h"
+
+namespace tpfa {
+
+enum Mode : int { MODE_RESIDUAL = 0, MODE_JACOBIAN = 1, MODE_VJP = 2 };
+
+// Tile table. A workgroup owns a TX x TY column block of one model and marches
+// it through a chunk of z planes. All shapes keep the halo ring (2 TX + 2 TY
+// cells) within one cell per thread.
+struct TileShape {
+  int tx, ty, threads;
+};
+constexpr int kNumTiles = 6;
+constexpr TileShape kTiles[kNumTiles] = {
+    {64, 4, 256}, {32, 8, 256}, {16, 16, 256}, {64, 8, 512}, {128, 4, 512}, {32, 16, 512}};
+constexpr int kDefaultTile = 0;
+constexpr int kDefaultKzChunk = 32;
+
+// Everything a kernel needs about one grid; passed by value (kernel argument)
+// for single launches and stored in a device table for the batched kernel.
+struct Args {
+  int32_t nx, ny, nz;
+  int32_t kz_chunk;   // z planes per workgroup
+  int32_t ntx, nty, nzc;  // tiles along x, y and z chunks
+  int32_t remap;      // 1: XCD-aware workgroup order
+  int32_t tile;       // index into kTiles
+  int32_t pad_;
+  int64_t plane;      // nx * ny
+  int64_t nblocks;    // ntx * nty * nzc
+  // transmissibility geometric factors a_d and directional ratios (y, z)
+  double ax, ay, az, ry, rz;
+  double gk, dz;      // gravity along +k, cell size along k
+  double rho0, cf, p0, mu;
+  float ax2f, ay2f, az2f;  // FP32 form: 2 a_d r_d
+  float rho0f, cff, inv_muf, gdzf;
+  const void *p;
+  const double *pref;
+  const void *kx;
+  const uint8_t *seal;
+  const void *w;
+  void *r;
+  void *J;
+  void *gp;
+  void *gm;
+};
+
+// Fills the derived fields of `a` from the ABI structs (host only).
+void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
+               const tpfa_state_t &st, int tile, int kz_chunk, int flags);
+
+// Launchers (host). Return hipSuccess or the launch error.
+hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &a,
+                        hipStream_t stream);
+hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, double p_top,
+                              double *pref, hipStream_t stream);
+hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
+                         hipStream_t stream);
+
+// Batched persistent kernel (tpfa_batch.hip).
+struct WorkItem {
+  int32_t model;
+  int32_t bx, by, kb;
+};
+hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, const Args *d_models,
+                             const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
+                             int n_workgroups, hipStream_t stream);
+int persistent_workgroups(tpfa_precision_t prec, Mode mode);
+
+}  // namespace tpfa

@@ -126,3 +126,139 @@ def cells_touching(faces: np.ndarray) -> np.ndarray:
     touch = touch | shift(faces[1].astype(np.float64), 2).astype(bool)
     touch = touch | shift(faces[2].astype(np.float64), 4).astype(bool)
     return touch
+
+
+# ---------------------------------------------------------------------------
+# GPU-vs-oracle comparison with upwind ties. Where a face's potential
+# difference is within tau of 0, either upwind choice is a correct result;
+# a cell that disagrees must touch such a face and must then agree with the
+# oracle evaluated with the upwind choice of those faces flipped.
+# ---------------------------------------------------------------------------
+
+def _flip_force(dphi_faces, ties):
+    force = np.zeros(dphi_faces.shape, np.int8)
+    force[ties] = np.where(dphi_faces[ties] >= 0, -1, 1)  # the rule's opposite
+    return force
+
+
+def compare_full(orc, grid, fluid, kx, p, r_gpu, J_gpu, *, tol, tau, ry, rz, seal):
+    """Full-grid comparison of r (and J if given). Returns a report dict."""
+    want = ("r", "J", "scale", "dphi")
+    ref = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, want=want)
+    r_gpu = None if r_gpu is None else np.asarray(r_gpu, np.float64).reshape(ref["r"].shape)
+    J_gpu = None if J_gpu is None else np.asarray(J_gpu, np.float64).reshape(ref["J"].shape)
+    err = _errs(r_gpu, J_gpu, ref)
+    ties = tie_faces(ref["dphi"], tau)
+    rep = {"max_err": float(err.max()), "n_tie_faces": int(ties.sum()), "n_flipped_cells": 0}
+    bad = err > tol
+    if bad.any():
+        touch = cells_touching(ties)
+        assert not (bad & ~touch).any(), (
+            f"{int((bad & ~touch).sum())} cells differ by up to {err[bad & ~touch].max():.3e} "
+            "away from any upwind tie")
+        alt = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal,
+                           force=_flip_force(ref["dphi"], ties), want=("r", "J", "scale"))
+        err2 = _errs(r_gpu, J_gpu, alt)
+        still = bad & (err2 > tol)
+        assert not still.any(), f"{int(still.sum())} tie cells match neither upwind choice"
+        rep["n_flipped_cells"] = int(bad.sum())
+        rep["max_err"] = float(np.where(bad, err2, err).max())
+    return rep
+
+
+def _errs(r_gpu, J_gpu, ref):
+    e = np.zeros(ref["r"].shape)
+    if r_gpu is not None:
+        e = np.maximum(e, rel_err(r_gpu, ref["r"], ref["scale"][0]))
+    if J_gpu is not None:
+        e = np.maximum(e, rel_err(J_gpu[0], ref["J"][0], ref["scale"][1]))
+        for n in range(6):
+            e = np.maximum(e, rel_err(J_gpu[1 + n], ref["J"][1 + n], np.abs(ref["J"][1 + n])))
+    return e
+
+
+def _row_errs(r_gpu, J_gpu, r, J, s):
+    e = rel_err(r_gpu, r, s[0]) if r_gpu is not None else np.zeros(r.shape)
+    if J_gpu is not None:
+        e = np.maximum(e, rel_err(J_gpu[0], J[0], s[1]))
+        for n in range(6):
+            e = np.maximum(e, rel_err(J_gpu[1 + n], J[1 + n], np.abs(J[1 + n])))
+    return e
+
+
+def compare_rows(orc, grid, fluid, kx, p, cells, r_rows, J_rows, *, tol, tau, ry, rz, seal):
+    """Comparison of sampled cells (r_rows[n], J_rows[7, n] from the GPU)."""
+    r, J, s, d = orc.rows(grid, fluid, kx, p, cells, ry=ry, rz=rz, seal=seal, with_dphi=True)
+    err = _row_errs(r_rows, J_rows, r, J, s)
+    with np.errstate(invalid="ignore"):
+        tie = np.abs(d) <= tau  # [6, n]
+    rep = {"max_err": float(err.max()), "n_tie_faces": int(tie.sum()), "n_flipped_cells": 0}
+    bad = err > tol
+    if bad.any():
+        assert tie[:, bad].any(axis=0).all(), (
+            f"{int((bad & ~tie.any(axis=0)).sum())} sampled cells differ by up to "
+            f"{err[bad & ~tie.any(axis=0)].max():.3e} away from any upwind tie")
+        shape = (grid.nz, grid.ny, grid.nx)
+        N = int(np.prod(shape))
+        force = np.zeros((3, N), np.int8)
+        strides = (1, grid.nx, grid.nx * grid.ny)
+        for q in np.nonzero(bad)[0]:
+            for n in np.nonzero(tie[:, q])[0]:
+                axis, plus = n // 2, n % 2
+                lower = cells[q] if plus else cells[q] - strides[axis]
+                dlow = d[n, q] if plus else -d[n, q]  # potential seen from the lower cell
+                force[axis, lower] = -1 if dlow >= 0 else 1
+        r2, J2, s2 = orc.rows(grid, fluid, kx, p, cells[bad], ry=ry, rz=rz, seal=seal,
+                              force=force.reshape((3,) + shape))
+        e2 = _row_errs(None if r_rows is None else r_rows[bad],
+                       None if J_rows is None else J_rows[:, bad], r2, J2, s2)
+        assert np.all(e2 <= tol), f"{int((e2 > tol).sum())} tie cells match neither choice"
+        rep["n_flipped_cells"] = int(bad.sum())
+        rep["max_err"] = float(np.where(bad, 0, err).max())
+    return rep
+
+
+def vjp_scales(J_ref, scale, w):
+    """Natural magnitudes of J^T w and of the log-permeability gradient at each
+    cell: sums of the absolute values of their terms."""
+    aw = np.abs(w)
+    sp_ = apply_JT(np.abs(J_ref), aw)
+    wmax = aw.copy()
+    for n in range(6):
+        wmax = np.maximum(wmax, shift(aw, n))
+    sm = 2.0 * wmax * scale[0]
+    return sp_, sm
+
+
+def compare_vjp(orc, grid, fluid, kx, p, w, gp_gpu, gm_gpu, *, tol, tau, ry, rz, seal):
+    want = ("J", "grad_p", "grad_logk", "scale", "dphi")
+    ref = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, w=w, want=want)
+    sp_, sm = vjp_scales(ref["J"], ref["scale"], w)
+    shape = ref["grad_p"].shape
+
+    def errs(o):
+        e = np.zeros(shape)
+        if gp_gpu is not None:
+            e = np.maximum(e, rel_err(np.asarray(gp_gpu, np.float64).reshape(shape),
+                                      o["grad_p"], sp_))
+        if gm_gpu is not None:
+            e = np.maximum(e, rel_err(np.asarray(gm_gpu, np.float64).reshape(shape),
+                                      o["grad_logk"], sm))
+        return e
+
+    err = errs(ref)
+    ties = tie_faces(ref["dphi"], tau)
+    rep = {"max_err": float(err.max()), "n_tie_faces": int(ties.sum()), "n_flipped_cells": 0}
+    bad = err > tol
+    if bad.any():
+        touch = cells_touching(ties)
+        assert not (bad & ~touch).any(), (
+            f"{int((bad & ~touch).sum())} cells differ by up to "
+            f"{err[bad & ~touch].max():.3e} away from any upwind tie")
+        alt = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, w=w,
+                           force=_flip_force(ref["dphi"], ties), want=("grad_p", "grad_logk"))
+        err2 = errs(alt)
+        assert not (bad & (err2 > tol)).any()
+        rep["n_flipped_cells"] = int(bad.sum())
+        rep["max_err"] = float(np.where(bad, err2, err).max())
+    return rep

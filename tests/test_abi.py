@@ -1,0 +1,188 @@
+"""C-ABI checks that need no GPU: libtpfa.so loads, exports every function
+declared in include/tpfa.h, and rejects invalid arguments on the host with the
+documented error codes before anything is enqueued."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import paper_2304_11274_amd as tp
+from paper_2304_11274_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tpfa.h")
+DUMMY = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpfa_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_introspection(lib):
+    assert lib.tpfa_version() >= 10000
+    shapes = tp.tile_shapes()
+    assert len(shapes) == lib.tpfa_num_tiles()
+    for tx, ty, th in shapes:
+        assert tx * ty == th and 2 * (tx + ty) <= th
+    assert lib.tpfa_tile_shape(-1, None, None, None) == L.TPFA_ERR_TILE
+    assert lib.tpfa_tile_shape(lib.tpfa_num_tiles(), None, None, None) == L.TPFA_ERR_TILE
+    for code in range(0, -7, -1):
+        assert lib.tpfa_strerror(code)
+    assert b"unknown" in lib.tpfa_strerror(-99)
+
+
+def good():
+    g = L.Grid(8, 8, 8, 10.0, 10.0, 2.0, 9.81)
+    f = L.Fluid(1000.0, 1e-9, 1e7, 1e-3)
+    rk = L.Rock(DUMMY, None, None, 1.0, 0.1, None)
+    st = L.State(DUMMY, None)
+    return g, f, rk, st
+
+
+def call_res(lib, g, f, rk, st, prec=L.TPFA_FP64, r=DUMMY, launch=None):
+    return lib.tpfa_residual(None if g is None else C.byref(g), None if f is None else C.byref(f),
+                             None if rk is None else C.byref(rk),
+                             None if st is None else C.byref(st), prec, r,
+                             None if launch is None else C.byref(launch), None)
+
+
+def case(name, code, **mut):
+    return pytest.param(mut, code, id=name)
+
+
+@pytest.mark.parametrize("mut,code", [
+    case("grid-null", L.TPFA_ERR_NULL, grid=None),
+    case("fluid-null", L.TPFA_ERR_NULL, fluid=None),
+    case("rock-null", L.TPFA_ERR_NULL, rock=None),
+    case("state-null", L.TPFA_ERR_NULL, state=None),
+    case("nx-zero", L.TPFA_ERR_SHAPE, nx=0),
+    case("nz-negative", L.TPFA_ERR_SHAPE, nz=-3),
+    case("nx-over-int32", L.TPFA_ERR_SHAPE, nx=2**31),
+    case("ncell-overflow", L.TPFA_ERR_SHAPE, nx=2**31 - 1, ny=2**31 - 1, nz=2**31 - 1),
+    case("dx-zero", L.TPFA_ERR_PARAM, dx=0.0),
+    case("dz-nan", L.TPFA_ERR_PARAM, dz=math.nan),
+    case("gk-inf", L.TPFA_ERR_PARAM, gk=math.inf),
+    case("mu-zero", L.TPFA_ERR_PARAM, mu=0.0),
+    case("mu-negative", L.TPFA_ERR_PARAM, mu=-1e-3),
+    case("cf-nan", L.TPFA_ERR_PARAM, cf=math.nan),
+    case("ry-negative", L.TPFA_ERR_PARAM, ry=-1.0),
+    case("rz-nan", L.TPFA_ERR_PARAM, rz=math.nan),
+    case("kx-null", L.TPFA_ERR_NULL, kx=None),
+    case("ky-array", L.TPFA_ERR_UNSUPPORTED, ky=DUMMY),
+    case("kz-array", L.TPFA_ERR_UNSUPPORTED, kz=DUMMY),
+    case("p-null", L.TPFA_ERR_NULL, p=None),
+    case("fp32-no-pref", L.TPFA_ERR_UNSUPPORTED, prec=L.TPFA_FP32),
+    case("unknown-precision", L.TPFA_ERR_PARAM, prec=7),
+    case("r-null", L.TPFA_ERR_NULL, r=None),
+    case("tile-unknown", L.TPFA_ERR_TILE, launch=(99, 0, 0)),
+    case("tile-below", L.TPFA_ERR_TILE, launch=(-2, 0, 0)),
+    case("kz-negative", L.TPFA_ERR_TILE, launch=(0, -1, 0)),
+])
+def test_residual_validation(lib, mut, code):
+    g, f, rk, st = good()
+    prec, r, launch = L.TPFA_FP64, DUMMY, None
+    for k, v in mut.items():
+        if k == "grid":
+            g = v
+        elif k == "fluid":
+            f = v
+        elif k == "rock":
+            rk = v
+        elif k == "state":
+            st = v
+        elif k in ("nx", "ny", "nz", "dx", "dy", "dz", "gk"):
+            setattr(g, k, v)
+        elif k in ("mu", "cf", "rho0", "p0"):
+            setattr(f, k, v)
+        elif k in ("kx", "ky", "kz", "ry", "rz"):
+            setattr(rk, k, v if not isinstance(v, C.c_void_p) else v.value)
+        elif k == "p":
+            st.p = v
+        elif k == "prec":
+            prec = v
+        elif k == "r":
+            r = v
+        elif k == "launch":
+            launch = L.Launch(*v)
+    rc = call_res(lib, g, f, rk, st, prec=prec, r=r, launch=launch)
+    assert rc == code, lib.tpfa_last_error()
+    assert lib.tpfa_last_error()  # a detail message is always set
+
+
+def test_jacobian_and_vjp_validation(lib):
+    g, f, rk, st = good()
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st), L.TPFA_FP64)
+    assert lib.tpfa_jacobian(*args, DUMMY, None, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual_vjp(*args, None, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual_vjp(*args, DUMMY, None, None, None, None) == L.TPFA_ERR_NULL
+    rk2 = L.Rock(DUMMY.value, DUMMY.value, None, 1.0, 1.0, None)
+    assert lib.tpfa_residual_vjp(C.byref(g), C.byref(f), C.byref(rk2), C.byref(st),
+                                 L.TPFA_FP64, DUMMY, DUMMY, DUMMY, None,
+                                 None) == L.TPFA_ERR_UNSUPPORTED
+    g.nz = 0
+    assert lib.tpfa_jacobian(*args, DUMMY, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+
+
+def test_helpers_validation(lib):
+    g, f, _, _ = good()
+    assert lib.tpfa_hydrostatic(C.byref(g), C.byref(f), 1e7, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_hydrostatic(C.byref(g), C.byref(f), math.inf, DUMMY, None) == L.TPFA_ERR_PARAM
+    assert lib.tpfa_hydrostatic(None, C.byref(f), 1e7, DUMMY, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_offset_pressure(C.byref(g), None, DUMMY, DUMMY, None) == L.TPFA_ERR_NULL
+    g.ny = 0
+    assert lib.tpfa_offset_pressure(C.byref(g), DUMMY, DUMMY, DUMMY, None) == L.TPFA_ERR_SHAPE
+
+
+def test_batch_validation(lib):
+    g, f, rk, st = good()
+    out = C.c_void_p()
+    m = (L.Model * 2)()
+    for q in range(2):
+        m[q] = L.Model(g, f, rk, st, DUMMY.value, DUMMY.value, L.Launch(-1, 0, 0))
+    J = L.TPFA_BATCH_JACOBIAN
+    assert lib.tpfa_batch_create(m, 2, L.TPFA_FP64, J, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_batch_create(None, 2, L.TPFA_FP64, J, C.byref(out), None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_batch_create(m, 0, L.TPFA_FP64, J, C.byref(out), None) == L.TPFA_ERR_SHAPE
+    assert lib.tpfa_batch_create(m, 2, L.TPFA_FP64, 5, C.byref(out), None) == L.TPFA_ERR_PARAM
+    m[1].launch = L.Launch(3, 0, 0)  # a 512-thread tile
+    assert lib.tpfa_batch_create(m, 2, L.TPFA_FP64, J, C.byref(out), None) == L.TPFA_ERR_TILE
+    m[1].launch = L.Launch(-1, 0, 0)
+    m[1].J = None
+    assert lib.tpfa_batch_create(m, 2, L.TPFA_FP64, J, C.byref(out), None) == L.TPFA_ERR_NULL
+    assert b"model 1" in lib.tpfa_last_error()
+    m[1].grid.nx = 0
+    m[1].J = DUMMY.value
+    assert lib.tpfa_batch_create(m, 2, L.TPFA_FP64, J, C.byref(out), None) == L.TPFA_ERR_SHAPE
+    assert not out.value
+    assert lib.tpfa_batch_run(None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_batch_run_eager(None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_batch_info(None, None, None) == L.TPFA_ERR_NULL
+    lib.tpfa_batch_destroy(None)
+
+
+def test_python_binding_rejects_host_tensors():
+    import torch
+    import geomodel
+    g = geomodel.Grid(4, 4, 4)
+    t = torch.zeros(64, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        tp.residual(g, geomodel.Fluid(), t, t)
+    with pytest.raises(TypeError):
+        tp.residual(g, geomodel.Fluid(), t, t.to(torch.int32))
