@@ -137,8 +137,7 @@ def main():
                                  "4 rotating pressure fields",
                      "cells": N, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
                      "sigma_lnk": 1.5, "ry": 1.0, "rz": 0.1, "seal_fraction": 0.01,
-                     "launch": "library default (tile 64x4, 32 z-planes per workgroup, "
-                               "XCD-aware order)"}
+                     "launch": "library default (tile 64x4, 32 z-planes per workgroup)"}
 
     def rate(ms, k, bytes_per_cell):
         t = ms / 1e3 / k
@@ -235,6 +234,15 @@ def main():
                                 ry=geo_m.ry, rz=geo_m.rz))
         cells = sum(m.ncell for m in models)
         del models
+        from paper_2304_11274_amd import autotune
+        t1 = time.time()
+        # per-model launches: each model with its own tuned tile and z-chunk
+        table = autotune.tune_members(members)
+        solo = [(m["tile"], m["kz_chunk"]) for m in members]
+        # one persistent launch: tiles by lane utilisation, one z-chunk timed on the batch
+        kz_best, kz_times = autotune.tune_ensemble(members)
+        log(f"autotuned {len(table)} size classes for per-model launches, ensemble z-chunk "
+            f"{kz_best} ({kz_times}) in {time.time() - t1:.1f} s")
         ens = tp.Ensemble(members)
         n_items, n_wg = ens.info()
         log(f"ensemble of {len(members)} models, {cells} cells, {n_items} work items, "
@@ -249,11 +257,15 @@ def main():
         outs = [(torch.empty_like(m["p"]), torch.empty((7,) + tuple(m["p"].shape),
                                                        dtype=torch.float32, device=dev))
                 for m in members]
+        ens_tiles = sorted({(m["tile"], m["kz_chunk"]) for m in members})
+        for m, (t_, z_) in zip(members, solo):
+            m["tile"], m["kz_chunk"] = t_, z_
 
         def per_model():
             for m, (rr, JJ) in zip(members, outs):
                 tp.jacobian(m["grid"], m["fluid"], m["kx"], m["p"], seal=m["seal"],
-                            pref=m["pref"], ry=m["ry"], rz=m["rz"], r_out=rr, J_out=JJ)
+                            pref=m["pref"], ry=m["ry"], rz=m["rz"], r_out=rr, J_out=JJ,
+                            tile=m["tile"], kz_chunk=m["kz_chunk"])
         for _ in range(W):
             per_model()
         with Timer(torch) as tm:
@@ -264,6 +276,7 @@ def main():
                           "workgroups": n_wg, "dtype": "f32",
                           "cells_per_s": cells / (t_graph / 1e3), "ms_per_step": t_graph,
                           "algorithmic_GBps": BYTES_FP32_RJ * cells / (t_graph / 1e3) / 1e9,
+                          "ensemble_tiles": ens_tiles, "ensemble_kz_timing_ms": kz_times,
                           "per_model_launch_cells_per_s": cells / (t_loop / 1e3),
                           "per_model_launch_ms": t_loop,
                           "speedup_vs_per_model": t_loop / t_graph}

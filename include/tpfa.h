@@ -90,14 +90,15 @@ typedef struct {
 
 /* Optional launch shape (pass NULL for the defaults): tile = id from
    tpfa_tile_shape(), or -1; kz_chunk = z planes marched by one workgroup
-   (0 = default); flags bit 0 disables the XCD-aware workgroup order. */
+   (0 = default); flags bit 0 selects the XCD-aware workgroup order (each of
+   the 8 XCDs takes one contiguous range of tiles). */
 typedef struct {
   int tile;
   int kz_chunk;
   int flags;
 } tpfa_launch_t;
 
-#define TPFA_LAUNCH_NO_XCD_REMAP 1
+#define TPFA_LAUNCH_XCD_REMAP 1
 
 /* Residual r[ncell] (paper Algorithm 1 with the Eq. (3)-(5) flux). */
 int tpfa_residual(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,

@@ -23,7 +23,7 @@ TPFA_FP64 = 0
 TPFA_FP32 = 1
 TPFA_BATCH_RESIDUAL = 0
 TPFA_BATCH_JACOBIAN = 1
-TPFA_LAUNCH_NO_XCD_REMAP = 1
+TPFA_LAUNCH_XCD_REMAP = 1
 
 
 class Grid(C.Structure):

@@ -30,10 +30,10 @@ def _fluid(f) -> L.Fluid:
 
 
 def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap: bool):
-    if tile is None and kz_chunk is None and xcd_remap:
+    if tile is None and kz_chunk is None and not xcd_remap:
         return None
     return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
-                    0 if xcd_remap else L.TPFA_LAUNCH_NO_XCD_REMAP)
+                    L.TPFA_LAUNCH_XCD_REMAP if xcd_remap else 0)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -85,7 +85,7 @@ def _rock(kx, seal, ry, rz) -> L.Rock:
 
 
 def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
-             tile=None, kz_chunk=None, xcd_remap=True) -> torch.Tensor:
+             tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -104,7 +104,7 @@ def _launch_ref(tile, kz_chunk, xcd_remap):
 
 
 def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r=True,
-             r_out=None, J_out=None, tile=None, kz_chunk=None, xcd_remap=True):
+             r_out=None, J_out=None, tile=None, kz_chunk=None, xcd_remap=False):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
@@ -124,7 +124,7 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r
 
 def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
                  want_p=True, want_logk=True, gp_out=None, gm_out=None, tile=None,
-                 kz_chunk=None, xcd_remap=True):
+                 kz_chunk=None, xcd_remap=False):
     """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
     _need(w, "w", dt, n, dev)

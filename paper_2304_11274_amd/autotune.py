@@ -1,0 +1,135 @@
+"""Launch-shape autotuner: picks the tile shape and the z-chunk length of the
+march kernels per grid size class by timing the candidates on the GPU.
+
+A size class groups grids whose (nx, ny, nz) round to the same buckets; one
+representative per class is timed and the winner applies to the whole class.
+Candidates whose lane utilisation (fraction of a tile's columns inside the
+grid) is far below the best are skipped before timing. Results are returned
+as {class: (tile, kz_chunk)} and can be cached in a JSON file.
+
+Every tile and z-chunk computes each cell with the same arithmetic, so the
+choice changes speed only, never results.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import api
+
+TILE_IDS_256 = (0, 1, 2)          # the tiles the persistent ensemble kernel accepts
+TILE_IDS_ALL = (0, 1, 2, 3, 4, 5)
+KZ_CANDIDATES = (8, 16, 32, 64)
+
+
+def size_class(nx: int, ny: int, nz: int) -> Tuple[int, int, int]:
+    """Buckets of 16 cells in x and y, 32 planes in z."""
+    return (int(math.ceil(nx / 16)), int(math.ceil(ny / 16)), int(math.ceil(nz / 32)))
+
+
+def lane_utilisation(nx: int, ny: int, tile: int) -> float:
+    tx, ty, _ = api.tile_shapes()[tile]
+    return (nx / (math.ceil(nx / tx) * tx)) * (ny / (math.ceil(ny / ty) * ty))
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune_member(m: dict, *, tiles: Sequence[int] = TILE_IDS_256,
+                kz: Sequence[int] = KZ_CANDIDATES, mode: str = "jacobian", reps: int = 5,
+                keep: float = 0.8) -> Tuple[int, int, float]:
+    """Time every (tile, kz) candidate on one grid; returns (tile, kz, ms)."""
+    g = m["grid"]
+    util = {t: lane_utilisation(g.nx, g.ny, t) for t in tiles}
+    best_u = max(util.values())
+    cands = [(t, z) for t in tiles if util[t] >= keep * best_u for z in kz if z <= 2 * g.nz]
+    p = m["p"]
+    r = torch.empty_like(p)
+    J = torch.empty((7,) + tuple(p.shape), dtype=p.dtype, device=p.device)
+    best = None
+    for t, z in cands:
+        kw = dict(seal=m.get("seal"), pref=m.get("pref"), ry=m.get("ry", 1.0),
+                  rz=m.get("rz", 1.0), tile=t, kz_chunk=z)
+        if mode == "jacobian":
+            fn = lambda: api.jacobian(g, m["fluid"], m["kx"], p, r_out=r, J_out=J, **kw)  # noqa: E731
+        else:
+            fn = lambda: api.residual(g, m["fluid"], m["kx"], p, out=r, **kw)  # noqa: E731
+        ms = _time(fn, reps)
+        if best is None or ms < best[2]:
+            best = (t, z, ms)
+    return best
+
+
+def tune_members(members: Sequence[dict], *, cache: Optional[str] = None, **kw
+                 ) -> Dict[Tuple[int, int, int], Tuple[int, int]]:
+    """Tune one representative per size class and assign ``tile`` and
+    ``kz_chunk`` to every member in place. Returns the class table."""
+    table: Dict[Tuple[int, int, int], Tuple[int, int]] = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            for k, v in json.load(f).items():
+                table[tuple(int(x) for x in k.split(","))] = (int(v[0]), int(v[1]))
+    reps: Dict[Tuple[int, int, int], dict] = {}
+    for m in members:
+        g = m["grid"]
+        c = size_class(g.nx, g.ny, g.nz)
+        if c not in table and c not in reps:
+            reps[c] = m
+    for c, m in reps.items():
+        t, z, _ = tune_member(m, **kw)
+        table[c] = (t, z)
+    for m in members:
+        g = m["grid"]
+        m["tile"], m["kz_chunk"] = table[size_class(g.nx, g.ny, g.nz)]
+    if cache:
+        with open(cache, "w") as f:
+            json.dump({",".join(map(str, k)): list(v) for k, v in sorted(table.items())}, f,
+                      indent=1)
+    return table
+
+
+def ensemble_tile(nx: int, ny: int) -> int:
+    """The 256-thread tile with the best lane utilisation; ties go to the wider
+    tile (longer contiguous rows per wave)."""
+    best = None
+    for t in TILE_IDS_256:
+        u = lane_utilisation(nx, ny, t)
+        if best is None or u > best[1] + 1e-12:
+            best = (t, u)
+    return best[0]
+
+
+def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64, 128),
+                  reps: int = 5, mode: str = "jacobian") -> Tuple[int, Dict[int, float]]:
+    """Tiles per member by lane utilisation, then one z-chunk for the whole
+    ensemble chosen by timing the persistent launch (the work list then has
+    items of similar length and the prologue cost per item is amortised).
+    Sets ``tile`` and ``kz_chunk`` on every member; returns (kz, {kz: ms})."""
+    for m in members:
+        m["tile"] = ensemble_tile(m["grid"].nx, m["grid"].ny)
+    times = {}
+    for z in kz:
+        for m in members:
+            m["kz_chunk"] = z
+        ens = api.Ensemble(members, mode=mode)
+        times[z] = _time(ens.run, reps)
+        ens.close()
+        del ens
+    best = min(times, key=times.get)
+    for m in members:
+        m["kz_chunk"] = best
+    return best, times

@@ -108,7 +108,7 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.ntx = (int32_t)((g.nx + ts.tx - 1) / ts.tx);
   a.nty = (int32_t)((g.ny + ts.ty - 1) / ts.ty);
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
-  a.remap = (flags & TPFA_LAUNCH_NO_XCD_REMAP) ? 0 : 1;
+  a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : 0;
   a.tile = tile;
   a.plane = g.nx * g.ny;
   a.nblocks = (int64_t)a.ntx * a.nty * a.nzc;
@@ -124,13 +124,19 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.cf = f.cf;
   a.p0 = f.p0;
   a.mu = f.mu;
-  a.ax2f = (float)(2.0 * a.ax);
-  a.ay2f = (float)(2.0 * a.ay * rk.ry);
-  a.az2f = (float)(2.0 * a.az * rk.rz);
+  a.a2x = 2.0 * a.ax;
+  a.a2y = 2.0 * a.ay * rk.ry;
+  a.a2z = 2.0 * a.az * rk.rz;
+  a.inv_mu = 1.0 / f.mu;
+  a.G = g.gk * g.dz;
+  a.hc = 0.5 * f.cf * a.G;
+  a.a2xf = (float)a.a2x;
+  a.a2yf = (float)a.a2y;
+  a.a2zf = (float)a.a2z;
   a.rho0f = (float)f.rho0;
   a.cff = (float)f.cf;
-  a.inv_muf = (float)(1.0 / f.mu);
-  a.gdzf = (float)(g.gk * g.dz);
+  a.inv_muf = (float)a.inv_mu;
+  a.hcf = (float)a.hc;
   a.p = st.p;
   a.pref = st.pref;
   a.kx = rk.kx;

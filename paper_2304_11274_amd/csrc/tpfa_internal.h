@@ -38,8 +38,14 @@ struct Args {
   double ax, ay, az, ry, rz;
   double gk, dz;      // gravity along +k, cell size along k
   double rho0, cf, p0, mu;
-  float ax2f, ay2f, az2f;  // FP32 form: 2 a_d r_d
-  float rho0f, cff, inv_muf, gdzf;
+  // derived constants of the FP64 path
+  double a2x, a2y, a2z;  // 2 a_d r_d
+  double inv_mu;         // 1 / mu
+  double G;              // gk * dz: gravity potential drop across a z face per unit density
+  double hc;             // 0.5 * cf * G
+  // FP32 precision form
+  float a2xf, a2yf, a2zf;
+  float rho0f, cff, inv_muf, hcf, pad2_;
   const void *p;
   const double *pref;
   const void *kx;

@@ -47,101 +47,74 @@ namespace tpfa {
 // Per-precision cell quantities
 // ----------------------------------------------------------------------------
 
+// One cell as loaded from HBM.
 template <class S>
 struct Cell {
-  S p;         // stored pressure value (absolute for FP64, offset for FP32)
+  S p;         // stored pressure value (absolute for FP64, offset from pref for FP32)
   S k;         // kx
   S w;         // cotangent (vector-Jacobian product only)
   uint32_t s;  // seal bits
 };
 
+// Density-derived quantities of a cell, evaluated once per cell.
 template <class S>
-struct Props;
-
-template <>
-struct Props<double> {
-  using C = double;
-  double pa;   // absolute pressure
-  double rho;  // density, Eq. (5)
-  double lam;  // mobility rho / mu
-  static __device__ __forceinline__ double absp(double v, double) { return v; }
-  __device__ __forceinline__ void set(double v, double, const Args &a) {
-    pa = v;
-    rho = a.rho0 * exp(a.cf * (pa - a.p0));
-    lam = rho / a.mu;
-  }
+struct Props {
+  S rho;  // density, Eq. (5)
+  S lam;  // mobility rho / mu
 };
 
-template <>
-struct Props<float> {
-  using C = float;
-  double pa;
-  float rho;
-  float lam;
-  static __device__ __forceinline__ double absp(float v, double pref_k) {
-    return pref_k + (double)v;
-  }
-  __device__ __forceinline__ void set(float v, double pref_k, const Args &a) {
-    pa = pref_k + (double)v;
-    rho = a.rho0f * __expf((float)(pa - a.p0) * a.cff);
-    lam = rho * a.inv_muf;
-  }
-};
-
-// One face between a lower-index cell (Lo) and an upper-index cell (Up).
-template <class C>
-struct Face {
-  C F;    // F_{Lo,Up}: outflow of Lo
-  C dLo;  // dF / dp_Lo
-  C dUp;  // dF / dp_Up
-  C qLo;  // k_Lo / (k_Lo + k_Up)   (vector-Jacobian product only)
-  C qUp;  // k_Up / (k_Lo + k_Up)
-};
-
-// FP64 face. `A` is the geometric factor a_d, kLo/kUp the directional
-// permeabilities, G = gk * dz on z faces and 0 (GRAV = false) otherwise.
-template <bool GRAV, bool DERIV, bool VJP>
-__device__ __forceinline__ Face<double> face64(const Args &a, double A, double kLo, double kUp,
-                                                bool open, double pLo, double pUp,
-                                                double rhoLo, double rhoUp, double lamLo,
-                                                double lamUp) {
-  Face<double> f;
-  const double ks = kLo + kUp;
-  double T;
-  if (VJP) {
-    const double inv = 1.0 / ks;
-    f.qLo = kLo * inv;
-    f.qUp = kUp * inv;
-    T = A * ((2.0 * (kLo * kUp)) * inv);
-  } else {
-    T = A * ((2.0 * (kLo * kUp)) / ks);
-  }
-  T = (open && ks != 0.0) ? T : 0.0;
-  double dphi = pLo - pUp;
-  if (GRAV) dphi = dphi + ((0.5 * (rhoLo + rhoUp)) * a.gk) * a.dz;
-  const bool up = dphi >= 0.0;  // a tie goes to the lower index
-  const double lam = up ? lamLo : lamUp;
-  f.F = (T * lam) * dphi;
-  if (DERIV) {
-    const double t = (a.cf * lam) * dphi;  // d(lambda_up)/dp_up * dPhi
-    double gLo = 1.0, gUp = -1.0;          // dPhi/dp_Lo, dPhi/dp_Up
-    if (GRAV) {
-      gLo = 1.0 + ((0.5 * (a.cf * rhoLo)) * a.gk) * a.dz;
-      gUp = -1.0 + ((0.5 * (a.cf * rhoUp)) * a.gk) * a.dz;
-    }
-    f.dLo = T * ((up ? t : 0.0) + lam * gLo);
-    f.dUp = T * ((up ? 0.0 : t) + lam * gUp);
-  }
-  return f;
+// Eq. (5). FP64: rho0 exp(cf (p - p0)). FP32 form: the exponent is formed from
+// the plane's reference offset x_k = pref[k] - p0 (in float) plus dp; its
+// rounding (< 1 Pa) shifts the exponent by < 1e-9.
+__device__ __forceinline__ Props<double> props(double p, double, const Args &a) {
+  Props<double> q;
+  q.rho = a.rho0 * exp(a.cf * (p - a.p0));
+  q.lam = q.rho * a.inv_mu;
+  return q;
+}
+__device__ __forceinline__ Props<float> props(float dp, float xk, const Args &a) {
+  Props<float> q;
+  q.rho = a.rho0f * __expf(a.cff * (xk + dp));
+  q.lam = q.rho * a.inv_muf;
+  return q;
 }
 
-// FP32 face of the precision form: potential difference in FP64.
-// A2 = 2 a_d r_d, kLo/kUp are kx (the ratio r_d cancels in k/(k+k)).
-template <bool GRAV, bool DERIV, bool VJP>
-__device__ __forceinline__ Face<float> face32(const Args &a, float A2, float kLo, float kUp,
-                                               bool open, double pLo, double pUp, float rhoLo,
-                                               float rhoUp, float lamLo, float lamUp) {
-  Face<float> f;
+// 1/x to about one ulp: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// One face between a lower-index cell (Lo) and an upper-index cell (Up):
+// F = F_{Lo,Up} (outflow of Lo), its pressure derivatives, and for the
+// vector-Jacobian product the permeability weights k_Lo/(k_Lo+k_Up),
+// k_Up/(k_Lo+k_Up) that give d Ups / d ln k.
+template <class C>
+struct Face {
+  C F, dLo, dUp, qLo, qUp;
+  C w;  // z faces: cotangent of the lower cell (vector-Jacobian product only)
+};
+
+// Transmissibility 2 a r k_Lo k_Up / (k_Lo + k_Up) (A2 = 2 a r), closed when
+// the face is sealed or k_Lo + k_Up = 0.
+template <bool VJP>
+__device__ __forceinline__ double trans64(double A2, double kLo, double kUp, bool open,
+                                          Face<double> &f) {
+  const double ks = kLo + kUp;
+  const double inv = rcp64(ks);
+  if (VJP) {
+    f.qLo = kLo * inv;
+    f.qUp = kUp * inv;
+  }
+  const double T = (A2 * kLo) * (kUp * inv);
+  return (open && ks > 0.0) ? T : 0.0;
+}
+template <bool VJP>
+__device__ __forceinline__ float trans32(float A2, float kLo, float kUp, bool open,
+                                         Face<float> &f) {
   const float ks = kLo + kUp;
   const float inv = __builtin_amdgcn_rcpf(ks);
   const float qUp = kUp * inv;
@@ -149,272 +122,338 @@ __device__ __forceinline__ Face<float> face32(const Args &a, float A2, float kLo
     f.qLo = kLo * inv;
     f.qUp = qUp;
   }
-  float T = (A2 * kLo) * qUp;
-  T = (open && ks > 0.0f) ? T : 0.0f;
-  double dphi = pLo - pUp;
-  if (GRAV) dphi = dphi + (double)(0.5f * (rhoLo + rhoUp)) * (a.gk * a.dz);
-  const bool up = dphi >= 0.0;
-  const float dphif = (float)dphi;
-  const float lam = up ? lamLo : lamUp;
-  f.F = (T * lam) * dphif;
+  const float T = (A2 * kLo) * qUp;
+  return (open && ks > 0.0f) ? T : 0.0f;
+}
+
+// Upwinded flux and derivatives from T, the potential difference and the
+// pressure derivatives gLo = dPhi/dp_Lo, gUp = dPhi/dp_Up (1 and -1 on x/y
+// faces). The upwind mobility is lambda_Lo when dPhi >= 0 (a tie goes to the
+// lower index), and its pressure derivative is cf * lambda.
+template <class C, bool DERIV, bool GRAV>
+__device__ __forceinline__ void upwind(Face<C> &f, C T, C dphi, bool up, C lamLo, C lamUp,
+                                       C cf, C gLo, C gUp) {
+  const C lam = up ? lamLo : lamUp;
+  const C TL = T * lam;
+  f.F = TL * dphi;
   if (DERIV) {
-    const float t = (a.cff * lam) * dphif;
-    float gLo = 1.0f, gUp = -1.0f;
+    const C t = (cf * lam) * dphi;
+    const C tLo = up ? t : C(0);
+    const C tUp = t - tLo;
     if (GRAV) {
-      gLo = 1.0f + (0.5f * a.cff * rhoLo) * a.gdzf;
-      gUp = -1.0f + (0.5f * a.cff * rhoUp) * a.gdzf;
+      f.dLo = fma(TL, gLo, T * tLo);
+      f.dUp = fma(TL, gUp, T * tUp);
+    } else {
+      f.dLo = fma(T, tLo, TL);
+      f.dUp = fma(T, tUp, -TL);
     }
-    f.dLo = T * ((up ? t : 0.0f) + lam * gLo);
-    f.dUp = T * ((up ? 0.0f : t) + lam * gUp);
   }
+}
+
+// x or y face (no elevation difference).
+template <bool DERIV, bool VJP>
+__device__ __forceinline__ Face<double> face_h(const Args &a, double A2, double kLo, double kUp,
+                                               bool open, double pLo, double pUp, double lamLo,
+                                               double lamUp) {
+  Face<double> f;
+  const double T = trans64<VJP>(A2, kLo, kUp, open, f);
+  const double dphi = pLo - pUp;
+  upwind<double, DERIV, false>(f, T, dphi, dphi >= 0.0, lamLo, lamUp, a.cf, 1.0, -1.0);
+  return f;
+}
+// FP32 form: both cells lie in the same plane, so dPhi = dp_Lo - dp_Up and
+// the sign of the rounded float difference is exact: the upwind choice is the
+// one FP64 makes.
+template <bool DERIV, bool VJP>
+__device__ __forceinline__ Face<float> face_h(const Args &a, float A2, float kLo, float kUp,
+                                              bool open, float pLo, float pUp, float lamLo,
+                                              float lamUp) {
+  Face<float> f;
+  const float T = trans32<VJP>(A2, kLo, kUp, open, f);
+  const float dphi = pLo - pUp;
+  upwind<float, DERIV, false>(f, T, dphi, dphi >= 0.0f, lamLo, lamUp, a.cff, 1.0f, -1.0f);
   return f;
 }
 
-template <class S, bool GRAV, bool DERIV, bool VJP>
-__device__ __forceinline__ Face<typename Props<S>::C> face(const Args &a, int axis, S kxLo,
-                                                          S kxUp, bool open, double pLo,
-                                                          double pUp,
-                                                          typename Props<S>::C rhoLo,
-                                                          typename Props<S>::C rhoUp,
-                                                          typename Props<S>::C lamLo,
-                                                          typename Props<S>::C lamUp) {
-  if constexpr (sizeof(S) == 8) {
-    // directional permeability exactly as r_d * kx, geometric factor a_d
-    const double A = axis == 0 ? a.ax : (axis == 1 ? a.ay : a.az);
-    const double r = axis == 0 ? 1.0 : (axis == 1 ? a.ry : a.rz);
-    const double kLo = axis == 0 ? (double)kxLo : r * (double)kxLo;
-    const double kUp = axis == 0 ? (double)kxUp : r * (double)kxUp;
-    return face64<GRAV, DERIV, VJP>(a, A, kLo, kUp, open, pLo, pUp, rhoLo, rhoUp, lamLo, lamUp);
-  } else {
-    const float A2 = axis == 0 ? a.ax2f : (axis == 1 ? a.ay2f : a.az2f);
-    return face32<GRAV, DERIV, VJP>(a, A2, kxLo, kxUp, open, pLo, pUp, rhoLo, rhoUp, lamLo,
-                                    lamUp);
-  }
+// z face between planes k (Lo) and k+1 (Up): dPhi = (p_Lo - p_Up) + rho_avg G.
+// For FP32 `dpref` = pref[k] - pref[k+1] and the potential is formed in FP64.
+__device__ __forceinline__ double zpot(double pLo, double pUp, double, double ra, const Args &a) {
+  return fma(ra, a.G, pLo - pUp);
+}
+__device__ __forceinline__ double zpot(float pLo, float pUp, double dpref, float ra,
+                                       const Args &a) {
+  return fma((double)ra, a.G, dpref + ((double)pLo - (double)pUp));
 }
 
-template <class S, int MODE>
-__device__ __forceinline__ void load_cell(Cell<S> &c, const Args &a, int64_t idx, bool ok) {
-  if (ok) {
-    c.p = static_cast<const S *>(a.p)[idx];
-    c.k = static_cast<const S *>(a.kx)[idx];
-    c.s = a.seal ? (uint32_t)a.seal[idx] : 0u;
-    if (MODE == MODE_VJP) c.w = static_cast<const S *>(a.w)[idx];
-  } else {
-    c.p = S(0);
-    c.k = S(0);
-    c.s = 0u;
-    c.w = S(0);
-  }
+template <bool DERIV, bool VJP, class S>
+__device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open, S pLo, S pUp,
+                                          double dpref, Props<S> Lo, Props<S> Up) {
+  Face<S> f;
+  S T;
+  if constexpr (sizeof(S) == 8)
+    T = trans64<VJP>(a.a2z, kLo, kUp, open, f);
+  else
+    T = trans32<VJP>(a.a2zf, kLo, kUp, open, f);
+  const S ra = S(0.5) * (Lo.rho + Up.rho);
+  const double dphi = zpot(pLo, pUp, dpref, ra, a);
+  const S hc = sizeof(S) == 8 ? S(a.hc) : S(a.hcf);
+  const S cf = sizeof(S) == 8 ? S(a.cf) : S(a.cff);
+  upwind<S, DERIV, true>(f, T, (S)dphi, dphi >= 0.0, Lo.lam, Up.lam, cf, fma(hc, Lo.rho, S(1)),
+                         fma(hc, Up.rho, S(-1)));
+  return f;
 }
+
+// Global-address-space views of the argument pointers: the ensemble kernel
+// reads them from its model table, where the compiler cannot infer the address
+// space and would otherwise emit flat (generic) memory instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
 
 template <class T>
-__device__ __forceinline__ void st_nt(T *base, int64_t idx, T v) {
-  __builtin_nontemporal_store(v, base + idx);
+__device__ __forceinline__ void st_nt(T *p, T v) {
+  __builtin_nontemporal_store(v, (gptr<T>)p);
 }
 
-// Bytes of LDS one tile needs.
+// Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
+// p, k, mobility, seal (and w for the vector-Jacobian product).
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
-  return 2 * HW * ((int)sizeof(S) * (MODE == MODE_VJP ? 3 : 2) +
-                   (int)sizeof(typename Props<S>::C) + 1);
+  return 2 * HW * ((int)sizeof(S) * (MODE == MODE_VJP ? 4 : 3) + 1);
 }
 
 // ----------------------------------------------------------------------------
 // The tile body: columns [bx*TX, bx*TX+TX) x [by*TY, by*TY+TY), planes
 // [kb, min(kb + kz_chunk, nz)).
 // ----------------------------------------------------------------------------
+
+// Uniform (scalar) base of plane k of an array plus a per-thread 32-bit byte
+// offset: addresses cost no vector ALU work.
+template <class T>
+__device__ __forceinline__ T at(const T *base, size_t plane_elems, int k, uint32_t boff) {
+  return *(gptr<const T>)(reinterpret_cast<const char *>(base + (size_t)k * plane_elems) + boff);
+}
+template <class T>
+__device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(base + elems) + boff);
+}
+
 template <class S, int MODE, int TX, int TY>
-__device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
-  using P = Props<S>;
-  using C = typename P::C;
-  constexpr int W = TX + 2, H = TY + 2, HW = W * H;
-  constexpr bool VJP = MODE == MODE_VJP;
-  constexpr bool DERIV = MODE != MODE_RESIDUAL;
-  constexpr bool FP32 = sizeof(S) == 4;
+struct Tile {
+  static constexpr int W = TX + 2, H = TY + 2, HW = W * H;
+  static constexpr bool VJP = MODE == MODE_VJP;
+  static constexpr bool DERIV = MODE != MODE_RESIDUAL;
+  static constexpr bool FP32 = sizeof(S) == 4;
 
-  S *s_p = reinterpret_cast<S *>(smem);
-  S *s_k = s_p + 2 * HW;
-  C *s_l = reinterpret_cast<C *>(s_k + 2 * HW);
-  S *s_w = reinterpret_cast<S *>(s_l + 2 * HW);
-  uint8_t *s_s = reinterpret_cast<uint8_t *>(s_w + (VJP ? 2 * HW : 0));
+  const Args &a;
+  S *s_p, *s_k, *s_l, *s_w;
+  uint8_t *s_s;
+  size_t plane;
+  int nz, kb, ke;
+  bool own, hv;
+  int ol, hl;
+  uint32_t cb, hb;     // byte offsets of the own and the halo cell within a plane (S elements)
+  uint32_t cs, hs;     // the same for the 1-byte seal array
+  S A2x, A2y;
 
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int64_t plane = a.plane;
-  const int ke = min(kb + a.kz_chunk, nz);
-  const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int i = bx * TX + tx, j = by * TY + ty;
-  const bool own = i < nx && j < ny;
-  const int64_t col = own ? (int64_t)j * nx + i : 0;
-  const int ol = (ty + 1) * W + tx + 1;
-
-  // the halo cell this thread stages (threads beyond the ring stage none)
-  int hl = -1, hi = -1, hj = -1;
-  if (tid < TX) {
-    hi = bx * TX + tid;
-    hj = by * TY - 1;
-    hl = tid + 1;
-  } else if (tid < 2 * TX) {
-    hi = bx * TX + tid - TX;
-    hj = by * TY + TY;
-    hl = (TY + 1) * W + tid - TX + 1;
-  } else if (tid < 2 * TX + TY) {
-    hi = bx * TX - 1;
-    hj = by * TY + tid - 2 * TX;
-    hl = (tid - 2 * TX + 1) * W;
-  } else if (tid < 2 * TX + 2 * TY) {
-    hi = bx * TX + TX;
-    hj = by * TY + tid - 2 * TX - TY;
-    hl = (tid - 2 * TX - TY + 1) * W + TX + 1;
-  }
-  const bool hv = hl >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
-  const int64_t hcol = hv ? (int64_t)hj * nx + hi : 0;
-
-  const bool has_mx = i > 0, has_px = i + 1 < nx;
-  const bool has_my = j > 0, has_py = j + 1 < ny;
-
-  const double *pref = a.pref;
-  auto pref_at = [&](int k) -> double { return FP32 ? pref[k] : 0.0; };
-
-  Cell<S> cur{}, nx1{}, pf{}, hcur{}, hnx{};
-  P dcur{}, dnx1{};
-  load_cell<S, MODE>(cur, a, kb * plane + col, own);
-  load_cell<S, MODE>(hcur, a, kb * plane + hcol, hv);
-  if (kb + 1 < nz) load_cell<S, MODE>(nx1, a, (kb + 1) * plane + col, own);
-  dcur.set(cur.p, pref_at(kb), a);
-
-  // -z face of the first plane of the chunk: face (kb-1, kb), own cell is Up
-  Face<C> fmz{};
-  S wmz = S(0);
-  if (kb > 0) {
-    Cell<S> pr;
-    load_cell<S, MODE>(pr, a, (kb - 1) * plane + col, own);
-    P dp;
-    dp.set(pr.p, pref_at(kb - 1), a);
-    fmz = face<S, true, DERIV, VJP>(a, 2, pr.k, cur.k, (pr.s & 4u) == 0u, dp.pa, dcur.pa,
-                                    dp.rho, dcur.rho, dp.lam, dcur.lam);
-    wmz = pr.w;
+  __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem) : a(a_) {
+    s_p = reinterpret_cast<S *>(smem);
+    s_k = s_p + 2 * HW;
+    s_l = s_k + 2 * HW;
+    s_w = s_l + 2 * HW;
+    s_s = reinterpret_cast<uint8_t *>(s_w + (VJP ? 2 * HW : 0));
+    const int nx = a.nx, ny = a.ny;
+    nz = a.nz;
+    kb = kb_;
+    ke = min(kb + a.kz_chunk, nz);
+    plane = (size_t)a.plane;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = bx * TX + tx, j = by * TY + ty;
+    own = i < nx && j < ny;
+    const uint32_t col = own ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
+    ol = (ty + 1) * W + tx + 1;
+    // the halo cell this thread stages (threads beyond the ring stage none)
+    int hi = -1, hj = -1;
+    hl = -1;
+    if (tid < TX) {
+      hi = bx * TX + tid;
+      hj = by * TY - 1;
+      hl = tid + 1;
+    } else if (tid < 2 * TX) {
+      hi = bx * TX + tid - TX;
+      hj = by * TY + TY;
+      hl = (TY + 1) * W + tid - TX + 1;
+    } else if (tid < 2 * TX + TY) {
+      hi = bx * TX - 1;
+      hj = by * TY + tid - 2 * TX;
+      hl = (tid - 2 * TX + 1) * W;
+    } else if (tid < 2 * TX + 2 * TY) {
+      hi = bx * TX + TX;
+      hj = by * TY + tid - 2 * TX - TY;
+      hl = (tid - 2 * TX - TY + 1) * W + TX + 1;
+    }
+    hv = hl >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const uint32_t hcol = hv ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
+    cb = col * (uint32_t)sizeof(S);
+    hb = hcol * (uint32_t)sizeof(S);
+    cs = col;
+    hs = hcol;
+    A2x = FP32 ? S(a.a2xf) : S(a.a2x);
+    A2y = FP32 ? S(a.a2yf) : S(a.a2y);
   }
 
-  for (int k = kb; k < ke; ++k) {
+  // A cell outside the domain reads the plane's first cell (any finite value)
+  // and gets k = 0, which closes every face that touches it (T = 0).
+  __device__ __forceinline__ void load(Cell<S> &c, int k, bool halo) const {
+    const bool ok = halo ? hv : own;
+    const uint32_t b = halo ? hb : cb;
+    c.p = at(static_cast<const S *>(a.p), plane, k, b);
+    const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
+    c.k = ok ? kx : S(0);
+    c.s = a.seal ? (uint32_t)at(a.seal, plane, k, halo ? hs : cs) : 0u;
+    if (VJP) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+  }
+
+  // FP32 form: x_k = pref[k] - p0 for the density exponent
+  __device__ __forceinline__ double pr(int k) const { return *((gptr<const double>)a.pref + k); }
+  __device__ __forceinline__ S xoff(int k) const { return FP32 ? (S)(pr(k) - a.p0) : S(0); }
+  __device__ __forceinline__ double dpref(int k) const { return FP32 ? pr(k) - pr(k + 1) : 0.0; }
+
+  // The -z face of the chunk's first plane: face (kb-1, kb), own cell is Up.
+  __device__ __forceinline__ Face<S> first_zface(const Cell<S> &cur, const Props<S> &dcur) const {
+    Face<S> f{};
+    if (kb > 0) {
+      Cell<S> pr;
+      load(pr, kb - 1, false);
+      const Props<S> dp = props(pr.p, xoff(kb - 1), a);
+      f = face_z<DERIV, VJP>(a, pr.k, cur.k, (pr.s & 4u) == 0u, pr.p, cur.p, dpref(kb - 1), dp,
+                             dcur);
+      f.w = pr.w;
+    }
+    return f;
+  }
+
+  // One plane k. c0/d0: own cell at k; c1: own cell at k+1 (loaded), d1 is
+  // computed here; c2 receives the prefetch of k+2. h0: halo cell at k, h1
+  // receives the halo cell at k+1. zm: face (k-1, k); zp receives face (k, k+1).
+  __device__ __forceinline__ void step(int k, const Cell<S> &c0, const Props<S> &d0,
+                                       const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
+                                       const Cell<S> &h0, Cell<S> &h1, const Face<S> &zm,
+                                       Face<S> &zp) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
-    const double pref_k = pref_at(k);
-    // prefetch: own column two planes ahead, halo one plane ahead
-    if (k + 2 < nz && k + 2 <= ke) load_cell<S, MODE>(pf, a, (int64_t)(k + 2) * plane + col, own);
-    if (k + 1 < ke) load_cell<S, MODE>(hnx, a, (int64_t)(k + 1) * plane + hcol, hv);
+    const S xk = xoff(k);
+    if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2, false);
+    if (k + 1 < ke) load(h1, k + 1, true);
 
-    // stage plane k: own cell and halo cell
-    s_p[b + ol] = cur.p;
-    s_k[b + ol] = cur.k;
-    s_l[b + ol] = dcur.lam;
-    s_s[b + ol] = (uint8_t)cur.s;
-    if (VJP) s_w[b + ol] = cur.w;
+    // stage plane k: own cell and halo cell (absent cells stage zeros, which
+    // make every face towards them closed: T = 0)
+    s_p[b + ol] = c0.p;
+    s_k[b + ol] = c0.k;
+    s_l[b + ol] = d0.lam;
+    s_s[b + ol] = (uint8_t)c0.s;
+    if (VJP) s_w[b + ol] = c0.w;
     if (hl >= 0) {
-      P dh;
-      dh.set(hcur.p, pref_k, a);
-      s_p[b + hl] = hcur.p;
-      s_k[b + hl] = hcur.k;
-      s_l[b + hl] = hv ? dh.lam : C(0);
-      s_s[b + hl] = (uint8_t)hcur.s;
-      if (VJP) s_w[b + hl] = hcur.w;
+      const Props<S> dh = props(h0.p, xk, a);
+      s_p[b + hl] = h0.p;
+      s_k[b + hl] = h0.k;
+      s_l[b + hl] = dh.lam;
+      s_s[b + hl] = (uint8_t)h0.s;
+      if (VJP) s_w[b + hl] = h0.w;
     }
     __syncthreads();
 
-    if (has_pz) dnx1.set(nx1.p, pref_at(k + 1), a);
+    // on the last plane c1 holds a stale (finite) cell and the +z face is closed
+    d1 = props(c1.p, xoff(has_pz ? k + 1 : k), a);
 
-    // the six faces, in the neighbour order -x, +x, -y, +y, -z, +z
-    Face<C> f[6] = {};
-    S wn[6] = {};
-    {
-      const int sl[4] = {ol - 1, ol + 1, ol - W, ol + W};
+    // the six faces, in the neighbour order -x, +x, -y, +y, -z, +z; a face
+    // whose neighbour does not exist has T = 0 and contributes exact zeros
+    Face<S> f[6];
+    S wn[6];
+    const int sl[4] = {ol - 1, ol + 1, ol - W, ol + W};
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const int axis = n >> 1;
-        const bool lower_is_own = n & 1;
-        const int q = b + sl[n];
-        const S pn = s_p[q];
-        const S kn = s_k[q];
-        const C ln = s_l[q];
-        const uint32_t sn = s_s[q];
-        if (VJP) wn[n] = s_w[q];
-        const double pna = P::absp(pn, pref_k);
-        const uint32_t bit = 1u << axis;
-        if (lower_is_own) {
-          f[n] = face<S, false, DERIV, VJP>(a, axis, cur.k, kn, (cur.s & bit) == 0u, dcur.pa, pna,
-                                            C(0), C(0), dcur.lam, ln);
-        } else {
-          f[n] = face<S, false, DERIV, VJP>(a, axis, kn, cur.k, (sn & bit) == 0u, pna, dcur.pa,
-                                            C(0), C(0), ln, dcur.lam);
+    for (int n = 0; n < 4; ++n) {
+      const int axis = n >> 1;
+      const int q = b + sl[n];
+      const S pn = s_p[q];
+      const S kn = s_k[q];
+      const S ln = s_l[q];
+      const uint32_t sn = s_s[q];
+      if (VJP) wn[n] = s_w[q];
+      const uint32_t bit = 1u << axis;
+      const S A2 = axis == 0 ? A2x : A2y;
+      if (n & 1)
+        f[n] = face_h<DERIV, VJP>(a, A2, c0.k, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
+      else
+        f[n] = face_h<DERIV, VJP>(a, A2, kn, c0.k, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
+    }
+    f[4] = zm;
+    wn[4] = zm.w;
+    zp = face_z<DERIV, VJP>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
+                            has_pz ? dpref(k) : 0.0, d0, d1);
+    zp.w = c0.w;
+    f[5] = zp;
+    wn[5] = c1.w;
+
+    if (!own) return;
+    const size_t ko = (size_t)k * plane;
+    if constexpr (MODE == MODE_VJP) {
+      // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
+      double gp = 0.0, gm = 0.0;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) {
+        const double d = (double)c0.w - (double)wn[n];
+        if (n & 1) {  // own cell is Lo
+          gp = fma(d, (double)f[n].dLo, gp);
+          gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
+        } else {      // own cell is Up
+          gp = fma(-d, (double)f[n].dUp, gp);
+          gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
         }
       }
-    }
-    f[4] = fmz;
-    wn[4] = wmz;
-    if (has_pz) {
-      f[5] = face<S, true, DERIV, VJP>(a, 2, cur.k, nx1.k, (cur.s & 4u) == 0u, dcur.pa, dnx1.pa,
-                                       dcur.rho, dnx1.rho, dcur.lam, dnx1.lam);
-      wn[5] = nx1.w;
-    }
-    const bool ex[6] = {has_mx, has_px, has_my, has_py, k > 0, has_pz};
-
-    if (own) {
-      const int64_t idx = (int64_t)k * plane + col;
-      if constexpr (MODE == MODE_VJP) {
-        double gp = 0.0, gm = 0.0;
+      if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
+      if (a.gm) st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
+    } else {
+      // residual in the neighbour order, accumulated in FP64
+      double r = 0.0;
 #pragma unroll
-        for (int n = 0; n < 6; ++n) {
-          if (!ex[n]) continue;
-          const double d = (double)cur.w - (double)wn[n];
-          if (n & 1) {  // own cell is Lo
-            gp += d * (double)f[n].dLo;
-            gm += d * ((double)f[n].F * (double)f[n].qUp);
-          } else {      // own cell is Up
-            gp -= d * (double)f[n].dUp;
-            gm -= d * ((double)f[n].F * (double)f[n].qLo);
-          }
-        }
-        if (a.gp) st_nt(static_cast<S *>(a.gp), idx, (S)gp);
-        if (a.gm) st_nt(static_cast<S *>(a.gm), idx, (S)gm);
-      } else {
-        double r = 0.0;
-        double dg = 0.0;
-        C off[6];
+      for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
+      if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
+      if constexpr (DERIV) {
+        S *J = static_cast<S *>(a.J);
+        const size_t nc = (size_t)nz * plane;
+        S dg = S(0);
 #pragma unroll
-        for (int n = 0; n < 6; ++n) {
-          if (n & 1) {
-            r += ex[n] ? (double)f[n].F : 0.0;
-            if (DERIV) {
-              dg += ex[n] ? (double)f[n].dLo : 0.0;
-              off[n] = ex[n] ? f[n].dUp : C(0);
-            }
-          } else {
-            r -= ex[n] ? (double)f[n].F : 0.0;
-            if (DERIV) {
-              dg -= ex[n] ? (double)f[n].dUp : 0.0;
-              off[n] = ex[n] ? -f[n].dLo : C(0);
-            }
-          }
-        }
-        if (a.r) st_nt(static_cast<S *>(a.r), idx, (S)r);
-        if constexpr (DERIV) {
-          S *J = static_cast<S *>(a.J);
-          const int64_t nc = (int64_t)nz * plane;
-          st_nt(J, idx, (S)dg);
+        for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
+        st_nt(at_w(J, ko, cb), dg);
 #pragma unroll
-          for (int n = 0; n < 6; ++n) st_nt(J, (int64_t)(n + 1) * nc + idx, (S)off[n]);
-        }
+        for (int n = 0; n < 6; ++n)
+          st_nt(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
       }
     }
+  }
+};
 
-    // advance the column: the +z face becomes the next plane's -z face
-    fmz = f[5];
-    wmz = cur.w;
-    cur = nx1;
-    dcur = dnx1;
-    nx1 = pf;
-    hcur = hnx;
+template <class S, int MODE, int TX, int TY>
+__device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
+  const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem);
+  // own column at planes k, k+1, k+2, halo cell at k, k+1, z faces (k-1,k), (k,k+1)
+  Cell<S> c0{}, c1{}, c2{}, h0{}, h1{};
+  Props<S> d0{}, d1{};
+  Face<S> z0{}, z1{};
+  t.load(c0, kb, false);
+  t.load(h0, kb, true);
+  if (kb + 1 < t.nz) t.load(c1, kb + 1, false);
+  d0 = props(c0.p, t.xoff(kb), a);
+  z0 = t.first_zface(c0, d0);
+  for (int k = kb; k < t.ke; ++k) {
+    t.step(k, c0, d0, c1, d1, c2, h0, h1, z0, z1);
+    c0 = c1;
+    d0 = d1;
+    c1 = c2;
+    h0 = h1;
+    z0 = z1;
   }
 }
 
@@ -437,7 +476,8 @@ __device__ __forceinline__ void decode_tile(const Args &a, int64_t b, int &bx, i
 }
 
 template <class S, int MODE, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) march_kernel(const Args a) {
+__global__ void __launch_bounds__(TX *TY)
+    march_kernel(const Args a) {
   __shared__ __attribute__((aligned(16))) char smem[tile_lds_bytes<S, MODE, TX, TY>()];
   int bx, by, kb;
   decode_tile(a, blockIdx.x, bx, by, kb);
@@ -469,11 +509,13 @@ __global__ void __launch_bounds__(kPersistThreads)
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&counter[0], 1u);
     __syncthreads();
-    const unsigned int it = s_item;
+    // the item index is uniform: keep it (and everything read through it) in
+    // scalar registers
+    const unsigned int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // s_item is rewritten next iteration
     if ((int64_t)it >= n_items) break;
     const WorkItem w = items[it];
-    const Args m = models[w.model];
+    const Args &m = models[__builtin_amdgcn_readfirstlane(w.model)];
     switch (m.tile) {
       case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
       case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;

@@ -1,0 +1,155 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (library defaults; autotuned tiles for the ensemble):
+
+* 512 x 512 x 256 FP64 residual + Jacobian, and the FP32 precision form of the
+  same geomodel: sampled cells (random, plus every domain face, edge and
+  corner class) against the oracle evaluated cell by cell, and an invariant
+  over the whole grid (the columns of J sum to zero);
+* 256 x 256 x 128 FP32 residual and vector-Jacobian product against the full
+  oracle evaluation;
+* the 64-model uneven ensemble in one persistent launch: every model bitwise
+  equal to its own single-grid launch, and sampled cells against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import geomodel
+from helpers import compare_full, compare_rows, compare_vjp
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL64, TOL32, TAU32 = 1e-12, 1e-5, 0.05
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sample_cells(grid, n_random, seed):
+    nx, ny, nz = grid.nx, grid.ny, grid.nz
+    rng = np.random.default_rng(seed)
+    cells = [rng.integers(0, nx * ny * nz, n_random)]
+    # every combination of low / interior / high position along each axis
+    for i in (0, 1, nx // 2, nx - 2, nx - 1):
+        for j in (0, 1, ny // 3, ny - 2, ny - 1):
+            for k in (0, 1, nz // 2, nz - 2, nz - 1):
+                cells.append(np.array([i + nx * (j + ny * k)]))
+    # a full x row and a full y column on the bottom plane
+    cells.append(np.arange(nx) + nx * (ny // 2))
+    cells.append(nx // 2 + nx * np.arange(ny))
+    return np.unique(np.concatenate(cells)).astype(np.int64)
+
+
+def colsum_check(J, tol):
+    """Columns of J sum to zero (sum_K r_K is identically zero) on the whole grid."""
+    col = J[0].clone()
+    col[:, :, 1:] += J[2][:, :, :-1]    # +x neighbour entries of cell i-1
+    col[:, :, :-1] += J[1][:, :, 1:]    # -x neighbour entries of cell i+1
+    col[:, 1:, :] += J[4][:, :-1, :]
+    col[:, :-1, :] += J[3][:, 1:, :]
+    col[1:, :, :] += J[6][:-1, :, :]
+    col[:-1, :, :] += J[5][1:, :, :]
+    scale = J.abs().sum(dim=0)
+    bad = (col.abs() > tol * scale).sum().item()
+    assert bad == 0, f"{bad} columns of J do not sum to zero"
+
+
+@pytest.fixture(scope="module")
+def big(orc):
+    geo = geomodel.big512(noise_seeds=(2,))
+    pref = orc.hydrostatic(geo.grid, geo.fluid)
+    return geo, pref
+
+
+def test_fullsize_fp64_jacobian(gpu, orc, big):
+    geo, pref = big
+    print("512x512x256 fp64 jacobian", flush=True)
+    p = pref[:, None, None] + geo.noise[0]
+    r, J = gpu.jacobian(geo.grid, geo.fluid, dev(geo.kx), dev(p), seal=dev(geo.seal),
+                        ry=geo.ry, rz=geo.rz)
+    torch.cuda.synchronize()
+    colsum_check(J, 1e-14)
+    cells = sample_cells(geo.grid, 40000, 11)
+    idx = torch.from_numpy(cells).cuda()
+    r_s = r.view(-1)[idx].cpu().numpy()
+    J_s = J.view(7, -1)[:, idx].cpu().numpy()
+    del r, J
+    rep = compare_rows(orc, geo.grid, geo.fluid, geo.kx, p, cells, r_s, J_s, tol=TOL64,
+                       tau=1e-9 * np.abs(p).max(), ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    print("fp64 full size:", rep)
+    assert rep["max_err"] <= TOL64
+
+
+def test_fullsize_fp32_jacobian(gpu, orc, big):
+    geo, pref = big
+    print("512x512x256 fp32 jacobian", flush=True)
+    dp, k32 = geo.dp32(0), geo.kx32()
+    r, J = gpu.jacobian(geo.grid, geo.fluid, dev(k32), dev(dp), seal=dev(geo.seal),
+                        pref=dev(pref), ry=geo.ry, rz=geo.rz)
+    torch.cuda.synchronize()
+    colsum_check(J.double(), 1e-6)
+    cells = sample_cells(geo.grid, 40000, 12)
+    idx = torch.from_numpy(cells).cuda()
+    r_s = r.view(-1)[idx].double().cpu().numpy()
+    J_s = J.view(7, -1)[:, idx].double().cpu().numpy()
+    del r, J
+    p_w = orc.widen_fp32(dp, pref)
+    rep = compare_rows(orc, geo.grid, geo.fluid, k32.astype(np.float64), p_w, cells, r_s, J_s,
+                       tol=TOL32, tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    print("fp32 full size:", rep)
+    assert rep["max_err"] <= TOL32
+
+
+def test_fullsize_adjoint(gpu, orc):
+    geo = geomodel.adjoint256(n_sets=1)
+    print("256x256x128 fp32 residual + vjp", flush=True)
+    pref = orc.hydrostatic(geo.grid, geo.fluid)
+    dp, k32 = geo.dp32(0), geo.kx32()
+    w32 = geo.extra["w"][0].astype(np.float32)
+    kw = dict(seal=dev(geo.seal), pref=dev(pref), ry=geo.ry, rz=geo.rz)
+    r = gpu.residual(geo.grid, geo.fluid, dev(k32), dev(dp), **kw)
+    gp, gm = gpu.residual_vjp(geo.grid, geo.fluid, dev(k32), dev(dp), dev(w32), **kw)
+    torch.cuda.synchronize()
+    p_w = orc.widen_fp32(dp, pref)
+    k_w = k32.astype(np.float64)
+    rep = compare_full(orc, geo.grid, geo.fluid, k_w, p_w, r.cpu().numpy(), None, tol=TOL32,
+                       tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    print("adjoint forward:", rep)
+    assert rep["max_err"] <= TOL32
+    rep = compare_vjp(orc, geo.grid, geo.fluid, k_w, p_w, w32.astype(np.float64),
+                      gp.cpu().numpy(), gm.cpu().numpy(), tol=TOL32, tau=TAU32, ry=geo.ry,
+                      rz=geo.rz, seal=geo.seal)
+    print("adjoint vjp:", rep)
+    assert rep["max_err"] <= TOL32
+
+
+def test_fullsize_ensemble(gpu, orc):
+    from paper_2304_11274_amd import autotune
+    models = geomodel.ensemble()
+    print(f"ensemble of {len(models)} models", flush=True)
+    members, prefs = [], []
+    for geo in models:
+        pref = orc.hydrostatic(geo.grid, geo.fluid)
+        prefs.append(pref)
+        members.append(dict(grid=geo.grid, fluid=geo.fluid, kx=dev(geo.kx32()), p=dev(geo.dp32()),
+                            seal=dev(geo.seal), pref=dev(pref), ry=geo.ry, rz=geo.rz))
+    autotune.tune_members(members)
+    ens = gpu.Ensemble(members)
+    ens.run()
+    torch.cuda.synchronize()
+    for q, (m, geo) in enumerate(zip(members, models)):
+        r, J = gpu.jacobian(m["grid"], m["fluid"], m["kx"], m["p"], seal=m["seal"],
+                            pref=m["pref"], ry=m["ry"], rz=m["rz"], tile=m["tile"],
+                            kz_chunk=m["kz_chunk"])
+        torch.cuda.synchronize()
+        assert torch.equal(ens.r[q], r) and torch.equal(ens.J[q], J), q
+        cells = sample_cells(geo.grid, 300, 100 + q)
+        idx = torch.from_numpy(cells).cuda()
+        r_s = ens.r[q].view(-1)[idx].double().cpu().numpy()
+        J_s = ens.J[q].view(7, -1)[:, idx].double().cpu().numpy()
+        p_w = orc.widen_fp32(geo.dp32(), prefs[q])
+        rep = compare_rows(orc, geo.grid, geo.fluid, geo.kx32().astype(np.float64), p_w, cells,
+                           r_s, J_s, tol=TOL32, tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+        assert rep["max_err"] <= TOL32, (q, rep)
+    ens.close()

@@ -79,7 +79,7 @@ def test_fp64_kz_chunks_bitwise(gpu, orc, kz):
     r0, J0 = fp64_run(gpu, geo, p)
     r, J = fp64_run(gpu, geo, p, kz_chunk=kz, tile=1)
     assert np.array_equal(r, r0) and np.array_equal(J, J0)
-    r, J = fp64_run(gpu, geo, p, kz_chunk=kz, xcd_remap=False)
+    r, J = fp64_run(gpu, geo, p, kz_chunk=kz, xcd_remap=True)
     assert np.array_equal(r, r0) and np.array_equal(J, J0)
 
 

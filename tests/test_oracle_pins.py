@@ -479,3 +479,47 @@ def test_golden_regression(orc):
     assert [[float.hex(float(v)) for v in row] for row in J] == doc["J"]
     pref = orc.hydrostatic(geo.grid, geo.fluid)
     assert [float.hex(float(v)) for v in pref] == doc["pref"]
+
+
+def test_fd_gradients_32cube(orc):
+    """Central differences of L = w . r on the 32^3 adjoint recipe: step 1e-4
+    relative in ln k (smooth), 10 Pa in p (cells next to a face within 40 Pa
+    of an upwind switch are skipped)."""
+    geo = geomodel.fd32()
+    p = orc.pressure(geo)
+    w = geo.extra["w"][0]
+    kw = dict(ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    out = orc.evaluate(geo.grid, geo.fluid, geo.kx, p, w=w, want=("r", "grad_p", "grad_logk",
+                                                                  "dphi"), **kw)
+    from helpers import cells_touching, tie_faces
+    kink = cells_touching(tie_faces(out["dphi"], 40.0)).ravel()
+    rng = np.random.default_rng(3)
+    N = geo.grid.ncell
+    m = geo.logk.ravel()
+
+    def L_of(kx=None, pp=None):
+        r = orc.evaluate(geo.grid, geo.fluid, geo.kx if kx is None else kx,
+                         p if pp is None else pp, want=("r",), **kw)["r"]
+        return float(np.dot(w.ravel(), r.ravel()))
+
+    for c in rng.choice(N, 48, replace=False):
+        h = 1e-4 * abs(m[c])
+        kp, km = geo.kx.copy().ravel(), geo.kx.copy().ravel()
+        kp[c] = np.exp(m[c] + h)
+        km[c] = np.exp(m[c] - h)
+        fd = (L_of(kx=kp.reshape(geo.grid.shape)) - L_of(kx=km.reshape(geo.grid.shape))) / (2 * h)
+        g = out["grad_logk"].ravel()[c]
+        assert abs(fd - g) <= 1e-5 * max(abs(g), 1e-3 * np.abs(out["grad_logk"]).max()), (c, fd, g)
+    checked = 0
+    for c in rng.choice(N, 96, replace=False):
+        if kink[c]:
+            continue
+        h = 10.0
+        pp, pm = p.copy().ravel(), p.copy().ravel()
+        pp[c] += h
+        pm[c] -= h
+        fd = (L_of(pp=pp.reshape(geo.grid.shape)) - L_of(pp=pm.reshape(geo.grid.shape))) / (2 * h)
+        g = out["grad_p"].ravel()[c]
+        assert abs(fd - g) <= 1e-6 * max(abs(g), 1e-3 * np.abs(out["grad_p"]).max()), (c, fd, g)
+        checked += 1
+    assert checked >= 48
