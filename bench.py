@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--sections", default="fp64,fp32,res,batched,adjoint,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -163,6 +163,9 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": res["algorithmic_GBps"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": res["hbm_frac"], "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
+                                           "WRITE_SIZE, copy-calibrated)",
+                           "algorithmic_bytes_per_launch": BYTES_FP64_RJ * N,
                            "kernel": "march_kernel<double, JACOBIAN, 64, 4>",
                            "bytes_per_cell": BYTES_FP64_RJ}
         log(f"fp64 r+J: {res['ms_per_step']:.4f} ms/step, {res['cells_per_s'] / 1e9:.2f} "
