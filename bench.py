@@ -137,7 +137,7 @@ def main():
                                  "4 rotating pressure fields",
                      "cells": N, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
                      "sigma_lnk": 1.5, "ry": 1.0, "rz": 0.1, "seal_fraction": 0.01,
-                     "launch": "library default (tile 64x4, 32 z-planes per workgroup)"}
+                     "launch": "library default (64x8 tiles, 16 z-planes per workgroup)"}
 
     def rate(ms, k, bytes_per_cell):
         t = ms / 1e3 / k
@@ -166,7 +166,7 @@ def main():
                            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                            "WRITE_SIZE, copy-calibrated)",
                            "algorithmic_bytes_per_launch": BYTES_FP64_RJ * N,
-                           "kernel": "march_kernel<double, JACOBIAN, 64, 4>",
+                           "kernel": "march_kernel<double, JACOBIAN, 64, 8>",
                            "bytes_per_cell": BYTES_FP64_RJ}
         log(f"fp64 r+J: {res['ms_per_step']:.4f} ms/step, {res['cells_per_s'] / 1e9:.2f} "
             f"Gcell/s, {res['algorithmic_GBps']:.0f} GB/s ({100 * res['hbm_frac']:.1f}% of 8 TB/s)")
@@ -243,10 +243,11 @@ def main():
         table = autotune.tune_members(members)
         solo = [(m["tile"], m["kz_chunk"]) for m in members]
         # one persistent launch: tiles by lane utilisation, one z-chunk timed on the batch
-        kz_best, kz_times = autotune.tune_ensemble(members)
-        log(f"autotuned {len(table)} size classes for per-model launches, ensemble z-chunk "
-            f"{kz_best} ({kz_times}) in {time.time() - t1:.1f} s")
+        ens_best, ens_times = autotune.tune_ensemble(members)
+        log(f"autotuned {len(table)} size classes for per-model launches; ensemble launch "
+            f"{ens_best} ({ens_times}) in {time.time() - t1:.1f} s")
         ens = tp.Ensemble(members)
+        ens.set_schedule(ens_best[2])
         n_items, n_wg = ens.info()
         log(f"ensemble of {len(members)} models, {cells} cells, {n_items} work items, "
             f"{n_wg} workgroups, set up in {time.time() - t0:.1f} s")
@@ -276,10 +277,11 @@ def main():
                 per_model()
         t_loop = tm.ms / KA
         out["batched"] = {"models": len(members), "cells": cells, "work_items": n_items,
-                          "workgroups": n_wg, "dtype": "f32",
+                          "workgroups": n_wg, "schedule": ens_best[2], "dtype": "f32",
                           "cells_per_s": cells / (t_graph / 1e3), "ms_per_step": t_graph,
                           "algorithmic_GBps": BYTES_FP32_RJ * cells / (t_graph / 1e3) / 1e9,
-                          "ensemble_tiles": ens_tiles, "ensemble_kz_timing_ms": kz_times,
+                          "ensemble_launch": ens_best, "ensemble_tiles": ens_tiles,
+                          "ensemble_autotune_ms": ens_times,
                           "per_model_launch_cells_per_s": cells / (t_loop / 1e3),
                           "per_model_launch_ms": t_loop,
                           "speedup_vs_per_model": t_loop / t_graph}

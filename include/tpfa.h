@@ -171,6 +171,15 @@ int tpfa_batch_run(tpfa_batch_t *batch, void *stream);
 /* The same persistent kernel launched directly, without the graph. */
 int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream);
 
+/* How the one launch of a batch covers its work list:
+   TPFA_SCHEDULE_PERSISTENT (default): one workgroup per CU slot, taking work
+   items from a device counter until the list is drained;
+   TPFA_SCHEDULE_GROUPED: one workgroup per work item, dispatched by the
+   hardware. Re-captures the batch's graph; results are identical. */
+#define TPFA_SCHEDULE_PERSISTENT 0
+#define TPFA_SCHEDULE_GROUPED 1
+int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule);
+
 /* Number of work items and of persistent workgroups of a batch. */
 int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgroups);
 

@@ -24,6 +24,8 @@ TPFA_FP32 = 1
 TPFA_BATCH_RESIDUAL = 0
 TPFA_BATCH_JACOBIAN = 1
 TPFA_LAUNCH_XCD_REMAP = 1
+TPFA_SCHEDULE_PERSISTENT = 0
+TPFA_SCHEDULE_GROUPED = 1
 
 
 class Grid(C.Structure):
@@ -71,6 +73,7 @@ SIGNATURES = {
     "tpfa_batch_run": (C.c_int, [vp, vp]),
     "tpfa_batch_run_eager": (C.c_int, [vp, vp]),
     "tpfa_batch_info": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
+    "tpfa_batch_set_schedule": (C.c_int, [vp, C.c_int]),
     "tpfa_batch_destroy": (None, [vp]),
     "tpfa_num_tiles": (C.c_int, []),
     "tpfa_tile_shape": (C.c_int, [C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),

@@ -217,6 +217,13 @@ class Ensemble:
         L.check(self._lib.tpfa_batch_create(arr, len(self.members), prec, self.mode,
                                             C.byref(self._handle), _stream(self.device)),
                 self._lib)
+        self.schedule = "persistent"
+
+    def set_schedule(self, schedule: str):
+        """'persistent' (work counter) or 'grouped' (one workgroup per item)."""
+        code = {"persistent": L.TPFA_SCHEDULE_PERSISTENT, "grouped": L.TPFA_SCHEDULE_GROUPED}[schedule]
+        L.check(self._lib.tpfa_batch_set_schedule(self._handle, code), self._lib)
+        self.schedule = schedule
 
     def run(self, graph: bool = True):
         fn = self._lib.tpfa_batch_run if graph else self._lib.tpfa_batch_run_eager

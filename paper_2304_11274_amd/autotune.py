@@ -102,34 +102,43 @@ def tune_members(members: Sequence[dict], *, cache: Optional[str] = None, **kw
     return table
 
 
-def ensemble_tile(nx: int, ny: int) -> int:
-    """The 256-thread tile with the best lane utilisation; ties go to the wider
-    tile (longer contiguous rows per wave)."""
+def ensemble_tile(nx: int, ny: int, tiles: Sequence[int] = (0, 1)) -> int:
+    """The tile with the best lane utilisation among ``tiles``; ties go to the
+    wider tile (longer contiguous rows per wave). 16-wide rows are left out by
+    default: in FP32 they fill only half a 128-byte line per row."""
     best = None
-    for t in TILE_IDS_256:
+    for t in tiles:
         u = lane_utilisation(nx, ny, t)
         if best is None or u > best[1] + 1e-12:
             best = (t, u)
     return best[0]
 
 
-def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64, 128),
-                  reps: int = 5, mode: str = "jacobian") -> Tuple[int, Dict[int, float]]:
-    """Tiles per member by lane utilisation, then one z-chunk for the whole
-    ensemble chosen by timing the persistent launch (the work list then has
-    items of similar length and the prologue cost per item is amortised).
-    Sets ``tile`` and ``kz_chunk`` on every member; returns (kz, {kz: ms})."""
-    for m in members:
-        m["tile"] = ensemble_tile(m["grid"].nx, m["grid"].ny)
-    times = {}
-    for z in kz:
-        for m in members:
-            m["kz_chunk"] = z
-        ens = api.Ensemble(members, mode=mode)
-        times[z] = _time(ens.run, reps)
-        ens.close()
-        del ens
-    best = min(times, key=times.get)
-    for m in members:
-        m["kz_chunk"] = best
-    return best, times
+def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64),
+                  tiles: Sequence[int] = TILE_IDS_256,
+                  schedules: Sequence[str] = ("persistent", "grouped"), reps: int = 5,
+                  mode: str = "jacobian") -> Tuple[Tuple[str, int, str], Dict[str, float]]:
+    """Chooses the launch shape of one ensemble launch by timing it: every
+    uniform tile and a mixed assignment (per-model tile by lane utilisation),
+    each with every z-chunk and every schedule. Sets ``tile`` and ``kz_chunk``
+    on every member; returns ((assignment, kz, schedule), {label: ms})."""
+    mixed = [ensemble_tile(m["grid"].nx, m["grid"].ny) for m in members]
+    cands = [(f"tile{t}", [t] * len(members)) for t in tiles] + [("mixed", mixed)]
+    times, best = {}, None
+    for label, assign in cands:
+        for z in kz:
+            for m, t in zip(members, assign):
+                m["tile"], m["kz_chunk"] = t, z
+            ens = api.Ensemble(members, mode=mode)
+            for sch in schedules:
+                ens.set_schedule(sch)
+                ms = _time(ens.run, reps)
+                times[f"{label}/kz{z}/{sch}"] = ms
+                if best is None or ms < best[0]:
+                    best = (ms, label, assign, z, sch)
+            ens.close()
+            del ens
+    _, label, assign, z, sch = best
+    for m, t in zip(members, assign):
+        m["tile"], m["kz_chunk"] = t, z
+    return (label, z, sch), times

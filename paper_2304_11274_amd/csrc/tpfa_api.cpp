@@ -83,11 +83,17 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
   return TPFA_OK;
 }
 
-int default_tile(const tpfa_grid_t &g) {
+// Launch-shape defaults from a tile x z-chunk sweep on MI355X (512x512x256):
+// the Jacobian and residual kernels run best with 64x8 tiles, the
+// vector-Jacobian product (more registers) with 64x4; narrow grids take
+// narrower tiles.
+int default_tile(const tpfa_grid_t &g, tpfa::Mode mode) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
-  return tpfa::kDefaultTile;
+  return mode == tpfa::MODE_VJP ? 0 : 3;
 }
+
+int default_kz(tpfa::Mode mode) { return mode == tpfa::MODE_RESIDUAL ? 32 : 16; }
 
 int hip_fail(hipError_t e, const char *what) {
   return fail(TPFA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -147,10 +153,10 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
 
 namespace {
 
-int resolve_launch(const tpfa_grid_t &g, const tpfa_launch_t *launch, int &tile, int &kz,
-                   int &flags) {
-  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g);
-  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : tpfa::kDefaultKzChunk;
+int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, const tpfa_launch_t *launch,
+                   int &tile, int &kz, int &flags) {
+  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g, mode);
+  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode);
   flags = launch ? launch->flags : 0;
   return TPFA_OK;
 }
@@ -159,7 +165,7 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
   int tile, kz, flags;
-  resolve_launch(*g, launch, tile, kz, flags);
+  resolve_launch(*g, mode, launch, tile, kz, flags);
   // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
   tpfa::Args b;
   tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
@@ -272,6 +278,8 @@ struct tpfa_batch {
   unsigned int *d_counter = nullptr;
   int64_t n_items = 0;
   int n_wg = 0;
+  int tiles = 3;  // the tile shared by every model, or 3 for a mix
+  int schedule = TPFA_SCHEDULE_PERSISTENT;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -284,6 +292,34 @@ static void batch_free(tpfa_batch *b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_counter) (void)hipFree(b->d_counter);
   delete b;
+}
+
+static hipError_t batch_launch(tpfa_batch *b, hipStream_t st) {
+  if (b->schedule == TPFA_SCHEDULE_GROUPED)
+    return tpfa::launch_grouped(b->prec, b->mode, b->tiles, b->d_models, b->d_items, b->n_items,
+                                st);
+  return tpfa::launch_persistent(b->prec, b->mode, b->tiles, b->d_models, b->d_items, b->n_items,
+                                 b->d_counter, b->n_wg, st);
+}
+
+// Captures the batch's one launch into a graph on a private stream.
+static hipError_t batch_capture(tpfa_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t le = batch_launch(b, cs);
+    e = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  return e;
 }
 
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
@@ -310,7 +346,10 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       if (mode == TPFA_BATCH_RESIDUAL && !md.r)
         return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": r is NULL");
       int tile, kz, flags;
-      resolve_launch(md.grid, &md.launch, tile, kz, flags);
+      resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
+                                                          : tpfa::MODE_RESIDUAL,
+                     &md.launch, tile, kz, flags);
+      if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
                                        ": batched tiles must be 256-thread tiles");
@@ -330,7 +369,8 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     }
     if (items.size() > (size_t)std::numeric_limits<uint32_t>::max() / 2)
       return fail(TPFA_ERR_SHAPE, "too many work items");
-    // largest items first, so the shortest ones fill the tail
+    // full-size items first in natural order (neighbouring tiles of one model
+    // run together and share their halos in L2), partial items fill the tail
     std::stable_sort(items.begin(), items.end(),
                      [](const Item &x, const Item &y) { return x.cells > y.cells; });
     std::vector<tpfa::WorkItem> wl(items.size());
@@ -340,7 +380,10 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     b->prec = prec;
     b->mode = mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN : tpfa::MODE_RESIDUAL;
     b->n_items = (int64_t)wl.size();
-    const int wg = tpfa::persistent_workgroups(prec, b->mode);
+    b->tiles = args[0].tile;
+    for (const tpfa::Args &a : args)
+      if (a.tile != b->tiles) b->tiles = 3;
+    const int wg = tpfa::persistent_workgroups(prec, b->mode, b->tiles);
     if (wg <= 0) {
       batch_free(b);
       return fail(TPFA_ERR_HIP, "could not query the device occupancy");
@@ -363,22 +406,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       batch_free(b);
       return hip_fail(e, "batch upload");
     }
-    // capture the persistent launch into a graph on a private stream
-    hipStream_t cs = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
-      batch_free(b);
-      return hip_fail(e, "capture stream");
-    }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      const hipError_t le = tpfa::launch_persistent(prec, b->mode, b->d_models, b->d_items,
-                                                    b->n_items, b->d_counter, b->n_wg, cs);
-      e = hipStreamEndCapture(cs, &b->graph);
-      if (e == hipSuccess) e = le;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) {
+    if ((e = batch_capture(b)) != hipSuccess) {
       batch_free(b);
       return hip_fail(e, "graph capture");
     }
@@ -402,11 +430,21 @@ int tpfa_batch_run(tpfa_batch_t *batch, void *stream) {
 
 int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream) {
   if (!batch || !batch->d_items) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
-  const hipError_t e =
-      tpfa::launch_persistent(batch->prec, batch->mode, batch->d_models, batch->d_items,
-                              batch->n_items, batch->d_counter, batch->n_wg,
-                              static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "persistent launch");
+  const hipError_t e = batch_launch(batch, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "ensemble launch");
+  return ok();
+}
+
+int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule) {
+  if (!batch || !batch->d_items) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
+  if (schedule != TPFA_SCHEDULE_PERSISTENT && schedule != TPFA_SCHEDULE_GROUPED)
+    return fail(TPFA_ERR_PARAM, "unknown schedule");
+  if (batch->n_items > (int64_t)std::numeric_limits<uint32_t>::max() &&
+      schedule == TPFA_SCHEDULE_GROUPED)
+    return fail(TPFA_ERR_SHAPE, "too many work items for one workgroup each");
+  batch->schedule = schedule;
+  const hipError_t e = batch_capture(batch);
+  if (e != hipSuccess) return hip_fail(e, "graph capture");
   return ok();
 }
 

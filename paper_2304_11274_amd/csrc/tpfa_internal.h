@@ -12,16 +12,15 @@ namespace tpfa {
 enum Mode : int { MODE_RESIDUAL = 0, MODE_JACOBIAN = 1, MODE_VJP = 2 };
 
 // Tile table. A workgroup owns a TX x TY column block of one model and marches
-// it through a chunk of z planes. All shapes keep the halo ring (2 TX + 2 TY
-// cells) within one cell per thread.
+// it through a chunk of z planes; each thread stages ceil(2 (TX + TY) / threads)
+// cells of the halo ring. Wide tiles write long contiguous runs per plane.
 struct TileShape {
   int tx, ty, threads;
 };
-constexpr int kNumTiles = 6;
+constexpr int kNumTiles = 10;
 constexpr TileShape kTiles[kNumTiles] = {
-    {64, 4, 256}, {32, 8, 256}, {16, 16, 256}, {64, 8, 512}, {128, 4, 512}, {32, 16, 512}};
-constexpr int kDefaultTile = 0;
-constexpr int kDefaultKzChunk = 32;
+    {64, 4, 256},  {32, 8, 256},  {16, 16, 256}, {64, 8, 512},  {128, 4, 512},
+    {32, 16, 512}, {128, 2, 256}, {256, 1, 256}, {256, 2, 512}, {512, 1, 512}};
 
 // Everything a kernel needs about one grid; passed by value (kernel argument)
 // for single launches and stored in a device table for the batched kernel.
@@ -74,9 +73,12 @@ struct WorkItem {
   int32_t model;
   int32_t bx, by, kb;
 };
-hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, const Args *d_models,
+// `tiles`: 0, 1, 2 when every model uses that 256-thread tile, 3 for a mix.
+hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
                              const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
                              int n_workgroups, hipStream_t stream);
-int persistent_workgroups(tpfa_precision_t prec, Mode mode);
+int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles);
+hipError_t launch_grouped(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
+                          const WorkItem *d_items, int64_t n_items, hipStream_t stream);
 
 }  // namespace tpfa

@@ -245,15 +245,21 @@ struct Tile {
   static constexpr bool DERIV = MODE != MODE_RESIDUAL;
   static constexpr bool FP32 = sizeof(S) == 4;
 
+  static constexpr int NT = TX * TY;          // threads
+  static constexpr int NH = 2 * (TX + TY);    // halo ring cells (no corners)
+  static constexpr int HC = (NH + NT - 1) / NT;  // halo cells staged per thread
+
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w;
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
-  bool own, hv;
-  int ol, hl;
-  uint32_t cb, hb;     // byte offsets of the own and the halo cell within a plane (S elements)
-  uint32_t cs, hs;     // the same for the 1-byte seal array
+  bool own;
+  int ol;
+  uint32_t cb, cs;     // byte offset of the own cell within a plane (S elements / seal bytes)
+  bool hv[HC];         // halo cell q lies in the domain
+  int hl[HC];          // its LDS slot, -1 if the thread stages no q-th halo cell
+  uint32_t hb[HC], hs[HC];
   S A2x, A2y;
 
   __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem) : a(a_) {
@@ -273,46 +279,54 @@ struct Tile {
     own = i < nx && j < ny;
     const uint32_t col = own ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
     ol = (ty + 1) * W + tx + 1;
-    // the halo cell this thread stages (threads beyond the ring stage none)
-    int hi = -1, hj = -1;
-    hl = -1;
-    if (tid < TX) {
-      hi = bx * TX + tid;
-      hj = by * TY - 1;
-      hl = tid + 1;
-    } else if (tid < 2 * TX) {
-      hi = bx * TX + tid - TX;
-      hj = by * TY + TY;
-      hl = (TY + 1) * W + tid - TX + 1;
-    } else if (tid < 2 * TX + TY) {
-      hi = bx * TX - 1;
-      hj = by * TY + tid - 2 * TX;
-      hl = (tid - 2 * TX + 1) * W;
-    } else if (tid < 2 * TX + 2 * TY) {
-      hi = bx * TX + TX;
-      hj = by * TY + tid - 2 * TX - TY;
-      hl = (tid - 2 * TX - TY + 1) * W + TX + 1;
-    }
-    hv = hl >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
-    const uint32_t hcol = hv ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
     cb = col * (uint32_t)sizeof(S);
-    hb = hcol * (uint32_t)sizeof(S);
     cs = col;
-    hs = hcol;
+    // halo ring: bottom row, top row, left column, right column
+#pragma unroll
+    for (int q = 0; q < HC; ++q) {
+      const int h = tid + q * NT;
+      int hi = -1, hj = -1, l = -1;
+      if (h < TX) {
+        hi = bx * TX + h;
+        hj = by * TY - 1;
+        l = h + 1;
+      } else if (h < 2 * TX) {
+        hi = bx * TX + h - TX;
+        hj = by * TY + TY;
+        l = (TY + 1) * W + h - TX + 1;
+      } else if (h < 2 * TX + TY) {
+        hi = bx * TX - 1;
+        hj = by * TY + h - 2 * TX;
+        l = (h - 2 * TX + 1) * W;
+      } else if (h < NH) {
+        hi = bx * TX + TX;
+        hj = by * TY + h - 2 * TX - TY;
+        l = (h - 2 * TX - TY + 1) * W + TX + 1;
+      }
+      hl[q] = l;
+      hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+      const uint32_t hcol = hv[q] ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
+      hb[q] = hcol * (uint32_t)sizeof(S);
+      hs[q] = hcol;
+    }
     A2x = FP32 ? S(a.a2xf) : S(a.a2x);
     A2y = FP32 ? S(a.a2yf) : S(a.a2y);
   }
 
   // A cell outside the domain reads the plane's first cell (any finite value)
   // and gets k = 0, which closes every face that touches it (T = 0).
-  __device__ __forceinline__ void load(Cell<S> &c, int k, bool halo) const {
-    const bool ok = halo ? hv : own;
-    const uint32_t b = halo ? hb : cb;
+  __device__ __forceinline__ void load_at(Cell<S> &c, int k, bool ok, uint32_t b, uint32_t bs) const {
     c.p = at(static_cast<const S *>(a.p), plane, k, b);
     const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
     c.k = ok ? kx : S(0);
-    c.s = a.seal ? (uint32_t)at(a.seal, plane, k, halo ? hs : cs) : 0u;
+    c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
     if (VJP) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+  }
+  __device__ __forceinline__ void load(Cell<S> &c, int k) const { load_at(c, k, own, cb, cs); }
+  __device__ __forceinline__ void load_halo(Cell<S> (&h)[HC], int k) const {
+#pragma unroll
+    for (int q = 0; q < HC; ++q)
+      if (hl[q] >= 0) load_at(h[q], k, hv[q], hb[q], hs[q]);
   }
 
   // FP32 form: x_k = pref[k] - p0 for the density exponent
@@ -325,7 +339,7 @@ struct Tile {
     Face<S> f{};
     if (kb > 0) {
       Cell<S> pr;
-      load(pr, kb - 1, false);
+      load(pr, kb - 1);
       const Props<S> dp = props(pr.p, xoff(kb - 1), a);
       f = face_z<DERIV, VJP>(a, pr.k, cur.k, (pr.s & 4u) == 0u, pr.p, cur.p, dpref(kb - 1), dp,
                              dcur);
@@ -339,13 +353,13 @@ struct Tile {
   // receives the halo cell at k+1. zm: face (k-1, k); zp receives face (k, k+1).
   __device__ __forceinline__ void step(int k, const Cell<S> &c0, const Props<S> &d0,
                                        const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
-                                       const Cell<S> &h0, Cell<S> &h1, const Face<S> &zm,
-                                       Face<S> &zp) const {
+                                       const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
+                                       const Face<S> &zm, Face<S> &zp) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
     const S xk = xoff(k);
-    if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2, false);
-    if (k + 1 < ke) load(h1, k + 1, true);
+    if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
+    if (k + 1 < ke) load_halo(h1, k + 1);
 
     // stage plane k: own cell and halo cell (absent cells stage zeros, which
     // make every face towards them closed: T = 0)
@@ -354,13 +368,16 @@ struct Tile {
     s_l[b + ol] = d0.lam;
     s_s[b + ol] = (uint8_t)c0.s;
     if (VJP) s_w[b + ol] = c0.w;
-    if (hl >= 0) {
-      const Props<S> dh = props(h0.p, xk, a);
-      s_p[b + hl] = h0.p;
-      s_k[b + hl] = h0.k;
-      s_l[b + hl] = dh.lam;
-      s_s[b + hl] = (uint8_t)h0.s;
-      if (VJP) s_w[b + hl] = h0.w;
+#pragma unroll
+    for (int q = 0; q < HC; ++q) {
+      if (hl[q] < 0) continue;
+      const Props<S> dh = props(h0[q].p, xk, a);
+      const int l = b + hl[q];
+      s_p[l] = h0[q].p;
+      s_k[l] = h0[q].k;
+      s_l[l] = dh.lam;
+      s_s[l] = (uint8_t)h0[q].s;
+      if (VJP) s_w[l] = h0[q].w;
     }
     __syncthreads();
 
@@ -439,12 +456,13 @@ template <class S, int MODE, int TX, int TY>
 __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
   const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem);
   // own column at planes k, k+1, k+2, halo cell at k, k+1, z faces (k-1,k), (k,k+1)
-  Cell<S> c0{}, c1{}, c2{}, h0{}, h1{};
+  using T = Tile<S, MODE, TX, TY>;
+  Cell<S> c0{}, c1{}, c2{}, h0[T::HC]{}, h1[T::HC]{};
   Props<S> d0{}, d1{};
   Face<S> z0{}, z1{};
-  t.load(c0, kb, false);
-  t.load(h0, kb, true);
-  if (kb + 1 < t.nz) t.load(c1, kb + 1, false);
+  t.load(c0, kb);
+  t.load_halo(h0, kb);
+  if (kb + 1 < t.nz) t.load(c1, kb + 1);
   d0 = props(c0.p, t.xoff(kb), a);
   z0 = t.first_zface(c0, d0);
   for (int k = kb; k < t.ke; ++k) {
@@ -452,7 +470,8 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
     c0 = c1;
     d0 = d1;
     c1 = c2;
-    h0 = h1;
+#pragma unroll
+    for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
     z0 = z1;
   }
 }
@@ -491,37 +510,55 @@ __global__ void __launch_bounds__(TX *TY)
 // graph replay) on the stream starts from zero without a memset node.
 // ----------------------------------------------------------------------------
 constexpr int kPersistThreads = 256;
+constexpr int kMixedTiles = 3;  // TILE value of the kernel that switches shape per model
 
-template <class S, int MODE>
+template <class S, int MODE, int TILE>
 constexpr int persist_lds_bytes() {
   constexpr int a0 = tile_lds_bytes<S, MODE, 64, 4>();
   constexpr int a1 = tile_lds_bytes<S, MODE, 32, 8>();
   constexpr int a2 = tile_lds_bytes<S, MODE, 16, 16>();
-  return a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2);
+  return TILE == 0 ? a0
+                   : TILE == 1 ? a1
+                               : TILE == 2 ? a2 : (a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2));
 }
 
-template <class S, int MODE>
+// TILE = 0, 1, 2: every model uses that 256-thread tile (one code path, fewer
+// registers); TILE = kMixedTiles: the tile is read per model.
+template <class S, int MODE, int TILE>
 __global__ void __launch_bounds__(kPersistThreads)
     persistent_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items,
                       int64_t n_items, unsigned int *counter) {
-  __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE>()];
+  __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
   __shared__ unsigned int s_item;
+  if (threadIdx.x == 0) s_item = atomicAdd(&counter[0], 1u);
+  __syncthreads();
+  // the item index is uniform: keep it (and everything read through it) in
+  // scalar registers
+  unsigned int it = __builtin_amdgcn_readfirstlane(s_item);
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&counter[0], 1u);
-    __syncthreads();
-    // the item index is uniform: keep it (and everything read through it) in
-    // scalar registers
-    const unsigned int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();  // s_item is rewritten next iteration
     if ((int64_t)it >= n_items) break;
+    // claim the next item now; its index is only needed after this one
+    unsigned int nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(&counter[0], 1u);
     const WorkItem w = items[it];
-    const Args &m = models[__builtin_amdgcn_readfirstlane(w.model)];
-    switch (m.tile) {
-      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
-      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
-      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
+    const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
+    if constexpr (TILE == 0) {
+      march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
+    } else if constexpr (TILE == 1) {
+      march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
+    } else if constexpr (TILE == 2) {
+      march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
+    } else {
+      switch (m.tile) {
+        case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
+        case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
+        default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
+      }
     }
-    __syncthreads();  // LDS is reused by the next item
+    __syncthreads();  // LDS (and s_item) are reused by the next item
+    if (threadIdx.x == 0) s_item = nxt;
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_item);
   }
   // workgroup done: the last one out resets both counters for the next launch
   if (threadIdx.x == 0) {
@@ -584,6 +621,10 @@ static hipError_t launch_t(int tile, const Args &a, hipStream_t st) {
     case 3: march_kernel<S, MODE, 64, 8><<<grid, 512, 0, st>>>(a); break;
     case 4: march_kernel<S, MODE, 128, 4><<<grid, 512, 0, st>>>(a); break;
     case 5: march_kernel<S, MODE, 32, 16><<<grid, 512, 0, st>>>(a); break;
+    case 6: march_kernel<S, MODE, 128, 2><<<grid, 256, 0, st>>>(a); break;
+    case 7: march_kernel<S, MODE, 256, 1><<<grid, 256, 0, st>>>(a); break;
+    case 8: march_kernel<S, MODE, 256, 2><<<grid, 512, 0, st>>>(a); break;
+    case 9: march_kernel<S, MODE, 512, 1><<<grid, 512, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -606,51 +647,88 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
   }
 }
 
+// One workgroup per work item, dispatched by the hardware: the alternative
+// schedule of an ensemble launch (no counter, no item loop).
+template <class S, int MODE, int TILE>
+__global__ void __launch_bounds__(kPersistThreads)
+    grouped_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items) {
+  __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
+  const WorkItem w = items[blockIdx.x];
+  const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
+  if constexpr (TILE == 0) {
+    march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
+  } else if constexpr (TILE == 1) {
+    march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
+  } else if constexpr (TILE == 2) {
+    march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
+  } else {
+    switch (m.tile) {
+      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
+      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
+      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
+    }
+  }
+}
+
 template <class S, int MODE>
-static const void *persist_fn() {
-  return reinterpret_cast<const void *>(&persistent_kernel<S, MODE>);
+static const void *grouped_fn(int tiles) {
+  switch (tiles) {
+    case 0: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 0>);
+    case 1: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 1>);
+    case 2: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 2>);
+    default: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, kMixedTiles>);
+  }
 }
 
-static const void *persist_ptr(tpfa_precision_t prec, Mode mode) {
+hipError_t launch_grouped(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
+                          const WorkItem *d_items, int64_t n_items, hipStream_t st) {
+  const void *fn;
   if (prec == TPFA_FP64)
-    return mode == MODE_RESIDUAL ? persist_fn<double, MODE_RESIDUAL>()
-                                 : persist_fn<double, MODE_JACOBIAN>();
-  return mode == MODE_RESIDUAL ? persist_fn<float, MODE_RESIDUAL>()
-                               : persist_fn<float, MODE_JACOBIAN>();
+    fn = mode == MODE_RESIDUAL ? grouped_fn<double, MODE_RESIDUAL>(tiles)
+                               : grouped_fn<double, MODE_JACOBIAN>(tiles);
+  else
+    fn = mode == MODE_RESIDUAL ? grouped_fn<float, MODE_RESIDUAL>(tiles)
+                               : grouped_fn<float, MODE_JACOBIAN>(tiles);
+  void *args[] = {(void *)&d_models, (void *)&d_items};
+  return hipLaunchKernel(fn, dim3((unsigned)n_items), dim3(kPersistThreads), args, 0, st);
 }
 
-int persistent_workgroups(tpfa_precision_t prec, Mode mode) {
+template <class S, int MODE>
+static const void *persist_fn(int tiles) {
+  switch (tiles) {
+    case 0: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 0>);
+    case 1: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 1>);
+    case 2: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 2>);
+    default: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, kMixedTiles>);
+  }
+}
+
+static const void *persist_ptr(tpfa_precision_t prec, Mode mode, int tiles) {
+  if (prec == TPFA_FP64)
+    return mode == MODE_RESIDUAL ? persist_fn<double, MODE_RESIDUAL>(tiles)
+                                 : persist_fn<double, MODE_JACOBIAN>(tiles);
+  return mode == MODE_RESIDUAL ? persist_fn<float, MODE_RESIDUAL>(tiles)
+                               : persist_fn<float, MODE_JACOBIAN>(tiles);
+}
+
+int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_ptr(prec, mode),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_ptr(prec, mode, tiles),
                                                    kPersistThreads, 0) != hipSuccess)
     return -1;
   if (per_cu < 1) per_cu = 1;
   return cus * per_cu;
 }
 
-hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, const Args *d_models,
+hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
                              const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
                              int n_workgroups, hipStream_t st) {
-  const dim3 grid((unsigned)n_workgroups);
-  if (prec == TPFA_FP64) {
-    if (mode == MODE_RESIDUAL)
-      persistent_kernel<double, MODE_RESIDUAL>
-          <<<grid, kPersistThreads, 0, st>>>(d_models, d_items, n_items, d_counter);
-    else
-      persistent_kernel<double, MODE_JACOBIAN>
-          <<<grid, kPersistThreads, 0, st>>>(d_models, d_items, n_items, d_counter);
-  } else {
-    if (mode == MODE_RESIDUAL)
-      persistent_kernel<float, MODE_RESIDUAL>
-          <<<grid, kPersistThreads, 0, st>>>(d_models, d_items, n_items, d_counter);
-    else
-      persistent_kernel<float, MODE_JACOBIAN>
-          <<<grid, kPersistThreads, 0, st>>>(d_models, d_items, n_items, d_counter);
-  }
-  return hipGetLastError();
+  void *args[] = {(void *)&d_models, (void *)&d_items, (void *)&n_items, (void *)&d_counter};
+  return hipLaunchKernel(persist_ptr(prec, mode, tiles), dim3((unsigned)n_workgroups),
+                         dim3(kPersistThreads), args, 0, st);
 }
 
 hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, double p_top,

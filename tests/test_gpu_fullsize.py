@@ -134,8 +134,9 @@ def test_fullsize_ensemble(gpu, orc):
         prefs.append(pref)
         members.append(dict(grid=geo.grid, fluid=geo.fluid, kx=dev(geo.kx32()), p=dev(geo.dp32()),
                             seal=dev(geo.seal), pref=dev(pref), ry=geo.ry, rz=geo.rz))
-    autotune.tune_members(members)
+    (_, _, schedule), _ = autotune.tune_ensemble(members, reps=2)
     ens = gpu.Ensemble(members)
+    ens.set_schedule(schedule)
     ens.run()
     torch.cuda.synchronize()
     for q, (m, geo) in enumerate(zip(members, models)):

@@ -284,10 +284,12 @@ def test_ensemble_matches_single_launches_and_oracle(gpu, orc, prec):
                             pref=d.get("pref"), ry=d["ry"], rz=d["rz"], tile=d["tile"],
                             kz_chunk=d["kz_chunk"])
         singles.append((r, J))
-    for replay in range(3):
+    for replay in range(5):
         for q in range(len(members)):
             ens.r[q].fill_(float("nan"))
             ens.J[q].fill_(float("nan"))
+        if replay == 3:
+            ens.set_schedule("grouped")
         ens.run(graph=(replay != 1))
         torch.cuda.synchronize()
         for q, (r, J) in enumerate(singles):
