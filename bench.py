@@ -15,6 +15,8 @@ The same run also times, as extra fields of the JSON line:
   batched  - the 64-model uneven ensemble: one persistent kernel replayed from a
              HIP graph vs one launch per model
   adjoint  - FP32 forward residual + vector-Jacobian product on 256 x 256 x 128
+  paper10  - the paper's own workload (Sec. 6): 1000 applications of the FP32
+             10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
   cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
 The roofline object is for the dominant kernel, the FP64 Jacobian kernel.
 
@@ -38,6 +40,9 @@ BYTES_FP32_RJ = 4 + 4 + 1 + 4 + 7 * 4      # dp, kx, seal -> r, J = 41
 BYTES_FP64_R = 8 + 8 + 1 + 8               # 25
 BYTES_FP32_R = 4 + 4 + 1 + 4               # 13
 BYTES_FP32_VJP = 4 + 4 + 1 + 4 + 4 + 4     # dp, kx, seal, w -> grad_p, grad_logk = 21
+BYTES_FP32_R10 = 4 + 4 + 4 + 4 + 4         # dp, kx, tne, tse -> r (no seals) = 20
+# the paper's wall times for 1000 applications on 750 x 994 x 246 (Sec. 6, Table 1)
+PAPER10_CONTEXT = {"cs2_s": 0.0823, "a100_raja_s": 16.8378, "a100_cuda_s": 14.6573}
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_11274_amd", "csrc", "tpfa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tpfa_jacobian_fp64_512x512x256_traffic.txt")
 
@@ -93,10 +98,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="fp64,fp32,res,batched,adjoint,cpu")
+    ap.add_argument("--sections", default="fp64,fp32,res,batched,adjoint,paper10,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--paper10-steps", type=int, default=1000,
+                    help="applications per mesh in the paper10 section (the paper uses 1000)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -326,6 +333,39 @@ def main():
         log(f"adjoint: {out['adjoint']}")
         del ka, sa, dpa, wa, ra, gpa, gma
         torch.cuda.empty_cache()
+
+    # ------------------------------- the paper's workload: FP32 10-flux residual
+    if "paper10" in sections:
+        K10 = args.paper10_steps
+        rows = []
+        for (nx_, ny_, nz_) in geomodel.PAPER10_SHAPES:
+            t0 = time.time()
+            geo_p = geomodel.paper10(nx_, ny_, nz_)
+            gp_ = geo_p.grid
+            prp = tp.hydrostatic(gp_, geo_p.fluid)
+            kp, dpp = up(geo_p.kx), up(geo_p.noise[0])
+            tn, ts = up(geo_p.extra["tne"]), up(geo_p.extra["tse"])
+            del geo_p
+            rp = torch.empty(gp_.shape, dtype=torch.float32, device=dev)
+            kw = dict(pref=prp, ry=1.0, rz=0.1, out=rp)
+            for _ in range(W):
+                tp.residual10(gp_, fl, kp, dpp, tn, ts, **kw)
+            with Timer(torch) as tm:
+                for _ in range(K10):
+                    tp.residual10(gp_, fl, kp, dpp, tn, ts, **kw)
+            Np = gp_.ncell
+            t = tm.ms / K10
+            rows.append({"grid": [nx_, ny_, nz_], "cells": Np, "ms_per_application": t,
+                         "s_per_1000": t, "cells_per_s": Np / (t / 1e3),
+                         "algorithmic_GBps": BYTES_FP32_R10 * Np / (t / 1e3) / 1e9,
+                         "hbm_frac": BYTES_FP32_R10 * Np / (t / 1e3) / 1e9 / HBM_PEAK_GBS})
+            log(f"paper10 {nx_}x{ny_}x{nz_}: {rows[-1]} (set up {time.time() - t0:.1f} s)")
+            del kp, dpp, tn, ts, rp
+            torch.cuda.empty_cache()
+        out["paper10"] = {"workload": "FP32 10-flux residual (6 TPFA faces + 4 in-plane "
+                                      "diagonal faces), 1000 applications per mesh, no seals",
+                          "applications": K10, "bytes_per_cell": BYTES_FP32_R10,
+                          "meshes": rows, "paper_750x994x246": PAPER10_CONTEXT}
 
     # ------------------------------------------- CPU baseline: the FP64 oracle
     if "cpu" in sections:

@@ -209,3 +209,47 @@ def random_small(seed: int, nx: int, ny: int, nz: int, *, sigma: float = 1.0,
     """Small odd-shaped grids for parity and property tests."""
     return draw(f"small{nx}x{ny}x{nz}s{seed}", Grid(nx, ny, nz, gk=gk), sigma=sigma,
                 seed=seed, ry=ry, rz=rz, seal_prob=seal_prob, noise_seeds=(None,))
+
+
+# The paper's own workloads (Sec. 6, weak-scaling table): Nx x Ny x 246 meshes
+# from 200 x 200 up to the full 750 x 994 fabric, residual only, 10 fluxes per
+# cell, FP32.
+PAPER10_SHAPES = ((200, 200, 246), (400, 400, 246), (600, 600, 246), (750, 600, 246),
+                  (750, 800, 246), (750, 994, 246))
+LN_T_DIAG_MEDIAN = math.log(1e-13)
+
+
+def paper10(nx: int = 750, ny: int = 994, nz: int = 246, seed: int = 8) -> Geomodel:
+    """A 10-flux workload, drawn directly in FP32 (the paper's precision) to keep
+    the 183M-cell case small: ln kx ~ N(ln 1e-13, 1), ky = kx, kz = 0.1 kx, no
+    seals, pressure noise ~ U(-1e5, 1e5) Pa, and the two diagonal
+    transmissibility fields (m^3) ``extra['tne']``, ``extra['tse']`` with
+    ln t ~ N(ln 1e-13, 1) i.i.d. per cell. All arrays are float32."""
+    grid = Grid(nx, ny, nz)
+    s_logk, s_noise, s_tne, s_tse = np.random.SeedSequence(seed).spawn(4)
+    logk = np.random.default_rng(s_logk).standard_normal(grid.shape, dtype=np.float32)
+    logk += np.float32(LN_K_MEDIAN)
+    kx = np.exp(logk)
+    noise = np.random.default_rng(s_noise).random(grid.shape, dtype=np.float32)
+    noise *= np.float32(2 * NOISE_AMP)
+    noise -= np.float32(NOISE_AMP)
+    geo = Geomodel(name=f"paper10_{nx}x{ny}x{nz}", grid=grid, fluid=Fluid(), sigma=1.0,
+                   seed=seed, logk=logk, kx=kx, ry=1.0, rz=0.1,
+                   seal=np.zeros(grid.shape, np.uint8), noise=[noise])
+    for key, s in (("tne", s_tne), ("tse", s_tse)):
+        t = np.random.default_rng(s).standard_normal(grid.shape, dtype=np.float32)
+        t += np.float32(LN_T_DIAG_MEDIAN)
+        geo.extra[key] = np.exp(t)
+    return geo
+
+
+def diagonal_t(grid: Grid, seed: int, zero_prob: float = 0.1) -> tuple:
+    """Diagonal transmissibility fields (tne, tse), float64, for small grids:
+    ln t ~ N(ln 1e-13, 1), with a fraction ``zero_prob`` of faces closed (t = 0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(2):
+        t = np.exp(LN_T_DIAG_MEDIAN + rng.standard_normal(grid.shape))
+        t[rng.random(grid.shape) < zero_prob] = 0.0
+        out.append(t)
+    return tuple(out)

@@ -127,6 +127,18 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                       tpfa_precision_t prec, const void *w, void *grad_p,
                       void *grad_logk, const tpfa_launch_t *launch, void *stream);
 
+/* Residual of the 10-flux stencil: the six faces above plus the four in-plane
+   diagonal faces that the paper's kernel also evaluates (Sec. 3, Algorithm 1
+   applied with four extra neighbours), whose transmissibilities the caller
+   supplies: tne[idx] for the face (i,j)-(i+1,j+1) and tse[idx] for the face
+   (i,j)-(i+1,j-1) (dtype of the precision; entries without that neighbour are
+   ignored). Diagonal faces have no elevation difference and no seal bit (a zero
+   transmissibility closes one). Residual only. */
+int tpfa_residual10(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                    const tpfa_rock_t *rock, const tpfa_state_t *state,
+                    tpfa_precision_t prec, const void *tne, const void *tse, void *r,
+                    const tpfa_launch_t *launch, void *stream);
+
 /* Discrete hydrostatic reference column (double pref[nz], device): pref[0] =
    p_top and pref[k+1] - pref[k] = (rho(pref[k]) + rho(pref[k+1]))/2 * gk * dz,
    i.e. the profile whose vertical potential differences (Eq. 3b) vanish. The

@@ -74,8 +74,13 @@ def _load():
                                        C.c_double, vp, vp]
         lib.oracle_hydrostatic.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid),
                                            C.c_double, vp]
+        lib.oracle_residual10.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, C.c_double,
+                                          C.c_double, vp, vp, vp, vp, vp, vp]
+        lib.oracle_residual10_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                             C.c_double, C.c_double, vp, vp, vp, vp, vp,
+                                             C.c_double, vp]
         for fn in ("oracle_eval", "oracle_rows", "oracle_eval_ld", "oracle_eval_cs",
-                   "oracle_hydrostatic"):
+                   "oracle_hydrostatic", "oracle_residual10", "oracle_residual10_cs"):
             getattr(lib, fn).restype = C.c_int
         _lib = lib
     return _lib
@@ -197,6 +202,38 @@ def evaluate_cs(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None, vp=None, vm=No
     if rc != 0:
         raise ValueError("oracle_eval_cs rejected its arguments")
     return re, im / h
+
+
+def residual10(grid, fluid, kx, p, tne, tse, *, ry=1.0, rz=1.0, seal=None):
+    """Residual of the 10-flux stencil (six TPFA faces plus the four in-plane
+    diagonal faces with given transmissibilities) and its flux scale sum |F|."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx, p = _arr(kx, np.float64, shape), _arr(p, np.float64, shape)
+    tne, tse = _arr(tne, np.float64, shape), _arr(tse, np.float64, shape)
+    seal = _arr(seal, np.uint8, shape)
+    r = np.empty(shape)
+    scale = np.empty((2,) + shape)
+    rc = _load().oracle_residual10(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), float(ry),
+                                   float(rz), _ptr(seal), _ptr(tne), _ptr(tse), _ptr(p), _ptr(r),
+                                   _ptr(scale))
+    if rc != 0:
+        raise ValueError("oracle_residual10 rejected its arguments")
+    return r, scale[0]
+
+
+def residual10_cs(grid, fluid, kx, p, tne, tse, vp, *, ry=1.0, rz=1.0, seal=None, h=1e-20):
+    """Complex-step directional derivative of the 10-flux residual along vp."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx, p = _arr(kx, np.float64, shape), _arr(p, np.float64, shape)
+    tne, tse = _arr(tne, np.float64, shape), _arr(tse, np.float64, shape)
+    vp, seal = _arr(vp, np.float64, shape), _arr(seal, np.uint8, shape)
+    im = np.empty(shape)
+    rc = _load().oracle_residual10_cs(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx),
+                                      float(ry), float(rz), _ptr(seal), _ptr(tne), _ptr(tse),
+                                      _ptr(p), _ptr(vp), float(h), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_residual10_cs rejected its arguments")
+    return im / h
 
 
 def hydrostatic(grid, fluid, p_top: Optional[float] = None) -> np.ndarray:

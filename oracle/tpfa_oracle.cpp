@@ -85,6 +85,8 @@ struct Problem {
   double ry, rz;
   const uint8_t* seal;         // NULL or bit a set: face towards +a neighbour closed
   const int8_t* force;         // NULL or [3][N]: +1 / -1 forces the lower / upper cell upwind
+  const S* tne = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j+1) of each cell
+  const S* tse = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j-1) of each cell
   int64_t ncell() const { return g->nx * g->ny * g->nz; }
 };
 
@@ -109,22 +111,32 @@ double geom_factor(const oracle_grid& g, int axis) {
   return g.dx * g.dy / g.dz;
 }
 
-// Neighbour n of a cell, n = 0..5 -> (-x, +x, -y, +y, -z, +z).
+// Neighbour n of a cell, n = 0..5 -> (-x, +x, -y, +y, -z, +z); with the four
+// in-plane diagonal neighbours of the 10-flux stencil, n = 6..9 -> (-x-y),
+// (+x+y), (+x-y), (-x+y).
 struct Nb {
   bool exists;
   int64_t L;
-  int axis;
-  int side;  // -1 or +1
+  int axis;  // 0, 1, 2; 3 for a diagonal
+  int side;  // -1 or +1 (cardinal); for a diagonal, +1 when the cell is the face's (i, j) end
 };
 
 Nb neighbour(const oracle_grid& g, int64_t i, int64_t j, int64_t k, int n) {
+  static const int dx[4] = {-1, 1, 1, -1}, dy[4] = {-1, 1, -1, 1};
   Nb nb;
-  nb.axis = n / 2;
-  nb.side = (n % 2) ? 1 : -1;
   int64_t ii = i, jj = j, kk = k;
-  if (nb.axis == 0) ii += nb.side;
-  if (nb.axis == 1) jj += nb.side;
-  if (nb.axis == 2) kk += nb.side;
+  if (n < 6) {
+    nb.axis = n / 2;
+    nb.side = (n % 2) ? 1 : -1;
+    if (nb.axis == 0) ii += nb.side;
+    if (nb.axis == 1) jj += nb.side;
+    if (nb.axis == 2) kk += nb.side;
+  } else {
+    nb.axis = 3;
+    ii += dx[n - 6];
+    jj += dy[n - 6];
+    nb.side = dx[n - 6] > 0 ? 1 : -1;  // the cell is the face's left (i) end
+  }
   nb.exists = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
   nb.L = nb.exists ? ii + g.nx * (jj + g.ny * kk) : -1;
   return nb;
@@ -146,17 +158,26 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
   const oracle_grid& g = *pb.g;
   const oracle_fluid& f = *pb.f;
   FluxKL<S> out;
-  const int64_t lo = side > 0 ? K : L;  // lower-index cell of the face
+  const int64_t lo = K < L ? K : L;  // lower-index cell of the face
 
-  // transmissibility (harmonic two-point form, closed if sealed)
-  out.kK = perm(pb, axis, K);
-  out.kL = perm(pb, axis, L);
-  const bool sealed = pb.seal && ((pb.seal[lo] >> axis) & 1u);
-  const S ksum = out.kK + out.kL;
-  if (sealed || real_part(ksum) == 0.0)
-    out.T = S(0);
-  else
-    out.T = S(geom_factor(g, axis)) * ((S(2) * (out.kK * out.kL)) / ksum);
+  if (axis == 3) {
+    // in-plane diagonal face: transmissibility given, stored on its left (i) end
+    out.kK = out.kL = S(0);
+    const int64_t left = side > 0 ? K : L;
+    const int64_t right = side > 0 ? L : K;
+    // the right end lies 1 + nx (face towards +y) or 1 - nx (towards -y) further in index
+    out.T = (right - left == 1 + g.nx) ? pb.tne[left] : pb.tse[left];
+  } else {
+    // transmissibility (harmonic two-point form, closed if sealed)
+    out.kK = perm(pb, axis, K);
+    out.kL = perm(pb, axis, L);
+    const bool sealed = pb.seal && ((pb.seal[lo] >> axis) & 1u);
+    const S ksum = out.kK + out.kL;
+    if (sealed || real_part(ksum) == 0.0)
+      out.T = S(0);
+    else
+      out.T = S(geom_factor(g, axis)) * ((S(2) * (out.kK * out.kL)) / ksum);
+  }
 
   // densities in K and L (Eq. 5), their average and pressure derivatives
   const S pK = pb.p[K], pL = pb.p[L];
@@ -166,6 +187,7 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
 
   // elevation difference zeta_L - zeta_K along +k
   const double dzeta = axis == 2 ? side * g.dz : 0.0;
+  const int force_axis = axis < 3 ? axis : 0;
 
   // potential difference (Eq. 3b, outflow orientation)
   out.dPhi = (pK - pL) + (rho_avg * S(g.gk)) * S(dzeta);
@@ -174,7 +196,7 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
 
   // single-point upwinding (Eq. 4); a tie goes to the lower index
   bool upK;
-  const int8_t forced = pb.force ? pb.force[(int64_t)axis * pb.ncell() + lo] : 0;
+  const int8_t forced = (pb.force && axis < 3) ? pb.force[(int64_t)force_axis * pb.ncell() + lo] : 0;
   if (forced != 0) {
     upK = (forced > 0) == (K == lo);
   } else {
@@ -228,12 +250,13 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
     for (int64_t j = 0; j < g.ny; ++j)
       for (int64_t i = 0; i < g.nx; ++i) {
         const int64_t K = i + g.nx * (j + g.ny * k);
-        for (int n = 0; n < 6; ++n) {
+        const int nn = pb.tne ? 10 : 6;
+        for (int n = 0; n < nn; ++n) {
           const Nb nb = neighbour(g, i, j, k, n);
           if (!nb.exists) continue;
           const FluxKL<S> fl = flux(pb, K, nb.L, nb.axis, nb.side);
           if (r) r[K] += fl.F;
-          if (J) {
+          if (J && n < 6) {
             J[K] += fl.dF_dpK;
             J[(1 + n) * N + K] = fl.dF_dpL;
           }
@@ -254,7 +277,7 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
             o.scale[K] += std::abs(real_part(fl.F));
             o.scale[N + K] += std::abs(real_part(fl.dF_dpK));
           }
-          if (o.dphi && nb.side > 0) o.dphi[nb.axis * N + K] = real_part(fl.dPhi);
+          if (o.dphi && n < 6 && nb.side > 0) o.dphi[nb.axis * N + K] = real_part(fl.dPhi);
         }
       }
 }
@@ -337,6 +360,57 @@ int oracle_rows(const oracle_grid* g, const oracle_fluid* f, const double* kx,
     if (cells[q] < 0 || cells[q] >= N) return -1;
   Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
   rows(pb, cells, n, r, J, scale, dphi);
+  return 0;
+}
+
+// Residual of the 10-flux stencil: the six TPFA faces plus the four in-plane
+// diagonal faces, whose transmissibilities are given per cell (tne: face with
+// (i+1, j+1), tse: face with (i+1, j-1); entries without that neighbour are
+// ignored). Optionally the flux scale sum |F| per cell.
+int oracle_residual10(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                      double ry, double rz, const uint8_t* seal, const double* tne,
+                      const double* tse, const double* p, double* r, double* scale) {
+  if (!valid(g, f, p, kx) || !tne || !tse || !r) return -1;
+  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.tne = tne;
+  pb.tse = tse;
+  Outputs o;
+  o.r = r;
+  o.scale = scale;
+  assemble(pb, o);
+  return 0;
+}
+
+// Complex-step residual of the 10-flux stencil along a pressure direction vp.
+int oracle_residual10_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                         double ry, double rz, const uint8_t* seal, const double* tne,
+                         const double* tse, const double* p, const double* vp, double h,
+                         double* r_im) {
+  if (!valid(g, f, p, kx) || !tne || !tse || !vp || !r_im) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  cplx* pc = new cplx[N];
+  cplx* kc = new cplx[N];
+  cplx* tn = new cplx[N];
+  cplx* ts = new cplx[N];
+  cplx* rc = new cplx[N];
+  for (int64_t c = 0; c < N; ++c) {
+    pc[c] = cplx(p[c], h * vp[c]);
+    kc[c] = cplx(kx[c], 0.0);
+    tn[c] = cplx(tne[c], 0.0);
+    ts[c] = cplx(tse[c], 0.0);
+  }
+  Problem<cplx> pb{g, f, pc, kc, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.tne = tn;
+  pb.tse = ts;
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t c = 0; c < N; ++c) r_im[c] = rc[c].imag();
+  delete[] pc;
+  delete[] kc;
+  delete[] tn;
+  delete[] ts;
+  delete[] rc;
   return 0;
 }
 

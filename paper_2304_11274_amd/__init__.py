@@ -5,7 +5,7 @@ package only marshals torch tensors into its C ABI (include/tpfa.h).
 """
 from ._lib import LIB_PATH, TpfaError, load  # noqa: F401
 from .api import (Ensemble, TPFAResidual, hydrostatic, jacobian, offset_pressure,  # noqa: F401
-                  residual, residual_vjp, tile_shapes)
+                  residual, residual10, residual_vjp, tile_shapes)
 
 __all__ = ["Ensemble", "TPFAResidual", "hydrostatic", "jacobian", "offset_pressure",
-           "residual", "residual_vjp", "tile_shapes", "load", "TpfaError", "LIB_PATH"]
+           "residual", "residual10", "residual_vjp", "tile_shapes", "load", "TpfaError", "LIB_PATH"]

@@ -67,6 +67,8 @@ SIGNATURES = {
                                 vp]),
     "tpfa_residual_vjp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
                                     P(Launch), vp]),
+    "tpfa_residual10": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
+                                  P(Launch), vp]),
     "tpfa_hydrostatic": (C.c_int, [P(Grid), P(Fluid), C.c_double, vp, vp]),
     "tpfa_offset_pressure": (C.c_int, [P(Grid), vp, vp, vp, vp]),
     "tpfa_batch_create": (C.c_int, [P(Model), C.c_int, C.c_int, C.c_int, P(vp), vp]),

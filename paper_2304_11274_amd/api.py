@@ -144,6 +144,24 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     return gp, gm
 
 
+def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+               tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+    """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
+    faces with caller-supplied transmissibilities tne, tse)."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    _need(tne, "tne", dt, n, dev)
+    _need(tse, "tse", dt, n, dev)
+    r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+    _need(r, "out", dt, n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_residual10(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                                C.byref(_rock(kx, seal, ry, rz)),
+                                C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
+                                _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap),
+                                _stream(dev)), lib)
+    return r
+
+
 def hydrostatic(grid, fluid, p_top: Optional[float] = None, device=None) -> torch.Tensor:
     """Discrete hydrostatic reference column pref[nz] (float64, on the GPU)."""
     dev = torch.device(device) if device is not None else torch.device("cuda",

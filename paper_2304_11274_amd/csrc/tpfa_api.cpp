@@ -90,10 +90,12 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
 int default_tile(const tpfa_grid_t &g, tpfa::Mode mode) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
-  return mode == tpfa::MODE_VJP ? 0 : 3;
+  return mode == tpfa::MODE_VJP || mode == tpfa::MODE_RES10 ? 0 : 3;
 }
 
-int default_kz(tpfa::Mode mode) { return mode == tpfa::MODE_RESIDUAL ? 32 : 16; }
+int default_kz(tpfa::Mode mode) {
+  return mode == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10 ? 32 : 16;
+}
 
 int hip_fail(hipError_t e, const char *what) {
   return fail(TPFA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -174,6 +176,8 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   b.w = a.w;
   b.gp = a.gp;
   b.gm = a.gm;
+  b.tne = a.tne;
+  b.tse = a.tse;
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
   const hipError_t e =
@@ -235,6 +239,26 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
     a.gp = grad_p;
     a.gm = grad_logk;
     return run(tpfa::MODE_VJP, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_residual10(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
+                    const tpfa_state_t *state, tpfa_precision_t prec, const void *tne,
+                    const void *tse, void *r, const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!tne || !tse) return fail(TPFA_ERR_NULL, "tne and tse are required");
+    if (!r) return fail(TPFA_ERR_NULL, "r is NULL");
+    tpfa::Args a{};
+    a.r = r;
+    a.tne = tne;
+    a.tse = tse;
+    return run(tpfa::MODE_RES10, grid, fluid, rock, state, prec, launch, a, stream);
   } catch (const std::exception &e) {
     return fail(TPFA_ERR_HIP, e.what());
   } catch (...) {

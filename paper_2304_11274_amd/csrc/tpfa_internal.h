@@ -9,7 +9,7 @@
 
 namespace tpfa {
 
-enum Mode : int { MODE_RESIDUAL = 0, MODE_JACOBIAN = 1, MODE_VJP = 2 };
+enum Mode : int { MODE_RESIDUAL = 0, MODE_JACOBIAN = 1, MODE_VJP = 2, MODE_RES10 = 3 };
 
 // Tile table. A workgroup owns a TX x TY column block of one model and marches
 // it through a chunk of z planes; each thread stages ceil(2 (TX + TY) / threads)
@@ -50,6 +50,8 @@ struct Args {
   const void *kx;
   const uint8_t *seal;
   const void *w;
+  const void *tne;   // 10-flux stencil: diagonal transmissibilities
+  const void *tse;
   void *r;
   void *J;
   void *gp;

@@ -53,7 +53,8 @@ struct Cell {
   S p;         // stored pressure value (absolute for FP64, offset from pref for FP32)
   S k;         // kx
   S w;         // cotangent (vector-Jacobian product only)
-  uint32_t s;  // seal bits
+  S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
+  uint32_t s;  // seal bits; bit 3 marks a cell outside the domain (10-flux stencil)
 };
 
 // Density-derived quantities of a cell, evaluated once per cell.
@@ -219,7 +220,8 @@ __device__ __forceinline__ void st_nt(T *p, T v) {
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
-  return 2 * HW * ((int)sizeof(S) * (MODE == MODE_VJP ? 4 : 3) + 1);
+  constexpr int arrays = 3 + (MODE == MODE_VJP ? 1 : 0) + (MODE == MODE_RES10 ? 2 : 0);
+  return 2 * HW * ((int)sizeof(S) * arrays + 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -238,19 +240,71 @@ __device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
   return reinterpret_cast<T *>(reinterpret_cast<char *>(base + elems) + boff);
 }
 
+// Accumulates and stores one cell's outputs from its six faces (neighbour
+// order -x, +x, -y, +y, -z, +z; odd faces have the cell as their lower cell).
+template <class S, int MODE>
+__device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz, uint32_t cb,
+                                     const Cell<S> &c0, const Face<S> (&f)[6], const S (&wn)[6],
+                                     const S (&fd)[4]) {
+  // derivatives are formed and stored by the Jacobian and adjoint modes only
+  constexpr bool DERIV = MODE == MODE_JACOBIAN || MODE == MODE_VJP;
+  const size_t ko = (size_t)k * plane;
+  if constexpr (MODE == MODE_VJP) {
+    // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
+    double gp = 0.0, gm = 0.0;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      const double d = (double)c0.w - (double)wn[n];
+      if (n & 1) {  // own cell is Lo
+        gp = fma(d, (double)f[n].dLo, gp);
+        gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
+      } else {      // own cell is Up
+        gp = fma(-d, (double)f[n].dUp, gp);
+        gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
+      }
+    }
+    if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
+    if (a.gm) st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
+  } else {
+    // residual in the neighbour order, accumulated in FP64
+    double r = 0.0;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
+    if constexpr (MODE == MODE_RES10) {
+      // diagonals -x-y, +x+y, +x-y, -x+y: the cell is the upper index of the
+      // first and third, the lower of the second and fourth
+#pragma unroll
+      for (int n = 0; n < 4; ++n) r = (n & 1) ? r + (double)fd[n] : r - (double)fd[n];
+    }
+    if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
+    if constexpr (DERIV) {
+      S *J = static_cast<S *>(a.J);
+      const size_t nc = (size_t)nz * plane;
+      S dg = S(0);
+#pragma unroll
+      for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
+      st_nt(at_w(J, ko, cb), dg);
+#pragma unroll
+      for (int n = 0; n < 6; ++n)
+        st_nt(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
+    }
+  }
+}
+
 template <class S, int MODE, int TX, int TY>
 struct Tile {
   static constexpr int W = TX + 2, H = TY + 2, HW = W * H;
   static constexpr bool VJP = MODE == MODE_VJP;
-  static constexpr bool DERIV = MODE != MODE_RESIDUAL;
+  static constexpr bool DERIV = MODE == MODE_JACOBIAN || MODE == MODE_VJP;
   static constexpr bool FP32 = sizeof(S) == 4;
 
+  static constexpr bool R10 = MODE == MODE_RES10;
   static constexpr int NT = TX * TY;          // threads
-  static constexpr int NH = 2 * (TX + TY);    // halo ring cells (no corners)
+  static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
   static constexpr int HC = (NH + NT - 1) / NT;  // halo cells staged per thread
 
   const Args &a;
-  S *s_p, *s_k, *s_l, *s_w;
+  S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
@@ -267,7 +321,9 @@ struct Tile {
     s_k = s_p + 2 * HW;
     s_l = s_k + 2 * HW;
     s_w = s_l + 2 * HW;
-    s_s = reinterpret_cast<uint8_t *>(s_w + (VJP ? 2 * HW : 0));
+    s_tn = s_w + (VJP ? 2 * HW : 0);
+    s_ts = s_tn + (R10 ? 2 * HW : 0);
+    s_s = reinterpret_cast<uint8_t *>(s_ts + (R10 ? 2 * HW : 0));
     const int nx = a.nx, ny = a.ny;
     nz = a.nz;
     kb = kb_;
@@ -298,10 +354,16 @@ struct Tile {
         hi = bx * TX - 1;
         hj = by * TY + h - 2 * TX;
         l = (h - 2 * TX + 1) * W;
-      } else if (h < NH) {
+      } else if (h < 2 * TX + 2 * TY) {
         hi = bx * TX + TX;
         hj = by * TY + h - 2 * TX - TY;
         l = (h - 2 * TX - TY + 1) * W + TX + 1;
+      } else if (h < NH) {  // corners (10-flux stencil)
+        const int c = h - 2 * TX - 2 * TY;
+        const int cx = c & 1, cy = c >> 1;
+        hi = cx ? bx * TX + TX : bx * TX - 1;
+        hj = cy ? by * TY + TY : by * TY - 1;
+        l = (cy ? TY + 1 : 0) * W + (cx ? TX + 1 : 0);
       }
       hl[q] = l;
       hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
@@ -321,6 +383,11 @@ struct Tile {
     c.k = ok ? kx : S(0);
     c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
     if (VJP) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+    if (R10) {
+      c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
+      c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
+      c.s = (c.s & 7u) | (ok ? 0u : 8u);
+    }
   }
   __device__ __forceinline__ void load(Cell<S> &c, int k) const { load_at(c, k, own, cb, cs); }
   __device__ __forceinline__ void load_halo(Cell<S> (&h)[HC], int k) const {
@@ -368,6 +435,10 @@ struct Tile {
     s_l[b + ol] = d0.lam;
     s_s[b + ol] = (uint8_t)c0.s;
     if (VJP) s_w[b + ol] = c0.w;
+    if (R10) {
+      s_tn[b + ol] = c0.tn;
+      s_ts[b + ol] = c0.ts;
+    }
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
       if (hl[q] < 0) continue;
@@ -378,6 +449,10 @@ struct Tile {
       s_l[l] = dh.lam;
       s_s[l] = (uint8_t)h0[q].s;
       if (VJP) s_w[l] = h0[q].w;
+      if (R10) {
+        s_tn[l] = h0[q].tn;
+        s_ts[l] = h0[q].ts;
+      }
     }
     __syncthreads();
 
@@ -413,44 +488,32 @@ struct Tile {
     f[5] = zp;
     wn[5] = c1.w;
 
-    if (!own) return;
-    const size_t ko = (size_t)k * plane;
-    if constexpr (MODE == MODE_VJP) {
-      // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
-      double gp = 0.0, gm = 0.0;
+    // the four in-plane diagonal faces of the 10-flux stencil: transmissibility
+    // given (tne on the face's left end for (i,j)-(i+1,j+1), tse for
+    // (i,j)-(i+1,j-1)), closed when either cell lies outside the domain
+    S fd[4] = {};
+    if constexpr (R10) {
+      const int dsl[4] = {ol - W - 1, ol + W + 1, ol - W + 1, ol + W - 1};
 #pragma unroll
-      for (int n = 0; n < 6; ++n) {
-        const double d = (double)c0.w - (double)wn[n];
-        if (n & 1) {  // own cell is Lo
-          gp = fma(d, (double)f[n].dLo, gp);
-          gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
-        } else {      // own cell is Up
-          gp = fma(-d, (double)f[n].dUp, gp);
-          gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
-        }
-      }
-      if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
-      if (a.gm) st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
-    } else {
-      // residual in the neighbour order, accumulated in FP64
-      double r = 0.0;
-#pragma unroll
-      for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
-      if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
-      if constexpr (DERIV) {
-        S *J = static_cast<S *>(a.J);
-        const size_t nc = (size_t)nz * plane;
-        S dg = S(0);
-#pragma unroll
-        for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
-        st_nt(at_w(J, ko, cb), dg);
-#pragma unroll
-        for (int n = 0; n < 6; ++n)
-          st_nt(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
+      for (int n = 0; n < 4; ++n) {
+        const int q = b + dsl[n];
+        const S pn = s_p[q], ln = s_l[q];
+        const bool open = ((c0.s | (uint32_t)s_s[q]) & 8u) == 0u;
+        // face transmissibility: stored on the face's left (i) end
+        const S T0 = n == 0 ? s_tn[q] : n == 1 ? c0.tn : n == 2 ? c0.ts : s_ts[q];
+        const S T = open ? T0 : S(0);
+        // the lower-index cell is the neighbour for n = 0, 2 and the own cell for 1, 3
+        const S pLo = (n & 1) ? c0.p : pn, pUp = (n & 1) ? pn : c0.p;
+        const S lLo = (n & 1) ? d0.lam : ln, lUp = (n & 1) ? ln : d0.lam;
+        const S dphi = pLo - pUp;
+        fd[n] = (T * (dphi >= S(0) ? lLo : lUp)) * dphi;
       }
     }
+    if (!own) return;
+    emit<S, MODE>(a, k, plane, nz, cb, c0, f, wn, fd);
   }
 };
+
 
 template <class S, int MODE, int TX, int TY>
 __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
@@ -497,9 +560,9 @@ __device__ __forceinline__ void decode_tile(const Args &a, int64_t b, int &bx, i
 template <class S, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY)
     march_kernel(const Args a) {
-  __shared__ __attribute__((aligned(16))) char smem[tile_lds_bytes<S, MODE, TX, TY>()];
   int bx, by, kb;
   decode_tile(a, blockIdx.x, bx, by, kb);
+  __shared__ __attribute__((aligned(16))) char smem[tile_lds_bytes<S, MODE, TX, TY>()];
   march_tile<S, MODE, TX, TY>(a, bx, by, kb, smem);
 }
 
@@ -637,12 +700,14 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
     switch (mode) {
       case MODE_RESIDUAL: return launch_t<double, MODE_RESIDUAL>(tile, a, st);
       case MODE_JACOBIAN: return launch_t<double, MODE_JACOBIAN>(tile, a, st);
+      case MODE_RES10: return launch_t<double, MODE_RES10>(tile, a, st);
       default: return launch_t<double, MODE_VJP>(tile, a, st);
     }
   }
   switch (mode) {
     case MODE_RESIDUAL: return launch_t<float, MODE_RESIDUAL>(tile, a, st);
     case MODE_JACOBIAN: return launch_t<float, MODE_JACOBIAN>(tile, a, st);
+    case MODE_RES10: return launch_t<float, MODE_RES10>(tile, a, st);
     default: return launch_t<float, MODE_VJP>(tile, a, st);
   }
 }

@@ -262,3 +262,53 @@ def compare_vjp(orc, grid, fluid, kx, p, w, gp_gpu, gm_gpu, *, tol, tau, ry, rz,
         rep["n_flipped_cells"] = int(bad.sum())
         rep["max_err"] = float(np.where(bad, err2, err).max())
     return rep
+
+
+# ---------------------------------------------------------------------------
+# 10-flux stencil. A cell whose residual differs from the oracle beyond tol
+# must touch an upwind tie (cardinal or diagonal face with |dPhi| <= tau);
+# flipping one tie face changes the residual by at most T |lam_K - lam_L| tau,
+# bounded here by T_max lam_max tau per face.
+# ---------------------------------------------------------------------------
+
+def diagonal_ties(p: np.ndarray, tau) -> np.ndarray:
+    """Cells touching an in-plane diagonal face with |p_K - p_L| <= tau."""
+    t = np.zeros(p.shape, bool)
+    ne = np.abs(p[:, :-1, :-1] - p[:, 1:, 1:]) <= tau     # (i,j)-(i+1,j+1)
+    se = np.abs(p[:, 1:, :-1] - p[:, :-1, 1:]) <= tau     # (i,j)-(i+1,j-1)
+    t[:, :-1, :-1] |= ne
+    t[:, 1:, 1:] |= ne
+    t[:, 1:, :-1] |= se
+    t[:, :-1, 1:] |= se
+    return t
+
+
+def compare_res10(orc, grid, fluid, kx, p, tne, tse, r_gpu, *, tol, tau, ry, rz, seal,
+                  mask=None):
+    """Residual of the 10-flux stencil against the oracle, cell by cell (only
+    where ``mask`` is set, if given). Returns a report dict."""
+    r_ref, scale = orc.residual10(grid, fluid, kx, p, tne, tse, ry=ry, rz=rz, seal=seal)
+    r_gpu = np.asarray(r_gpu, np.float64).reshape(r_ref.shape)
+    err = rel_err(r_gpu, r_ref, scale)
+    if mask is not None:
+        err = np.where(mask, err, 0.0)
+    bad = err > tol
+    rep = {"max_err": float(err.max()), "n_cells": int(err.size if mask is None else mask.sum()),
+           "n_tie_cells": 0}
+    if bad.any():
+        dphi = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, want=("dphi",))["dphi"]
+        touch = cells_touching(tie_faces(dphi, tau)) | diagonal_ties(p, tau)
+        assert not (bad & ~touch).any(), (
+            f"{int((bad & ~touch).sum())} cells differ by up to {err[bad & ~touch].max():.3e} "
+            "away from any upwind tie")
+        lam_max = fluid.rho0 * np.exp(fluid.cf * (np.max(p) - fluid.p0)) / fluid.mu
+        a = max(grid.dy * grid.dz / grid.dx, grid.dx * grid.dz / grid.dy,
+                grid.dx * grid.dy / grid.dz)
+        t_max = max(float(np.max(kx)) * a * max(1.0, ry, rz), float(np.max(tne)),
+                    float(np.max(tse)))
+        bound = tol * scale + 10 * t_max * lam_max * tau
+        diff = np.abs(r_gpu - r_ref)
+        assert not (bad & (diff > bound)).any(), "tie cells beyond the flip bound"
+        rep["n_tie_cells"] = int(bad.sum())
+        rep["max_err"] = float(np.where(bad, 0.0, err).max())
+    return rep

@@ -186,3 +186,15 @@ def test_python_binding_rejects_host_tensors():
         tp.residual(g, geomodel.Fluid(), t, t)
     with pytest.raises(TypeError):
         tp.residual(g, geomodel.Fluid(), t, t.to(torch.int32))
+
+
+def test_residual10_validation(lib):
+    g, f, rk, st = good()
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st), L.TPFA_FP64)
+    assert lib.tpfa_residual10(*args, None, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual10(*args, DUMMY, None, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual10(*args, DUMMY, DUMMY, None, None, None) == L.TPFA_ERR_NULL
+    bad = L.Launch(99, 0, 0)
+    assert lib.tpfa_residual10(*args, DUMMY, DUMMY, DUMMY, C.byref(bad), None) == L.TPFA_ERR_TILE
+    g.nx = 0
+    assert lib.tpfa_residual10(*args, DUMMY, DUMMY, DUMMY, None, None) == L.TPFA_ERR_SHAPE
