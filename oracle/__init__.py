@@ -79,8 +79,15 @@ def _load():
         lib.oracle_residual10_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                              C.c_double, C.c_double, vp, vp, vp, vp, vp,
                                              C.c_double, vp]
+        lib.oracle_eval_be.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, C.c_double,
+                                       C.c_double, vp, vp, vp, vp, C.c_double, C.c_double,
+                                       vp, vp, vp, vp, vp]
+        lib.oracle_eval_be_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                          C.c_double, C.c_double, vp, vp, vp, vp, C.c_double,
+                                          C.c_double, vp, C.c_double, vp]
         for fn in ("oracle_eval", "oracle_rows", "oracle_eval_ld", "oracle_eval_cs",
-                   "oracle_hydrostatic", "oracle_residual10", "oracle_residual10_cs"):
+                   "oracle_hydrostatic", "oracle_residual10", "oracle_residual10_cs",
+                   "oracle_eval_be", "oracle_eval_be_cs"):
             getattr(lib, fn).restype = C.c_int
         _lib = lib
     return _lib
@@ -233,6 +240,43 @@ def residual10_cs(grid, fluid, kx, p, tne, tse, vp, *, ry=1.0, rz=1.0, seal=None
                                       _ptr(p), _ptr(vp), float(h), _ptr(im))
     if rc != 0:
         raise ValueError("oracle_residual10_cs rejected its arguments")
+    return im / h
+
+
+def evaluate_be(grid, fluid, kx, p, phi, p_prev, dt, cr, *, ry=1.0, rz=1.0, seal=None,
+                v=None, want=("r", "J")) -> dict:
+    """Full backward-Euler residual of Eq. (2) (accumulation + flux sum) and any
+    of: J [7, ...] (with the accumulation derivative on the diagonal), jv = J v
+    (needs v), scale [2, ...] (sum of |terms| of r and of the diagonal)."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx, p = _arr(kx, np.float64, shape), _arr(p, np.float64, shape)
+    phi, p_prev = _arr(phi, np.float64, shape), _arr(p_prev, np.float64, shape)
+    seal, v = _arr(seal, np.uint8, shape), _arr(v, np.float64, shape)
+    bufs = {}
+    for key, sh in (("r", shape), ("J", (7,) + shape), ("jv", shape), ("scale", (2,) + shape)):
+        bufs[key] = np.empty(sh, np.float64) if key in want else None
+    rc = _load().oracle_eval_be(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), float(ry),
+                                float(rz), _ptr(seal), _ptr(p), _ptr(phi), _ptr(p_prev),
+                                float(dt), float(cr), _ptr(v), _ptr(bufs["r"]),
+                                _ptr(bufs["J"]), _ptr(bufs["jv"]), _ptr(bufs["scale"]))
+    if rc != 0:
+        raise ValueError("oracle_eval_be rejected its arguments")
+    return {k: bufs[k] for k in want}
+
+
+def evaluate_be_cs(grid, fluid, kx, p, phi, p_prev, dt, cr, vp, *, ry=1.0, rz=1.0, seal=None,
+                   h=1e-20) -> np.ndarray:
+    """Complex-step J vp of the full backward-Euler residual."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    kx, p = _arr(kx, np.float64, shape), _arr(p, np.float64, shape)
+    phi, p_prev = _arr(phi, np.float64, shape), _arr(p_prev, np.float64, shape)
+    seal, vp = _arr(seal, np.uint8, shape), _arr(vp, np.float64, shape)
+    im = np.empty(shape)
+    rc = _load().oracle_eval_be_cs(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), float(ry),
+                                   float(rz), _ptr(seal), _ptr(p), _ptr(phi), _ptr(p_prev),
+                                   float(dt), float(cr), _ptr(vp), float(h), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_eval_be_cs rejected its arguments")
     return im / h
 
 

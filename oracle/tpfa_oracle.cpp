@@ -33,7 +33,13 @@
 //  * Ties dPhi_KL = 0: the lower linear index is upwind, so that both sides of
 //    a face make the same choice (the flux is 0 either way).
 //  * Domain boundary: no-flow; boundary cells simply have fewer neighbours.
-//  * The accumulation term of Eq. (2) is excluded, as in the paper.
+//  * The accumulation term of Eq. (2) is excluded from the flux residual, as
+//    in the paper. The full backward-Euler residual (oracle_eval_be) adds it:
+//      r_K = V_K (phi(p_K) rho(p_K) - phi(pn_K) rho(pn_K)) / dt + sum_L F_KL
+//    with V_K = dx dy dz, pn the pressure of the previous time level, and the
+//    porosity linear in pressure (the paper says porosity depends linearly on
+//    p): phi(p) = phi_ref (1 + c_r (p - p_ref)), phi_ref given per cell, c_r
+//    the rock compressibility, p_ref the fluid's reference pressure.
 //
 // Jacobian: the 7-point derivative of r with respect to p, stored as seven
 // planes [diag, -x, +x, -y, +y, -z, +z]; plane 1+n holds dr_K/dp_L for the
@@ -87,6 +93,9 @@ struct Problem {
   const int8_t* force;         // NULL or [3][N]: +1 / -1 forces the lower / upper cell upwind
   const S* tne = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j+1) of each cell
   const S* tse = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j-1) of each cell
+  const S* phi = nullptr;      // NULL or phi_ref per cell: adds the accumulation term of Eq. (2)
+  const S* p_prev = nullptr;   // pressure of the previous time level (with phi)
+  double dt = 0.0, cr = 0.0;   // time step (s) and rock compressibility (1/Pa) (with phi)
   int64_t ncell() const { return g->nx * g->ny * g->nz; }
 };
 
@@ -214,9 +223,25 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
   return out;
 }
 
+// phi(p) rho(p): fluid mass per unit bulk volume, the accumulated quantity of Eq. (2)
+template <class S>
+S mass_density(const Problem<S>& pb, int64_t c, const S& p) {
+  const S phi = pb.phi[c] * (S(1) + S(pb.cr) * (p - S(pb.f->p_ref)));
+  return phi * density(p, *pb.f);
+}
+// d/dp of phi(p) rho(p) = phi_ref c_r rho + phi(p) c_f rho
+template <class S>
+S mass_density_dp(const Problem<S>& pb, int64_t c, const S& p) {
+  const S rho = density(p, *pb.f);
+  const S phi = pb.phi[c] * (S(1) + S(pb.cr) * (p - S(pb.f->p_ref)));
+  return (pb.phi[c] * S(pb.cr)) * rho + phi * (S(pb.f->cf) * rho);
+}
+
 struct Outputs {
   void* r = nullptr;       // [N]
   void* J = nullptr;       // [7][N]
+  const void* v = nullptr; // [N] direction of the Jacobian-vector product
+  void* jv = nullptr;      // [N] J v
   const double* w = nullptr;
   void* grad_p = nullptr;  // [N]
   void* grad_m = nullptr;  // [N] gradient with respect to ln kx
@@ -234,8 +259,11 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
   S* gm = static_cast<S*>(o.grad_m);
 
   // r := 0 (Algorithm 1), and the other accumulators
+  S* jv = static_cast<S*>(o.jv);
+  const S* v = static_cast<const S*>(o.v);
   for (int64_t c = 0; c < N; ++c) {
     if (r) r[c] = S(0);
+    if (jv) jv[c] = S(0);
     if (J)
       for (int e = 0; e < 7; ++e) J[e * N + c] = S(0);
     if (gp) gp[c] = S(0);
@@ -251,6 +279,20 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
       for (int64_t i = 0; i < g.nx; ++i) {
         const int64_t K = i + g.nx * (j + g.ny * k);
         const int nn = pb.tne ? 10 : 6;
+        if (pb.phi) {
+          // accumulation term of Eq. (2): V_K (phi rho - phi_n rho_n) / dt
+          const double vdt = (g.dx * g.dy * g.dz) / pb.dt;
+          const S m1 = mass_density(pb, K, pb.p[K]);
+          const S m0 = mass_density(pb, K, pb.p_prev[K]);
+          const S dm = mass_density_dp(pb, K, pb.p[K]);
+          if (r) r[K] += S(vdt) * (m1 - m0);
+          if (J) J[K] += S(vdt) * dm;
+          if (jv) jv[K] += (S(vdt) * dm) * v[K];
+          if (o.scale) {
+            o.scale[K] += vdt * (std::abs(real_part(m1)) + std::abs(real_part(m0)));
+            o.scale[N + K] += vdt * std::abs(real_part(dm));
+          }
+        }
         for (int n = 0; n < nn; ++n) {
           const Nb nb = neighbour(g, i, j, k, n);
           if (!nb.exists) continue;
@@ -260,6 +302,7 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
             J[K] += fl.dF_dpK;
             J[(1 + n) * N + K] = fl.dF_dpL;
           }
+          if (jv) jv[K] += fl.dF_dpK * v[K] + fl.dF_dpL * v[nb.L];
           if (o.w) {
             const S wK = S(o.w[K]);
             if (gp) {
@@ -360,6 +403,66 @@ int oracle_rows(const oracle_grid* g, const oracle_fluid* f, const double* kx,
     if (cells[q] < 0 || cells[q] >= N) return -1;
   Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
   rows(pb, cells, n, r, J, scale, dphi);
+  return 0;
+}
+
+// Full backward-Euler residual of Eq. (2): accumulation term plus the flux
+// sum, with phi_ref, p_prev, dt, cr as in the header. r, J, jv (= J v, needs
+// v) and scale ([2][N]: sum of |terms| of r and of the diagonal) are optional.
+int oracle_eval_be(const oracle_grid* g, const oracle_fluid* f, const double* kx, double ry,
+                   double rz, const uint8_t* seal, const double* p, const double* phi,
+                   const double* p_prev, double dt, double cr, const double* v, double* r,
+                   double* J, double* jv, double* scale) {
+  if (!valid(g, f, p, kx) || !phi || !p_prev || !(dt > 0.0)) return -1;
+  if (jv && !v) return -1;
+  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.phi = phi;
+  pb.p_prev = p_prev;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = r;
+  o.J = J;
+  o.v = v;
+  o.jv = jv;
+  o.scale = scale;
+  assemble(pb, o);
+  return 0;
+}
+
+// Complex-step directional derivative of the full backward-Euler residual
+// along vp: r_im = Im r(p + i h vp), so r_im / h = J vp to rounding.
+int oracle_eval_be_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                      double ry, double rz, const uint8_t* seal, const double* p,
+                      const double* phi, const double* p_prev, double dt, double cr,
+                      const double* vp, double h, double* r_im) {
+  if (!valid(g, f, p, kx) || !phi || !p_prev || !vp || !r_im || !(dt > 0.0)) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  cplx* pc = new cplx[N];
+  cplx* kc = new cplx[N];
+  cplx* fc = new cplx[N];
+  cplx* qc = new cplx[N];
+  cplx* rc = new cplx[N];
+  for (int64_t c = 0; c < N; ++c) {
+    pc[c] = cplx(p[c], h * vp[c]);
+    kc[c] = cplx(kx[c], 0.0);
+    fc[c] = cplx(phi[c], 0.0);
+    qc[c] = cplx(p_prev[c], 0.0);
+  }
+  Problem<cplx> pb{g, f, pc, kc, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.phi = fc;
+  pb.p_prev = qc;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t c = 0; c < N; ++c) r_im[c] = rc[c].imag();
+  delete[] pc;
+  delete[] kc;
+  delete[] fc;
+  delete[] qc;
+  delete[] rc;
   return 0;
 }
 

@@ -54,7 +54,7 @@ struct Cell {
   S k;         // kx
   S w;         // cotangent (vector-Jacobian product only)
   S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
-  uint32_t s;  // seal bits; bit 3 marks a cell outside the domain (10-flux stencil)
+  uint32_t s;  // seal bits
 };
 
 // Density-derived quantities of a cell, evaluated once per cell.
@@ -104,19 +104,22 @@ struct Face {
 template <bool VJP>
 __device__ __forceinline__ double trans64(double A2, double kLo, double kUp, bool open,
                                           Face<double> &f) {
-  const double ks = kLo + kUp;
+  // k_Lo + k_Up = 0 (both cells impermeable or outside the domain) gives T = 0:
+  // the sum is raised to the smallest normal number, which leaves every sum of
+  // normal permeabilities unchanged and turns 0 * (1/0) into 0 * finite
+  const double ks = fmax(kLo + kUp, 2.2250738585072014e-308);
   const double inv = rcp64(ks);
   if (VJP) {
     f.qLo = kLo * inv;
     f.qUp = kUp * inv;
   }
   const double T = (A2 * kLo) * (kUp * inv);
-  return (open && ks > 0.0) ? T : 0.0;
+  return open ? T : 0.0;
 }
 template <bool VJP>
 __device__ __forceinline__ float trans32(float A2, float kLo, float kUp, bool open,
                                          Face<float> &f) {
-  const float ks = kLo + kUp;
+  const float ks = fmaxf(kLo + kUp, 1.17549435e-38f);
   const float inv = __builtin_amdgcn_rcpf(ks);
   const float qUp = kUp * inv;
   if (VJP) {
@@ -124,7 +127,7 @@ __device__ __forceinline__ float trans32(float A2, float kLo, float kUp, bool op
     f.qUp = qUp;
   }
   const float T = (A2 * kLo) * qUp;
-  return (open && ks > 0.0f) ? T : 0.0f;
+  return open ? T : 0.0f;
 }
 
 // Upwinded flux and derivatives from T, the potential difference and the
@@ -215,14 +218,46 @@ __device__ __forceinline__ void st_nt(T *p, T v) {
   __builtin_nontemporal_store(v, (gptr<T>)p);
 }
 
+// LDS of one workgroup (gfx950: 160 KiB per CU, all of it addressable by one
+// workgroup).
+constexpr int kMaxLds = 160 * 1024;
+
+// FP64 residual-only modes evaluate every in-plane face once, in its lower
+// cell, and hand the flux to the upper cell through LDS: two buffers of the
+// plane of p, k, mobility and of the +x, +y (and +x+y, +x-y) face fluxes. An
+// FP64 face costs a double reciprocal with two Newton steps, so sharing saves
+// more than the extra LDS traffic costs; in FP32 (one hardware reciprocal per
+// face) it measured slower on MI355X and the two-sided form is kept.
+template <class S, int MODE, int TX, int TY>
+constexpr int share_lds_bytes() {
+  return 2 * (TX + 2) * (TY + 2) * (int)sizeof(S) * (MODE == MODE_RES10 ? 7 : 5);
+}
+template <class S, int MODE, int TX, int TY>
+constexpr bool tile_shares() {
+  return (MODE == MODE_RESIDUAL || MODE == MODE_RES10) && sizeof(S) == 8 &&
+         share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
+}
+
 // Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
-// p, k, mobility, seal (and w for the vector-Jacobian product).
+// p, k, mobility, seal (and w for the vector-Jacobian product, the diagonal
+// transmissibilities for the 10-flux stencil), or the shared-face layout.
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
   constexpr int arrays = 3 + (MODE == MODE_VJP ? 1 : 0) + (MODE == MODE_RES10 ? 2 : 0);
-  return 2 * HW * ((int)sizeof(S) * arrays + 1);
+  return tile_shares<S, MODE, TX, TY>() ? share_lds_bytes<S, MODE, TX, TY>()
+                                        : 2 * HW * ((int)sizeof(S) * arrays + 1);
 }
+
+// Lower-cell faces a halo cell evaluates for the tile in the shared-face form.
+constexpr uint32_t kPX = 1, kPY = 2, kNE = 4, kSE = 8;
+
+// Fluxes of a plane whose residual is completed at the next plane: its own
+// lower-cell faces (+x, +y, +x+y, +x-y) and its two z faces.
+template <class S>
+struct Pending {
+  S fpx, fpy, fzm, fzp, fne, fse;
+};
 
 // ----------------------------------------------------------------------------
 // The tile body: columns [bx*TX, bx*TX+TX) x [by*TY, by*TY+TY), planes
@@ -230,14 +265,16 @@ constexpr int tile_lds_bytes() {
 // ----------------------------------------------------------------------------
 
 // Uniform (scalar) base of plane k of an array plus a per-thread 32-bit byte
-// offset: addresses cost no vector ALU work.
+// offset.
 template <class T>
 __device__ __forceinline__ T at(const T *base, size_t plane_elems, int k, uint32_t boff) {
-  return *(gptr<const T>)(reinterpret_cast<const char *>(base + (size_t)k * plane_elems) + boff);
+  const char *pb = reinterpret_cast<const char *>(base + (size_t)k * plane_elems);
+  return *(gptr<const T>)(pb + boff);
 }
 template <class T>
 __device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
-  return reinterpret_cast<T *>(reinterpret_cast<char *>(base + elems) + boff);
+  char *pb = reinterpret_cast<char *>(base + elems);
+  return reinterpret_cast<T *>(pb + boff);
 }
 
 // Accumulates and stores one cell's outputs from its six faces (neighbour
@@ -299,19 +336,23 @@ struct Tile {
   static constexpr bool FP32 = sizeof(S) == 4;
 
   static constexpr bool R10 = MODE == MODE_RES10;
+  static constexpr bool SHARE = tile_shares<S, MODE, TX, TY>();
   static constexpr int NT = TX * TY;          // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
   static constexpr int HC = (NH + NT - 1) / NT;  // halo cells staged per thread
 
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
+  S *s_fx, *s_fy, *s_fne, *s_fse;  // shared-face fluxes (residual-only modes)
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
   bool own;
+  bool tnv, tsv;       // 10-flux: the own cell's +x+y / +x-y diagonal face exists
   int ol;
   uint32_t cb, cs;     // byte offset of the own cell within a plane (S elements / seal bytes)
   bool hv[HC];         // halo cell q lies in the domain
+  uint32_t hr[HC];     // shared faces: lower-cell faces halo cell q evaluates (kPX | kPY | kNE | kSE)
   int hl[HC];          // its LDS slot, -1 if the thread stages no q-th halo cell
   uint32_t hb[HC], hs[HC];
   S A2x, A2y;
@@ -324,6 +365,10 @@ struct Tile {
     s_tn = s_w + (VJP ? 2 * HW : 0);
     s_ts = s_tn + (R10 ? 2 * HW : 0);
     s_s = reinterpret_cast<uint8_t *>(s_ts + (R10 ? 2 * HW : 0));
+    s_fx = s_l + 2 * HW;
+    s_fy = s_fx + 2 * HW;
+    s_fne = s_fy + 2 * HW;
+    s_fse = s_fne + (R10 ? 2 * HW : 0);
     const int nx = a.nx, ny = a.ny;
     nz = a.nz;
     kb = kb_;
@@ -333,6 +378,8 @@ struct Tile {
     const int tx = tid % TX, ty = tid / TX;
     const int i = bx * TX + tx, j = by * TY + ty;
     own = i < nx && j < ny;
+    tnv = own && i + 1 < nx && j + 1 < ny;
+    tsv = own && i + 1 < nx && j >= 1;
     const uint32_t col = own ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
     ol = (ty + 1) * W + tx + 1;
     cb = col * (uint32_t)sizeof(S);
@@ -342,19 +389,23 @@ struct Tile {
     for (int q = 0; q < HC; ++q) {
       const int h = tid + q * NT;
       int hi = -1, hj = -1, l = -1;
-      if (h < TX) {
+      uint32_t role = 0;  // faces into the tile whose lower cell is this halo cell
+      if (h < TX) {  // bottom row: +y (and +x+y) faces
         hi = bx * TX + h;
         hj = by * TY - 1;
         l = h + 1;
-      } else if (h < 2 * TX) {
+        role = kPY | (R10 ? kNE : 0u);
+      } else if (h < 2 * TX) {  // top row: +x-y faces
         hi = bx * TX + h - TX;
         hj = by * TY + TY;
         l = (TY + 1) * W + h - TX + 1;
-      } else if (h < 2 * TX + TY) {
+        role = R10 ? kSE : 0u;
+      } else if (h < 2 * TX + TY) {  // left column: +x (and both diagonal) faces
         hi = bx * TX - 1;
         hj = by * TY + h - 2 * TX;
         l = (h - 2 * TX + 1) * W;
-      } else if (h < 2 * TX + 2 * TY) {
+        role = kPX | (R10 ? kNE | kSE : 0u);
+      } else if (h < 2 * TX + 2 * TY) {  // right column: none (the tile's lower cells)
         hi = bx * TX + TX;
         hj = by * TY + h - 2 * TX - TY;
         l = (h - 2 * TX - TY + 1) * W + TX + 1;
@@ -364,7 +415,9 @@ struct Tile {
         hi = cx ? bx * TX + TX : bx * TX - 1;
         hj = cy ? by * TY + TY : by * TY - 1;
         l = (cy ? TY + 1 : 0) * W + (cx ? TX + 1 : 0);
+        role = c == 0 ? kNE : c == 2 ? kSE : 0u;
       }
+      hr[q] = SHARE ? role : 0u;
       hl[q] = l;
       hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
       const uint32_t hcol = hv[q] ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
@@ -386,14 +439,29 @@ struct Tile {
     if (R10) {
       c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
       c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
-      c.s = (c.s & 7u) | (ok ? 0u : 8u);
     }
   }
-  __device__ __forceinline__ void load(Cell<S> &c, int k) const { load_at(c, k, own, cb, cs); }
+  // A diagonal face exists when both its cells lie in the domain; otherwise its
+  // transmissibility is staged as 0 (whatever the caller's array holds there).
+  // A halo cell's tne / tse serve only faces towards tile cells, so the halo
+  // cell's own presence decides; the own cell checks its (i+1, j+-1) partner.
+  __device__ __forceinline__ void load(Cell<S> &c, int k) const {
+    load_at(c, k, own, cb, cs);
+    if (R10) {
+      c.tn = tnv ? c.tn : S(0);
+      c.ts = tsv ? c.ts : S(0);
+    }
+  }
   __device__ __forceinline__ void load_halo(Cell<S> (&h)[HC], int k) const {
 #pragma unroll
     for (int q = 0; q < HC; ++q)
-      if (hl[q] >= 0) load_at(h[q], k, hv[q], hb[q], hs[q]);
+      if (hl[q] >= 0) {
+        load_at(h[q], k, hv[q], hb[q], hs[q]);
+        if (R10) {
+          h[q].tn = hv[q] ? h[q].tn : S(0);
+          h[q].ts = hv[q] ? h[q].ts : S(0);
+        }
+      }
   }
 
   // FP32 form: x_k = pref[k] - p0 for the density exponent
@@ -490,7 +558,7 @@ struct Tile {
 
     // the four in-plane diagonal faces of the 10-flux stencil: transmissibility
     // given (tne on the face's left end for (i,j)-(i+1,j+1), tse for
-    // (i,j)-(i+1,j-1)), closed when either cell lies outside the domain
+    // (i,j)-(i+1,j-1)), staged as 0 where the face does not exist
     S fd[4] = {};
     if constexpr (R10) {
       const int dsl[4] = {ol - W - 1, ol + W + 1, ol - W + 1, ol + W - 1};
@@ -498,10 +566,8 @@ struct Tile {
       for (int n = 0; n < 4; ++n) {
         const int q = b + dsl[n];
         const S pn = s_p[q], ln = s_l[q];
-        const bool open = ((c0.s | (uint32_t)s_s[q]) & 8u) == 0u;
         // face transmissibility: stored on the face's left (i) end
-        const S T0 = n == 0 ? s_tn[q] : n == 1 ? c0.tn : n == 2 ? c0.ts : s_ts[q];
-        const S T = open ? T0 : S(0);
+        const S T = n == 0 ? s_tn[q] : n == 1 ? c0.tn : n == 2 ? c0.ts : s_ts[q];
         // the lower-index cell is the neighbour for n = 0, 2 and the own cell for 1, 3
         const S pLo = (n & 1) ? c0.p : pn, pUp = (n & 1) ? pn : c0.p;
         const S lLo = (n & 1) ? d0.lam : ln, lUp = (n & 1) ? ln : d0.lam;
@@ -511,6 +577,115 @@ struct Tile {
     }
     if (!own) return;
     emit<S, MODE>(a, k, plane, nz, cb, c0, f, wn, fd);
+  }
+
+  // ---- shared-face form (residual-only modes) ----------------------------
+  // The face towards a neighbour N of higher index in the plane (+x, +y, and
+  // for the 10-flux stencil +x+y, +x-y) is evaluated once, by the cell on its
+  // -x / -y side, which is the face's lower cell (+x, +y, +x+y) or upper cell
+  // (+x-y). Its flux goes to LDS; the other cell reads it after the next
+  // barrier. Each face gets exactly the operands and operation order of the
+  // two-sided form, and the residual is summed in the same order, so both
+  // forms give bit-identical results.
+
+  // F of the face from cell X (at LDS slot x, values passed in) to the slot
+  // y of its +x, +y, +x+y or +x-y neighbour.
+  __device__ __forceinline__ S fwd_face(uint32_t dir, int y, S pX, S kX, S lX, uint32_t sX,
+                                        S tX) const {
+    const S pn = s_p[y], ln = s_l[y];
+    if (dir == kPX || dir == kPY) {
+      const S A2 = dir == kPX ? A2x : A2y;
+      const uint32_t bit = dir == kPX ? 1u : 2u;
+      return face_h<false, false>(a, A2, kX, s_k[y], (sX & bit) == 0u, pX, pn, lX, ln).F;
+    }
+    // diagonal: X is the lower cell of the +x+y face and the upper cell of the +x-y face
+    const bool lo = dir == kNE;
+    const S pLo = lo ? pX : pn, pUp = lo ? pn : pX;
+    const S lLo = lo ? lX : ln, lUp = lo ? ln : lX;
+    const S dphi = pLo - pUp;
+    return (tX * (dphi >= S(0) ? lLo : lUp)) * dphi;
+  }
+
+  // Residual of plane k of the own cell from its pending fluxes and the
+  // neighbours' shared fluxes in LDS buffer bq (same order as emit()).
+  __device__ __forceinline__ void finish(int k, int bq, const Pending<S> &pd) const {
+    if (!own) return;
+    double r = 0.0;
+    r = r - (double)s_fx[bq + ol - 1];
+    r = r + (double)pd.fpx;
+    r = r - (double)s_fy[bq + ol - W];
+    r = r + (double)pd.fpy;
+    r = r - (double)pd.fzm;
+    r = r + (double)pd.fzp;
+    if constexpr (R10) {
+      r = r - (double)s_fne[bq + ol - W - 1];
+      r = r + (double)pd.fne;
+      r = r - (double)pd.fse;
+      r = r + (double)s_fse[bq + ol + W - 1];
+    }
+    if (a.r) st_nt(at_w(static_cast<S *>(a.r), (size_t)k * plane, cb), (S)r);
+  }
+
+  // One plane k in the shared-face form: stage, complete plane k-1, evaluate
+  // the z face (k, k+1) and the lower-cell in-plane faces of plane k.
+  __device__ __forceinline__ void step_share(int k, const Cell<S> &c0, const Props<S> &d0,
+                                             const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
+                                             const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
+                                             const Face<S> &zm, Face<S> &zp,
+                                             Pending<S> &pd) const {
+    const int b = ((k - kb) & 1) * HW;
+    const bool has_pz = k + 1 < nz;
+    const S xk = xoff(k);
+    if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
+    if (k + 1 < ke) load_halo(h1, k + 1);
+
+    s_p[b + ol] = c0.p;
+    s_k[b + ol] = c0.k;
+    s_l[b + ol] = d0.lam;
+    S hlam[HC];
+#pragma unroll
+    for (int q = 0; q < HC; ++q) {
+      if (hl[q] < 0) continue;
+      hlam[q] = props(h0[q].p, xk, a).lam;
+      const int l = b + hl[q];
+      s_p[l] = h0[q].p;
+      s_k[l] = h0[q].k;
+      s_l[l] = hlam[q];
+    }
+    __syncthreads();
+
+    // plane k-1: its upper-cell fluxes were written before this barrier
+    if (k > kb) finish(k - 1, HW - b, pd);
+
+    d1 = props(c1.p, xoff(has_pz ? k + 1 : k), a);
+    zp = face_z<false, false>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
+                              has_pz ? dpref(k) : 0.0, d0, d1);
+
+    const int o = b + ol;
+    pd.fpx = fwd_face(kPX, o + 1, c0.p, c0.k, d0.lam, c0.s, S(0));
+    pd.fpy = fwd_face(kPY, o + W, c0.p, c0.k, d0.lam, c0.s, S(0));
+    s_fx[o] = pd.fpx;
+    s_fy[o] = pd.fpy;
+    if constexpr (R10) {
+      pd.fne = fwd_face(kNE, o + W + 1, c0.p, c0.k, d0.lam, c0.s, c0.tn);
+      pd.fse = fwd_face(kSE, o - W + 1, c0.p, c0.k, d0.lam, c0.s, c0.ts);
+      s_fne[o] = pd.fne;
+      s_fse[o] = pd.fse;
+    }
+    pd.fzm = zm.F;
+    pd.fzp = zp.F;
+    // faces entering the tile from the -x / -y side of the halo ring
+#pragma unroll
+    for (int q = 0; q < HC; ++q) {
+      const uint32_t role = hr[q];
+      if (role == 0u) continue;
+      const int l = b + hl[q];
+      const Cell<S> &h = h0[q];
+      if (role & kPX) s_fx[l] = fwd_face(kPX, l + 1, h.p, h.k, hlam[q], h.s, S(0));
+      if (role & kPY) s_fy[l] = fwd_face(kPY, l + W, h.p, h.k, hlam[q], h.s, S(0));
+      if (R10 && (role & kNE)) s_fne[l] = fwd_face(kNE, l + W + 1, h.p, h.k, hlam[q], h.s, h.tn);
+      if (R10 && (role & kSE)) s_fse[l] = fwd_face(kSE, l - W + 1, h.p, h.k, hlam[q], h.s, h.ts);
+    }
   }
 };
 
@@ -528,14 +703,30 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
   if (kb + 1 < t.nz) t.load(c1, kb + 1);
   d0 = props(c0.p, t.xoff(kb), a);
   z0 = t.first_zface(c0, d0);
-  for (int k = kb; k < t.ke; ++k) {
-    t.step(k, c0, d0, c1, d1, c2, h0, h1, z0, z1);
-    c0 = c1;
-    d0 = d1;
-    c1 = c2;
+  if constexpr (T::SHARE) {
+    Pending<S> pd{};
+    for (int k = kb; k < t.ke; ++k) {
+      t.step_share(k, c0, d0, c1, d1, c2, h0, h1, z0, z1, pd);
+      c0 = c1;
+      d0 = d1;
+      c1 = c2;
 #pragma unroll
-    for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
-    z0 = z1;
+      for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
+      z0 = z1;
+    }
+    // the last plane's upper-cell fluxes
+    __syncthreads();
+    t.finish(t.ke - 1, ((t.ke - 1 - kb) & 1) * T::HW, pd);
+  } else {
+    for (int k = kb; k < t.ke; ++k) {
+      t.step(k, c0, d0, c1, d1, c2, h0, h1, z0, z1);
+      c0 = c1;
+      d0 = d1;
+      c1 = c2;
+#pragma unroll
+      for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
+      z0 = z1;
+    }
   }
 }
 

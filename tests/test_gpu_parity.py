@@ -303,3 +303,58 @@ def test_ensemble_matches_single_launches_and_oracle(gpu, orc, prec):
                            tol=tol, tau=tau, ry=geo.ry, rz=geo.rz, seal=geo.seal)
         assert rep["max_err"] <= tol, (q, rep)
     ens.close()
+
+
+# ---------------------------------------------------------------------------
+# Residual-only kernels evaluate every in-plane face once and pass its flux
+# through LDS; they must reproduce the Jacobian kernels' residual (which
+# evaluates each face from both sides) bit for bit, for every tile shape and
+# z-chunk and in the ensemble kernels.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(70, 9, 37), (129, 13, 3), (17, 33, 5), (1, 6, 4), (5, 1, 9)],
+                         ids=lambda s: "x".join(map(str, s)) if isinstance(s, tuple) else s)
+def test_shared_face_residual_bitwise(gpu, orc, shape, prec):
+    geo = small(shape, seed=23)
+    if prec == "fp64":
+        k, p, pref = dev(geo.kx), dev(orc.pressure(geo)), None
+    else:
+        pref_h, dp, k32, _, _ = fp32_inputs(orc, geo)
+        k, p, pref = dev(k32), dev(dp), dev(pref_h)
+    kw = dict(seal=dev(geo.seal), pref=pref, ry=geo.ry, rz=geo.rz)
+    print(f"shared-face residual {prec} {shape}", flush=True)
+    r_ref, _ = gpu.jacobian(geo.grid, geo.fluid, k, p, **kw)
+    r_ref = host(r_ref)
+    for tile in range(len(gpu.tile_shapes())):
+        for kz in (0, 1, 2, 5):
+            r = host(gpu.residual(geo.grid, geo.fluid, k, p, tile=tile, kz_chunk=kz, **kw))
+            assert np.array_equal(r, r_ref), (tile, kz)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_ensemble_residual_mode_matches_single_launches(gpu, orc, prec):
+    models = geomodel.ensemble(n_models=9, scale=0.15, base_seed=4100)
+    members = []
+    for m, geo in enumerate(models):
+        if prec == "fp32":
+            pref, dp, k32, _, _ = fp32_inputs(orc, geo)
+            d = dict(grid=geo.grid, fluid=geo.fluid, kx=dev(k32), p=dev(dp), seal=dev(geo.seal),
+                     pref=dev(pref), ry=geo.ry, rz=geo.rz, tile=m % 3, kz_chunk=4 + 5 * m)
+        else:
+            d = dict(grid=geo.grid, fluid=geo.fluid, kx=dev(geo.kx), p=dev(orc.pressure(geo)),
+                     seal=dev(geo.seal), ry=geo.ry, rz=geo.rz, tile=m % 3, kz_chunk=4 + 5 * m)
+        members.append(d)
+    ens = gpu.Ensemble(members, mode="residual")
+    singles = [gpu.jacobian(d["grid"], d["fluid"], d["kx"], d["p"], seal=d["seal"],
+                            pref=d.get("pref"), ry=d["ry"], rz=d["rz"])[0] for d in members]
+    for replay in range(4):
+        for q in range(len(members)):
+            ens.r[q].fill_(float("nan"))
+        if replay == 2:
+            ens.set_schedule("grouped")
+        ens.run(graph=(replay != 1))
+        torch.cuda.synchronize()
+        for q, r in enumerate(singles):
+            assert torch.equal(ens.r[q], r), (replay, q)
+    ens.close()
