@@ -253,3 +253,20 @@ def diagonal_t(grid: Grid, seed: int, zero_prob: float = 0.1) -> tuple:
         t[rng.random(grid.shape) < zero_prob] = 0.0
         out.append(t)
     return tuple(out)
+
+
+# Backward-Euler inputs (accumulation term of Eq. (2)): reference porosity,
+# previous-level pressure noise and a Krylov direction.
+BE_DT = 86400.0   # one day (s)
+BE_CR = 5e-10     # rock compressibility (1/Pa)
+
+
+def be_fields(grid: Grid, seed: int, step_amp: float = 5e4) -> dict:
+    """phi_ref ~ U(0.1, 0.3); the previous level's pressure differs from the
+    current one by U(-step_amp, step_amp) Pa per cell (``dp_step``, to be
+    subtracted from the current pressure); v ~ N(0, 1). Float64, (nz, ny, nx)."""
+    s_phi, s_step, s_v = np.random.SeedSequence(seed).spawn(3)
+    return {"phi": np.random.default_rng(s_phi).uniform(0.1, 0.3, grid.shape),
+            "dp_step": np.random.default_rng(s_step).uniform(-step_amp, step_amp, grid.shape),
+            "v": np.random.default_rng(s_v).standard_normal(grid.shape),
+            "dt": BE_DT, "cr": BE_CR}

@@ -127,6 +127,49 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                       tpfa_precision_t prec, const void *w, void *grad_p,
                       void *grad_logk, const tpfa_launch_t *launch, void *stream);
 
+/* Accumulation term of the full backward-Euler residual, Eq. (2):
+     V_K (phi(p_K) rho(p_K) - phi(pn_K) rho(pn_K)) / dt,  V_K = dx dy dz,
+   with rho from Eq. (5) and the porosity linear in pressure (Sec. 3 states
+   that porosity depends linearly on p): phi(p) = phi_ref (1 + cr (p - p0)),
+   p0 the fluid's reference pressure.
+   phi    : phi_ref[ncell], device, dtype of the precision.
+   p_prev : pressure of the previous time level [ncell], device, in the form
+            of state->p (absolute FP64, or the FP32 offset from the same pref).
+   dt     : time step (s), > 0 and finite; cr: rock compressibility (1/Pa). */
+typedef struct {
+  const void *phi;
+  const void *p_prev;
+  double dt;
+  double cr;
+} tpfa_accum_t;
+
+/* Full backward-Euler residual of Eq. (2): the accumulation term above plus
+   the flux sum of tpfa_residual. accum is required (TPFA_ERR_NULL), dt <= 0 or
+   non-finite dt / cr give TPFA_ERR_PARAM. */
+int tpfa_residual_be(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                     const tpfa_rock_t *rock, const tpfa_state_t *state,
+                     const tpfa_accum_t *accum, tpfa_precision_t prec, void *r,
+                     const tpfa_launch_t *launch, void *stream);
+
+/* Its residual (r may be NULL) and 7-point Jacobian (layout of tpfa_jacobian);
+   the accumulation derivative V/dt (phi_ref cr rho + phi cf rho) is on the
+   diagonal. */
+int tpfa_jacobian_be(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                     const tpfa_rock_t *rock, const tpfa_state_t *state,
+                     const tpfa_accum_t *accum, tpfa_precision_t prec, void *r, void *J,
+                     const tpfa_launch_t *launch, void *stream);
+
+/* Matrix-free Jacobian-vector product jv = J v[ncell] (the operator a
+   Newton-Krylov solver of Eq. (2) applies; the paper names such an operator as
+   its next step, Sec. 8), without forming or storing J: the flux Jacobian of
+   tpfa_jacobian, plus the accumulation diagonal when accum is not NULL. The
+   residual is written too when r is not NULL (the flux residual, or the
+   backward-Euler residual with accum). v and jv are device arrays of the
+   precision's dtype; in the FP32 form v is a direction in dp. */
+int tpfa_jvp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
+             const tpfa_state_t *state, const tpfa_accum_t *accum, tpfa_precision_t prec,
+             const void *v, void *jv, void *r, const tpfa_launch_t *launch, void *stream);
+
 /* Residual of the 10-flux stencil: the six faces above plus the four in-plane
    diagonal faces that the paper's kernel also evaluates (Sec. 3, Algorithm 1
    applied with four extra neighbours), whose transmissibilities the caller

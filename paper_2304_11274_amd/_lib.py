@@ -48,6 +48,11 @@ class State(C.Structure):
     _fields_ = [("p", C.c_void_p), ("pref", C.c_void_p)]
 
 
+class Accum(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("p_prev", C.c_void_p), ("dt", C.c_double),
+                ("cr", C.c_double)]
+
+
 class Launch(C.Structure):
     _fields_ = [("tile", C.c_int), ("kz_chunk", C.c_int), ("flags", C.c_int)]
 
@@ -67,6 +72,12 @@ SIGNATURES = {
                                 vp]),
     "tpfa_residual_vjp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
                                     P(Launch), vp]),
+    "tpfa_residual_be": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int,
+                                   vp, P(Launch), vp]),
+    "tpfa_jacobian_be": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int,
+                                   vp, vp, P(Launch), vp]),
+    "tpfa_jvp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int, vp, vp,
+                           vp, P(Launch), vp]),
     "tpfa_residual10": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
                                   P(Launch), vp]),
     "tpfa_hydrostatic": (C.c_int, [P(Grid), P(Fluid), C.c_double, vp, vp]),

@@ -144,6 +144,79 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     return gp, gm
 
 
+def _accum(accum, dt_, n, dev):
+    """``accum`` = dict(phi=..., p_prev=..., dt=..., cr=...) -> (L.Accum, keep-alive)."""
+    if accum is None:
+        return None
+    phi, p_prev = accum["phi"], accum["p_prev"]
+    _need(phi, "phi", dt_, n, dev)
+    _need(p_prev, "p_prev", dt_, n, dev)
+    return L.Accum(_ptr(phi), _ptr(p_prev), float(accum["dt"]), float(accum.get("cr", 0.0)))
+
+
+def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+                tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+    """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
+    the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    acc = _accum(accum, dt, n, dev)
+    if acc is None:
+        raise ValueError("residual_be needs accum")
+    r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+    _need(r, "out", dt, n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_residual_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                                 C.byref(_rock(kx, seal, ry, rz)),
+                                 C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
+                                 _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)),
+            lib)
+    return r
+
+
+def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0,
+                want_r=True, r_out=None, J_out=None, tile=None, kz_chunk=None,
+                xcd_remap=False):
+    """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    acc = _accum(accum, dt, n, dev)
+    if acc is None:
+        raise ValueError("jacobian_be needs accum")
+    r = None
+    if want_r:
+        r = r_out if r_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+        _need(r, "r_out", dt, n, dev)
+    J = J_out if J_out is not None else torch.empty((7,) + tuple(p.shape), dtype=dt, device=dev)
+    _need(J, "J_out", dt, 7 * n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                                 C.byref(_rock(kx, seal, ry, rz)),
+                                 C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
+                                 _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap),
+                                 _stream(dev)), lib)
+    return r, J
+
+
+def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0,
+        want_r=False, out=None, r_out=None, tile=None, kz_chunk=None, xcd_remap=False):
+    """Matrix-free J v of the flux residual, or of the backward-Euler residual
+    when ``accum`` is given; returns (jv, r or None)."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    _need(v, "v", dt, n, dev)
+    acc = _accum(accum, dt, n, dev)
+    jv = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+    _need(jv, "out", dt, n, dev)
+    r = None
+    if want_r:
+        r = r_out if r_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
+        _need(r, "r_out", dt, n, dev)
+    lib = L.load()
+    L.check(lib.tpfa_jvp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+                         C.byref(_rock(kx, seal, ry, rz)), C.byref(L.State(_ptr(p), _ptr(pref))),
+                         None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
+                         _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+    return jv, r
+
+
 def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
                tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal

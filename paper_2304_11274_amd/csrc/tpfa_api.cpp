@@ -90,11 +90,12 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
 int default_tile(const tpfa_grid_t &g, tpfa::Mode mode) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
-  return mode == tpfa::MODE_VJP || mode == tpfa::MODE_RES10 ? 0 : 3;
+  const int b = tpfa::base_mode(mode);
+  return b == tpfa::MODE_VJP || b == tpfa::MODE_JVP || mode == tpfa::MODE_RES10 ? 0 : 3;
 }
 
 int default_kz(tpfa::Mode mode) {
-  return mode == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10 ? 32 : 16;
+  return tpfa::base_mode(mode) == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10 ? 32 : 16;
 }
 
 int hip_fail(hipError_t e, const char *what) {
@@ -178,6 +179,13 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   b.gm = a.gm;
   b.tne = a.tne;
   b.tse = a.tse;
+  b.jv = a.jv;
+  b.phi = a.phi;
+  b.pprev = a.pprev;
+  b.vdt = a.vdt;
+  b.cr = a.cr;
+  b.vdtf = a.vdtf;
+  b.crf = a.crf;
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
   const hipError_t e =
@@ -239,6 +247,83 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
     a.gp = grad_p;
     a.gm = grad_logk;
     return run(tpfa::MODE_VJP, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+// Accumulation fields of the backward-Euler modes from the descriptor.
+int set_accumulation(const tpfa_grid_t *g, const tpfa_accum_t *acc, tpfa::Args &a) {
+  if (!acc) return fail(TPFA_ERR_NULL, "accum is NULL");
+  if (!acc->phi || !acc->p_prev) return fail(TPFA_ERR_NULL, "accum->phi and accum->p_prev are required");
+  if (!(acc->dt > 0.0) || !std::isfinite(acc->dt))
+    return fail(TPFA_ERR_PARAM, "accum->dt must be positive and finite");
+  if (!std::isfinite(acc->cr)) return fail(TPFA_ERR_PARAM, "accum->cr must be finite");
+  a.phi = acc->phi;
+  a.pprev = acc->p_prev;
+  a.vdt = (g->dx * g->dy * g->dz) / acc->dt;
+  a.cr = acc->cr;
+  a.vdtf = (float)a.vdt;
+  a.crf = (float)acc->cr;
+  return TPFA_OK;
+}
+
+int tpfa_residual_be(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                     const tpfa_rock_t *rock, const tpfa_state_t *state,
+                     const tpfa_accum_t *accum, tpfa_precision_t prec, void *r,
+                     const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!r) return fail(TPFA_ERR_NULL, "r is NULL");
+    tpfa::Args a{};
+    if ((rc = set_accumulation(grid, accum, a))) return rc;
+    a.r = r;
+    return run(tpfa::MODE_RESIDUAL_BE, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_jacobian_be(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                     const tpfa_rock_t *rock, const tpfa_state_t *state,
+                     const tpfa_accum_t *accum, tpfa_precision_t prec, void *r, void *J,
+                     const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!J) return fail(TPFA_ERR_NULL, "J is NULL");
+    tpfa::Args a{};
+    if ((rc = set_accumulation(grid, accum, a))) return rc;
+    a.r = r;
+    a.J = J;
+    return run(tpfa::MODE_JACOBIAN_BE, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_jvp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
+             const tpfa_state_t *state, const tpfa_accum_t *accum, tpfa_precision_t prec,
+             const void *v, void *jv, void *r, const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!v) return fail(TPFA_ERR_NULL, "v is NULL");
+    if (!jv) return fail(TPFA_ERR_NULL, "jv is NULL");
+    tpfa::Args a{};
+    if (accum && (rc = set_accumulation(grid, accum, a))) return rc;
+    a.w = v;
+    a.jv = jv;
+    a.r = r;
+    return run(accum ? tpfa::MODE_JVP_BE : tpfa::MODE_JVP, grid, fluid, rock, state, prec,
+               launch, a, stream);
   } catch (const std::exception &e) {
     return fail(TPFA_ERR_HIP, e.what());
   } catch (...) {

@@ -9,7 +9,27 @@
 
 namespace tpfa {
 
-enum Mode : int { MODE_RESIDUAL = 0, MODE_JACOBIAN = 1, MODE_VJP = 2, MODE_RES10 = 3 };
+// Kernel modes. The *_BE modes add the accumulation term of the backward-Euler
+// residual; the JVP modes form J v without storing J.
+enum Mode : int {
+  MODE_RESIDUAL = 0,
+  MODE_JACOBIAN = 1,
+  MODE_VJP = 2,
+  MODE_RES10 = 3,
+  MODE_RESIDUAL_BE = 4,
+  MODE_JACOBIAN_BE = 5,
+  MODE_JVP = 6,
+  MODE_JVP_BE = 7
+};
+constexpr int base_mode(int m) {
+  return m == MODE_RESIDUAL_BE ? MODE_RESIDUAL
+         : m == MODE_JACOBIAN_BE ? MODE_JACOBIAN
+         : m == MODE_JVP_BE      ? MODE_JVP
+                                 : m;
+}
+constexpr bool has_accumulation(int m) {
+  return m == MODE_RESIDUAL_BE || m == MODE_JACOBIAN_BE || m == MODE_JVP_BE;
+}
 
 // Tile table. A workgroup owns a TX x TY column block of one model and marches
 // it through a chunk of z planes; each thread stages ceil(2 (TX + TY) / threads)
@@ -45,17 +65,24 @@ struct Args {
   // FP32 precision form
   float a2xf, a2yf, a2zf;
   float rho0f, cff, inv_muf, hcf, pad2_;
+  // accumulation term of the backward-Euler residual: V / dt and the rock
+  // compressibility (FP64 and FP32 copies)
+  double vdt, cr;
+  float vdtf, crf;
   const void *p;
   const double *pref;
   const void *kx;
   const uint8_t *seal;
-  const void *w;
+  const void *w;      // cotangent (VJP) or direction v (JVP)
+  const void *phi;    // reference porosity per cell (backward-Euler modes)
+  const void *pprev;  // pressure of the previous time level, in the form of p
   const void *tne;   // 10-flux stencil: diagonal transmissibilities
   const void *tse;
   void *r;
   void *J;
   void *gp;
   void *gm;
+  void *jv;           // J v (JVP modes)
 };
 
 // Fills the derived fields of `a` from the ABI structs (host only).

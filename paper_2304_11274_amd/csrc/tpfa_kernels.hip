@@ -54,6 +54,7 @@ struct Cell {
   S k;         // kx
   S w;         // cotangent (vector-Jacobian product only)
   S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
+  S phi, pn;   // reference porosity and previous-level pressure (backward-Euler modes)
   uint32_t s;  // seal bits
 };
 
@@ -234,7 +235,7 @@ constexpr int share_lds_bytes() {
 }
 template <class S, int MODE, int TX, int TY>
 constexpr bool tile_shares() {
-  return (MODE == MODE_RESIDUAL || MODE == MODE_RES10) && sizeof(S) == 8 &&
+  return (base_mode(MODE) == MODE_RESIDUAL || MODE == MODE_RES10) && sizeof(S) == 8 &&
          share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
 
@@ -244,7 +245,8 @@ constexpr bool tile_shares() {
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
-  constexpr int arrays = 3 + (MODE == MODE_VJP ? 1 : 0) + (MODE == MODE_RES10 ? 2 : 0);
+  constexpr int B = base_mode(MODE);
+  constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) + (MODE == MODE_RES10 ? 2 : 0);
   return tile_shares<S, MODE, TX, TY>() ? share_lds_bytes<S, MODE, TX, TY>()
                                         : 2 * HW * ((int)sizeof(S) * arrays + 1);
 }
@@ -257,7 +259,34 @@ constexpr uint32_t kPX = 1, kPY = 2, kNE = 4, kSE = 8;
 template <class S>
 struct Pending {
   S fpx, fpy, fzm, fzp, fne, fse;
+  double acc;  // accumulation term (backward-Euler residual)
 };
+
+// Accumulation term of the backward-Euler residual of one cell and its
+// pressure derivative: V/dt (phi(p) rho(p) - phi(pn) rho(pn)) with
+// phi(p) = phi_ref (1 + c_r (p - p0)), and V/dt (phi_ref c_r rho + phi c_f rho).
+// FP32 form: p - p0 = x_k + dp with the plane offset x_k; the two masses are
+// FP32 products and their difference is taken in FP64.
+__device__ __forceinline__ void accumulation(const Args &a, const Cell<double> &c,
+                                             const Props<double> &d, double, double &term,
+                                             double &diag) {
+  const double phi1 = c.phi * (1.0 + a.cr * (c.p - a.p0));
+  const double phi0 = c.phi * (1.0 + a.cr * (c.pn - a.p0));
+  const double rho0 = a.rho0 * exp(a.cf * (c.pn - a.p0));
+  const double m1 = phi1 * d.rho, m0 = phi0 * rho0;
+  term = a.vdt * (m1 - m0);
+  diag = a.vdt * ((c.phi * a.cr) * d.rho + phi1 * (a.cf * d.rho));
+}
+__device__ __forceinline__ void accumulation(const Args &a, const Cell<float> &c,
+                                             const Props<float> &d, float xk, double &term,
+                                             float &diag) {
+  const float phi1 = c.phi * (1.0f + a.crf * (xk + c.p));
+  const float phi0 = c.phi * (1.0f + a.crf * (xk + c.pn));
+  const float rho0 = a.rho0f * __expf(a.cff * (xk + c.pn));
+  const float m1 = phi1 * d.rho, m0 = phi0 * rho0;
+  term = a.vdt * ((double)m1 - (double)m0);
+  diag = a.vdtf * ((c.phi * a.crf) * d.rho + phi1 * (a.cff * d.rho));
+}
 
 // ----------------------------------------------------------------------------
 // The tile body: columns [bx*TX, bx*TX+TX) x [by*TY, by*TY+TY), planes
@@ -279,14 +308,16 @@ __device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
 
 // Accumulates and stores one cell's outputs from its six faces (neighbour
 // order -x, +x, -y, +y, -z, +z; odd faces have the cell as their lower cell).
+// In the backward-Euler modes the accumulation term comes first, as in Eq. (2).
 template <class S, int MODE>
 __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz, uint32_t cb,
-                                     const Cell<S> &c0, const Face<S> (&f)[6], const S (&wn)[6],
+                                     const Cell<S> &c0, const Props<S> &d0, S xk,
+                                     const Face<S> (&f)[6], const S (&wn)[6],
                                      const S (&fd)[4]) {
-  // derivatives are formed and stored by the Jacobian and adjoint modes only
-  constexpr bool DERIV = MODE == MODE_JACOBIAN || MODE == MODE_VJP;
+  constexpr int BASE = base_mode(MODE);
+  constexpr bool ACC = has_accumulation(MODE);
   const size_t ko = (size_t)k * plane;
-  if constexpr (MODE == MODE_VJP) {
+  if constexpr (BASE == MODE_VJP) {
     // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
     double gp = 0.0, gm = 0.0;
 #pragma unroll
@@ -303,21 +334,26 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
     if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
     if (a.gm) st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
   } else {
+    double acc = 0.0;
+    S dacc = S(0);
+    if constexpr (ACC) accumulation(a, c0, d0, xk, acc, dacc);
     // residual in the neighbour order, accumulated in FP64
-    double r = 0.0;
+    if (BASE != MODE_JVP || a.r) {
+      double r = acc;
 #pragma unroll
-    for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
-    if constexpr (MODE == MODE_RES10) {
-      // diagonals -x-y, +x+y, +x-y, -x+y: the cell is the upper index of the
-      // first and third, the lower of the second and fourth
+      for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
+      if constexpr (MODE == MODE_RES10) {
+        // diagonals -x-y, +x+y, +x-y, -x+y: the cell is the upper index of the
+        // first and third, the lower of the second and fourth
 #pragma unroll
-      for (int n = 0; n < 4; ++n) r = (n & 1) ? r + (double)fd[n] : r - (double)fd[n];
+        for (int n = 0; n < 4; ++n) r = (n & 1) ? r + (double)fd[n] : r - (double)fd[n];
+      }
+      if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
     }
-    if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
-    if constexpr (DERIV) {
+    if constexpr (BASE == MODE_JACOBIAN) {
       S *J = static_cast<S *>(a.J);
       const size_t nc = (size_t)nz * plane;
-      S dg = S(0);
+      S dg = dacc;
 #pragma unroll
       for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
       st_nt(at_w(J, ko, cb), dg);
@@ -325,14 +361,30 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
       for (int n = 0; n < 6; ++n)
         st_nt(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
     }
+    if constexpr (BASE == MODE_JVP) {
+      // (J v)_C = dacc v_C + sum over faces of dF_CN/dp_C v_C + dF_CN/dp_N v_N,
+      // each face's pair summed in S and the row accumulated in FP64
+      double jv = ACC ? (double)(dacc * c0.w) : 0.0;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) {
+        const S dC = (n & 1) ? f[n].dLo : -f[n].dUp;
+        const S dN = (n & 1) ? f[n].dUp : -f[n].dLo;
+        jv = jv + (double)(dC * c0.w + dN * wn[n]);
+      }
+      st_nt(at_w(static_cast<S *>(a.jv), ko, cb), (S)jv);
+    }
   }
 }
 
 template <class S, int MODE, int TX, int TY>
 struct Tile {
   static constexpr int W = TX + 2, H = TY + 2, HW = W * H;
-  static constexpr bool VJP = MODE == MODE_VJP;
-  static constexpr bool DERIV = MODE == MODE_JACOBIAN || MODE == MODE_VJP;
+  static constexpr int BASE = base_mode(MODE);
+  static constexpr bool ACC = has_accumulation(MODE);
+  static constexpr bool VJP = BASE == MODE_VJP;
+  static constexpr bool JVP = BASE == MODE_JVP;
+  static constexpr bool NEEDW = VJP || JVP;  // neighbours' w (VJP) or v (JVP) staged in LDS
+  static constexpr bool DERIV = BASE == MODE_JACOBIAN || VJP || JVP;
   static constexpr bool FP32 = sizeof(S) == 4;
 
   static constexpr bool R10 = MODE == MODE_RES10;
@@ -362,7 +414,7 @@ struct Tile {
     s_k = s_p + 2 * HW;
     s_l = s_k + 2 * HW;
     s_w = s_l + 2 * HW;
-    s_tn = s_w + (VJP ? 2 * HW : 0);
+    s_tn = s_w + (NEEDW ? 2 * HW : 0);
     s_ts = s_tn + (R10 ? 2 * HW : 0);
     s_s = reinterpret_cast<uint8_t *>(s_ts + (R10 ? 2 * HW : 0));
     s_fx = s_l + 2 * HW;
@@ -435,7 +487,7 @@ struct Tile {
     const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
     c.k = ok ? kx : S(0);
     c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
-    if (VJP) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+    if (NEEDW) c.w = at(static_cast<const S *>(a.w), plane, k, b);
     if (R10) {
       c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
       c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
@@ -447,6 +499,10 @@ struct Tile {
   // cell's own presence decides; the own cell checks its (i+1, j+-1) partner.
   __device__ __forceinline__ void load(Cell<S> &c, int k) const {
     load_at(c, k, own, cb, cs);
+    if (ACC) {
+      c.phi = at(static_cast<const S *>(a.phi), plane, k, cb);
+      c.pn = at(static_cast<const S *>(a.pprev), plane, k, cb);
+    }
     if (R10) {
       c.tn = tnv ? c.tn : S(0);
       c.ts = tsv ? c.ts : S(0);
@@ -502,7 +558,7 @@ struct Tile {
     s_k[b + ol] = c0.k;
     s_l[b + ol] = d0.lam;
     s_s[b + ol] = (uint8_t)c0.s;
-    if (VJP) s_w[b + ol] = c0.w;
+    if (NEEDW) s_w[b + ol] = c0.w;
     if (R10) {
       s_tn[b + ol] = c0.tn;
       s_ts[b + ol] = c0.ts;
@@ -516,7 +572,7 @@ struct Tile {
       s_k[l] = h0[q].k;
       s_l[l] = dh.lam;
       s_s[l] = (uint8_t)h0[q].s;
-      if (VJP) s_w[l] = h0[q].w;
+      if (NEEDW) s_w[l] = h0[q].w;
       if (R10) {
         s_tn[l] = h0[q].tn;
         s_ts[l] = h0[q].ts;
@@ -540,7 +596,7 @@ struct Tile {
       const S kn = s_k[q];
       const S ln = s_l[q];
       const uint32_t sn = s_s[q];
-      if (VJP) wn[n] = s_w[q];
+      if (NEEDW) wn[n] = s_w[q];
       const uint32_t bit = 1u << axis;
       const S A2 = axis == 0 ? A2x : A2y;
       if (n & 1)
@@ -576,7 +632,7 @@ struct Tile {
       }
     }
     if (!own) return;
-    emit<S, MODE>(a, k, plane, nz, cb, c0, f, wn, fd);
+    emit<S, MODE>(a, k, plane, nz, cb, c0, d0, xk, f, wn, fd);
   }
 
   // ---- shared-face form (residual-only modes) ----------------------------
@@ -610,7 +666,7 @@ struct Tile {
   // neighbours' shared fluxes in LDS buffer bq (same order as emit()).
   __device__ __forceinline__ void finish(int k, int bq, const Pending<S> &pd) const {
     if (!own) return;
-    double r = 0.0;
+    double r = ACC ? pd.acc : 0.0;
     r = r - (double)s_fx[bq + ol - 1];
     r = r + (double)pd.fpx;
     r = r - (double)s_fy[bq + ol - W];
@@ -674,6 +730,10 @@ struct Tile {
     }
     pd.fzm = zm.F;
     pd.fzp = zp.F;
+    if constexpr (ACC) {
+      S dacc;
+      accumulation(a, c0, d0, xk, pd.acc, dacc);
+    }
     // faces entering the tile from the -x / -y side of the halo ring
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
@@ -892,6 +952,10 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
       case MODE_RESIDUAL: return launch_t<double, MODE_RESIDUAL>(tile, a, st);
       case MODE_JACOBIAN: return launch_t<double, MODE_JACOBIAN>(tile, a, st);
       case MODE_RES10: return launch_t<double, MODE_RES10>(tile, a, st);
+      case MODE_RESIDUAL_BE: return launch_t<double, MODE_RESIDUAL_BE>(tile, a, st);
+      case MODE_JACOBIAN_BE: return launch_t<double, MODE_JACOBIAN_BE>(tile, a, st);
+      case MODE_JVP: return launch_t<double, MODE_JVP>(tile, a, st);
+      case MODE_JVP_BE: return launch_t<double, MODE_JVP_BE>(tile, a, st);
       default: return launch_t<double, MODE_VJP>(tile, a, st);
     }
   }
@@ -899,6 +963,10 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
     case MODE_RESIDUAL: return launch_t<float, MODE_RESIDUAL>(tile, a, st);
     case MODE_JACOBIAN: return launch_t<float, MODE_JACOBIAN>(tile, a, st);
     case MODE_RES10: return launch_t<float, MODE_RES10>(tile, a, st);
+    case MODE_RESIDUAL_BE: return launch_t<float, MODE_RESIDUAL_BE>(tile, a, st);
+    case MODE_JACOBIAN_BE: return launch_t<float, MODE_JACOBIAN_BE>(tile, a, st);
+    case MODE_JVP: return launch_t<float, MODE_JVP>(tile, a, st);
+    case MODE_JVP_BE: return launch_t<float, MODE_JVP_BE>(tile, a, st);
     default: return launch_t<float, MODE_VJP>(tile, a, st);
   }
 }

@@ -198,3 +198,26 @@ def test_residual10_validation(lib):
     assert lib.tpfa_residual10(*args, DUMMY, DUMMY, DUMMY, C.byref(bad), None) == L.TPFA_ERR_TILE
     g.nx = 0
     assert lib.tpfa_residual10(*args, DUMMY, DUMMY, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+
+
+def test_backward_euler_and_jvp_validation(lib):
+    g, f, rk, st = good()
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st))
+    acc = L.Accum(DUMMY.value, DUMMY.value, 3600.0, 1e-10)
+    P64 = L.TPFA_FP64
+    assert lib.tpfa_residual_be(*args, None, P64, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual_be(*args, C.byref(acc), P64, None, None, None) == L.TPFA_ERR_NULL
+    for bad in (L.Accum(None, DUMMY.value, 3600.0, 0.0), L.Accum(DUMMY.value, None, 3600.0, 0.0)):
+        assert lib.tpfa_residual_be(*args, C.byref(bad), P64, DUMMY, None, None) == L.TPFA_ERR_NULL
+    for dt, cr in ((0.0, 0.0), (-1.0, 0.0), (math.inf, 0.0), (math.nan, 0.0), (1.0, math.nan)):
+        bad = L.Accum(DUMMY.value, DUMMY.value, dt, cr)
+        assert lib.tpfa_residual_be(*args, C.byref(bad), P64, DUMMY, None, None) == L.TPFA_ERR_PARAM
+    assert lib.tpfa_jacobian_be(*args, C.byref(acc), P64, DUMMY, None, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_jacobian_be(*args, None, P64, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_jvp(*args, None, P64, None, DUMMY, None, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_jvp(*args, None, P64, DUMMY, None, None, None, None) == L.TPFA_ERR_NULL
+    bad = L.Accum(DUMMY.value, DUMMY.value, -5.0, 0.0)
+    assert lib.tpfa_jvp(*args, C.byref(bad), P64, DUMMY, DUMMY, None, None, None) == L.TPFA_ERR_PARAM
+    st.pref = None
+    assert lib.tpfa_jvp(*args, None, L.TPFA_FP32, DUMMY, DUMMY, None, None,
+                        None) == L.TPFA_ERR_UNSUPPORTED
