@@ -15,7 +15,9 @@ The same run also times, as extra fields of the JSON line:
   batched  - the 64-model uneven ensemble: one persistent kernel replayed from a
              HIP graph vs one launch per model
   adjoint  - FP32 forward residual + vector-Jacobian product on 256 x 256 x 128
-  paper10  - the paper's own workload (Sec. 6): 1000 applications of the FP32
+  newton   - the backward-Euler residual of Eq. (2) and the matrix-free J v (the
+             operator of a Newton-Krylov step) on 512 x 512 x 256, FP64 and FP32
+  paper10  - the paper's own workload (Sec. 7): 1000 applications of the FP32
              10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
   cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
 The roofline object is for the dominant kernel, the FP64 Jacobian kernel.
@@ -41,7 +43,12 @@ BYTES_FP64_R = 8 + 8 + 1 + 8               # 25
 BYTES_FP32_R = 4 + 4 + 1 + 4               # 13
 BYTES_FP32_VJP = 4 + 4 + 1 + 4 + 4 + 4     # dp, kx, seal, w -> grad_p, grad_logk = 21
 BYTES_FP32_R10 = 4 + 4 + 4 + 4 + 4         # dp, kx, tne, tse -> r (no seals) = 20
-# the paper's wall times for 1000 applications on 750 x 994 x 246 (Sec. 6, Table 1)
+# backward-Euler forms: + phi_ref, p_prev (and v in, J v out for the product)
+BYTES_FP64_RBE = 8 + 8 + 1 + 8 + 8 + 8      # p, kx, seal, phi, p_prev -> r = 41
+BYTES_FP64_JVP = BYTES_FP64_RBE + 8 + 8     # + v -> J v = 57
+BYTES_FP32_JVP = 4 + 4 + 1 + 4 + 4 + 4 + 4 + 4  # = 29
+BYTES_SPMV_FP64 = 7 * 8 + 8 + 8             # stored J, v -> J v = 72
+# the paper's wall times for 1000 applications on 750 x 994 x 246 (Sec. 7, Table 1)
 PAPER10_CONTEXT = {"cs2_s": 0.0823, "a100_raja_s": 16.8378, "a100_cuda_s": 14.6573}
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_11274_amd", "csrc", "tpfa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tpfa_jacobian_fp64_512x512x256_traffic.txt")
@@ -98,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="fp64,fp32,res,batched,adjoint,paper10,cpu")
+    ap.add_argument("--sections", default="fp64,fp32,res,newton,batched,adjoint,paper10,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -216,6 +223,49 @@ def main():
             out.setdefault("residual", {})["fp32"] = rate(tm.ms, KA, BYTES_FP32_R)
             log(f"fp32 residual: {out['residual']['fp32']}")
         del r, J, dps, kx32
+        torch.cuda.empty_cache()
+
+    # ----------------------- Newton step operators: backward-Euler r and J v
+    if "newton" in sections:
+        bf = geomodel.be_fields(g, 9)
+        phi64, step = up(bf["phi"]), up(bf["dp_step"])
+        v64 = up(bf["v"])
+        p64 = (pref[:, None, None] + noise[0]).contiguous()
+        pn64 = p64 - step
+        acc64 = dict(phi=phi64, p_prev=pn64, dt=bf["dt"], cr=bf["cr"])
+        kw = dict(seal=seal, ry=geo.ry, rz=geo.rz)
+        r = torch.empty(g.shape, dtype=torch.float64, device=dev)
+        jv = torch.empty_like(r)
+        res = {}
+        for name, fn, nbytes in (
+                ("fp64_residual_be", lambda: tp.residual_be(g, fl, kx64, p64, acc64, out=r, **kw),
+                 BYTES_FP64_RBE),
+                ("fp64_jvp_be_with_r", lambda: tp.jvp(g, fl, kx64, p64, v64, accum=acc64,
+                                                      want_r=True, out=jv, r_out=r, **kw),
+                 BYTES_FP64_JVP + 8),
+                ("fp64_jvp_be", lambda: tp.jvp(g, fl, kx64, p64, v64, accum=acc64, out=jv, **kw),
+                 BYTES_FP64_JVP)):
+            for _ in range(W):
+                fn()
+            with Timer(torch) as tm:
+                for _ in range(KA):
+                    fn()
+            res[name] = rate(tm.ms, KA, nbytes)
+        del r, jv, p64, pn64
+        dp32, pn32 = noise[0].float(), (noise[0] - step).float()
+        acc32 = dict(phi=phi64.float(), p_prev=pn32, dt=bf["dt"], cr=bf["cr"])
+        k32, v32 = kx64.float(), v64.float()
+        jv32 = torch.empty(g.shape, dtype=torch.float32, device=dev)
+        for _ in range(W):
+            tp.jvp(g, fl, k32, dp32, v32, accum=acc32, pref=pref, out=jv32, **kw)
+        with Timer(torch) as tm:
+            for _ in range(KA):
+                tp.jvp(g, fl, k32, dp32, v32, accum=acc32, pref=pref, out=jv32, **kw)
+        res["fp32_jvp_be"] = rate(tm.ms, KA, BYTES_FP32_JVP)
+        res["stored_J_spmv_bytes_per_cell_fp64"] = BYTES_SPMV_FP64
+        out["newton"] = res
+        log(f"newton: {res}")
+        del phi64, step, v64, dp32, pn32, acc32, k32, v32, jv32
         torch.cuda.empty_cache()
 
     # streaming-copy ceiling of this machine (torch copy kernel, context only)

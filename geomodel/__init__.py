@@ -211,7 +211,7 @@ def random_small(seed: int, nx: int, ny: int, nz: int, *, sigma: float = 1.0,
                 seed=seed, ry=ry, rz=rz, seal_prob=seal_prob, noise_seeds=(None,))
 
 
-# The paper's own workloads (Sec. 6, weak-scaling table): Nx x Ny x 246 meshes
+# The paper's own workloads (Sec. 7, weak-scaling table): Nx x Ny x 246 meshes
 # from 200 x 200 up to the full 750 x 994 fabric, residual only, 10 fluxes per
 # cell, FP32.
 PAPER10_SHAPES = ((200, 200, 246), (400, 400, 246), (600, 600, 246), (750, 600, 246),

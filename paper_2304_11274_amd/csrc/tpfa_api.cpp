@@ -83,15 +83,19 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
   return TPFA_OK;
 }
 
-// Launch-shape defaults from a tile x z-chunk sweep on MI355X (512x512x256):
-// the Jacobian and residual kernels run best with 64x8 tiles, the
-// vector-Jacobian product (more registers) with 64x4; narrow grids take
-// narrower tiles.
-int default_tile(const tpfa_grid_t &g, tpfa::Mode mode) {
+// Launch-shape defaults from tile x z-chunk sweeps on MI355X (512x512x256 and
+// 750x994x246): the Jacobian and the FP32 residual run best with 64x8 tiles,
+// the vector-Jacobian / Jacobian-vector products (more registers) and the FP64
+// residual (shared faces, more LDS) with 64x4, the 10-flux stencil with 128x4
+// on grids at least 128 cells wide; narrow grids take narrower tiles.
+int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
   const int b = tpfa::base_mode(mode);
-  return b == tpfa::MODE_VJP || b == tpfa::MODE_JVP || mode == tpfa::MODE_RES10 ? 0 : 3;
+  if (mode == tpfa::MODE_RES10) return g.nx >= 128 ? 4 : 0;
+  if (b == tpfa::MODE_VJP || b == tpfa::MODE_JVP) return 0;
+  if (b == tpfa::MODE_RESIDUAL && prec == TPFA_FP64) return 0;
+  return 3;
 }
 
 int default_kz(tpfa::Mode mode) {
@@ -156,9 +160,9 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
 
 namespace {
 
-int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, const tpfa_launch_t *launch,
-                   int &tile, int &kz, int &flags) {
-  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g, mode);
+int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
+                   const tpfa_launch_t *launch, int &tile, int &kz, int &flags) {
+  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g, mode, prec);
   kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode);
   flags = launch ? launch->flags : 0;
   return TPFA_OK;
@@ -168,7 +172,7 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
   int tile, kz, flags;
-  resolve_launch(*g, mode, launch, tile, kz, flags);
+  resolve_launch(*g, mode, prec, launch, tile, kz, flags);
   // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
   tpfa::Args b;
   tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
@@ -457,7 +461,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       int tile, kz, flags;
       resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                           : tpfa::MODE_RESIDUAL,
-                     &md.launch, tile, kz, flags);
+                     prec, &md.launch, tile, kz, flags);
       if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +

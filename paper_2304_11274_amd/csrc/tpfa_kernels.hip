@@ -392,6 +392,10 @@ struct Tile {
   static constexpr int NT = TX * TY;          // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
   static constexpr int HC = (NH + NT - 1) / NT;  // halo cells staged per thread
+  // Halo cells are loaded one plane ahead; the FP32 Jacobian (short planes,
+  // few registers) loads them two planes ahead, which measured faster on
+  // MI355X there and slower everywhere else.
+  static constexpr bool HALO2 = FP32 && BASE == MODE_JACOBIAN;
 
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
@@ -545,12 +549,16 @@ struct Tile {
   __device__ __forceinline__ void step(int k, const Cell<S> &c0, const Props<S> &d0,
                                        const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
                                        const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
-                                       const Face<S> &zm, Face<S> &zp) const {
+                                       Cell<S> (&h2)[HC], const Face<S> &zm, Face<S> &zp) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
     const S xk = xoff(k);
     if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
-    if (k + 1 < ke) load_halo(h1, k + 1);
+    if (HALO2) {
+      if (k + 2 < ke) load_halo(h2, k + 2);
+    } else if (k + 1 < ke) {
+      load_halo(h1, k + 1);
+    }
 
     // stage plane k: own cell and halo cell (absent cells stage zeros, which
     // make every face towards them closed: T = 0)
@@ -687,13 +695,17 @@ struct Tile {
   __device__ __forceinline__ void step_share(int k, const Cell<S> &c0, const Props<S> &d0,
                                              const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
                                              const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
-                                             const Face<S> &zm, Face<S> &zp,
+                                             Cell<S> (&h2)[HC], const Face<S> &zm, Face<S> &zp,
                                              Pending<S> &pd) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
     const S xk = xoff(k);
     if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
-    if (k + 1 < ke) load_halo(h1, k + 1);
+    if (HALO2) {
+      if (k + 2 < ke) load_halo(h2, k + 2);
+    } else if (k + 1 < ke) {
+      load_halo(h1, k + 1);
+    }
 
     s_p[b + ol] = c0.p;
     s_k[b + ol] = c0.k;
@@ -753,25 +765,30 @@ struct Tile {
 template <class S, int MODE, int TX, int TY>
 __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
   const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem);
-  // own column at planes k, k+1, k+2, halo cell at k, k+1, z faces (k-1,k), (k,k+1)
+  // own column at planes k, k+1, k+2, halo cell at k, k+1 (and k+2 with HALO2),
+  // z faces (k-1,k), (k,k+1)
   using T = Tile<S, MODE, TX, TY>;
-  Cell<S> c0{}, c1{}, c2{}, h0[T::HC]{}, h1[T::HC]{};
+  Cell<S> c0{}, c1{}, c2{}, h0[T::HC]{}, h1[T::HC]{}, h2[T::HC]{};
   Props<S> d0{}, d1{};
   Face<S> z0{}, z1{};
   t.load(c0, kb);
   t.load_halo(h0, kb);
+  if (T::HALO2 && kb + 1 < t.ke) t.load_halo(h1, kb + 1);
   if (kb + 1 < t.nz) t.load(c1, kb + 1);
   d0 = props(c0.p, t.xoff(kb), a);
   z0 = t.first_zface(c0, d0);
   if constexpr (T::SHARE) {
     Pending<S> pd{};
     for (int k = kb; k < t.ke; ++k) {
-      t.step_share(k, c0, d0, c1, d1, c2, h0, h1, z0, z1, pd);
+      t.step_share(k, c0, d0, c1, d1, c2, h0, h1, h2, z0, z1, pd);
       c0 = c1;
       d0 = d1;
       c1 = c2;
 #pragma unroll
-      for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
+      for (int q = 0; q < T::HC; ++q) {
+        h0[q] = h1[q];
+        if (T::HALO2) h1[q] = h2[q];
+      }
       z0 = z1;
     }
     // the last plane's upper-cell fluxes
@@ -779,12 +796,15 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
     t.finish(t.ke - 1, ((t.ke - 1 - kb) & 1) * T::HW, pd);
   } else {
     for (int k = kb; k < t.ke; ++k) {
-      t.step(k, c0, d0, c1, d1, c2, h0, h1, z0, z1);
+      t.step(k, c0, d0, c1, d1, c2, h0, h1, h2, z0, z1);
       c0 = c1;
       d0 = d1;
       c1 = c2;
 #pragma unroll
-      for (int q = 0; q < T::HC; ++q) h0[q] = h1[q];
+      for (int q = 0; q < T::HC; ++q) {
+        h0[q] = h1[q];
+        if (T::HALO2) h1[q] = h2[q];
+      }
       z0 = z1;
     }
   }
