@@ -270,3 +270,57 @@ def be_fields(grid: Grid, seed: int, step_amp: float = 5e4) -> dict:
             "dp_step": np.random.default_rng(s_step).uniform(-step_amp, step_amp, grid.shape),
             "v": np.random.default_rng(s_v).standard_normal(grid.shape),
             "dt": BE_DT, "cr": BE_CR}
+
+
+# Spatially correlated permeability and planar fault barriers (structured
+# geomodels beyond i.i.d. fields).
+
+def correlated_logk(grid: Grid, seed: int, sigma: float = 1.5,
+                    corr_len=(8.0, 8.0, 2.0)) -> np.ndarray:
+    """ln kx with a Gaussian covariance: white noise filtered by a Gaussian
+    kernel of standard deviation ``corr_len`` cells along (x, y, z) through
+    the FFT (periodic), rescaled to unit variance, times sigma, plus
+    ln 1e-13."""
+    w = np.random.default_rng(seed).standard_normal(grid.shape)
+    f = np.fft.rfftn(w)
+    kz = np.fft.fftfreq(grid.nz)[:, None, None]
+    ky = np.fft.fftfreq(grid.ny)[None, :, None]
+    kx = np.fft.rfftfreq(grid.nx)[None, None, :]
+    lx, ly, lz = corr_len
+    f *= np.exp(-2.0 * np.pi ** 2 * ((kx * lx) ** 2 + (ky * ly) ** 2 + (kz * lz) ** 2))
+    x = np.fft.irfftn(f, s=grid.shape, axes=(0, 1, 2))
+    x /= x.std() if x.std() > 0 else 1.0
+    return LN_K_MEDIAN + sigma * x
+
+
+def fault_seals(grid: Grid, *, x_fault: Optional[int] = None, y_fault: Optional[int] = None,
+                z_barrier: Optional[int] = None, gaps: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Seal bits of planar barriers: every +x face of the cells at i = x_fault
+    (a vertical fault normal to x), every +y face at j = y_fault, every +z face
+    at k = z_barrier (a shale layer); a fraction ``gaps`` of each barrier's
+    faces is left open at random."""
+    seal = np.zeros(grid.shape, np.uint8)
+    rng = np.random.default_rng(seed)
+    for bit, idx, axis_len in ((0, x_fault, grid.nx), (1, y_fault, grid.ny), (2, z_barrier, grid.nz)):
+        if idx is None or not (0 <= idx < axis_len - 1):
+            continue
+        sl = [slice(None)] * 3
+        sl[2 - bit] = idx
+        face = np.ones(seal[tuple(sl)].shape, bool)
+        if gaps > 0:
+            face &= rng.random(face.shape) >= gaps
+        seal[tuple(sl)] |= (face.astype(np.uint8) << np.uint8(bit))
+    return seal
+
+
+def faulted(seed: int = 12, nx: int = 96, ny: int = 80, nz: int = 40) -> Geomodel:
+    """Correlated ln k (sigma 1.5, correlation 8 x 8 x 2 cells), kz = 0.1 kx, a
+    vertical fault at i = nx/3 and a shale barrier at k = nz/2 with 10% gaps,
+    plus 0.5% random seals; one pressure field."""
+    grid = Grid(nx, ny, nz)
+    geo = draw(f"faulted{nx}x{ny}x{nz}", grid, sigma=1.5, seed=seed, ry=1.0, rz=0.1,
+               seal_prob=0.005)
+    geo.logk = correlated_logk(grid, seed + 1)
+    geo.kx = np.exp(geo.logk)
+    geo.seal |= fault_seals(grid, x_fault=nx // 3, z_barrier=nz // 2, gaps=0.1, seed=seed + 2)
+    return geo

@@ -70,14 +70,24 @@ typedef struct {
   double rho0, cf, p0, mu;
 } tpfa_fluid_t;
 
-/* Rock: kx (m^2, dtype of the precision) is required. ky and kz must be NULL:
-   the y and z permeabilities are ry*kx and rz*kx (ry, rz >= 0). seal may be
+/* Rock, in one of two forms.
+   Permeability form: kx (m^2, dtype of the precision) is required. ky and kz
+   must be NULL: the y and z permeabilities are ry*kx and rz*kx (ry, rz >= 0)
+   and each face gets the two-point harmonic transmissibility. seal may be
    NULL; bit a (0, 1, 2 = x, y, z) of seal[idx] closes the face between the
-   cell and its +a neighbour (bits on domain-boundary faces are ignored). */
+   cell and its +a neighbour (bits on domain-boundary faces are ignored).
+   Transmissibility form: tx, ty, tz (m^3, dtype of the precision) give the
+   transmissibility of the face between cell idx and its +x, +y, +z neighbour
+   directly (the face-centred data the paper stores with each cell, Sec. 5,
+   here once per face); entries on the last layer along a direction are
+   ignored and T = 0 closes a face. Then kx, ky, kz and seal must be NULL and
+   ry, rz are ignored. Supported by every entry point except
+   tpfa_residual_vjp and the batch (TPFA_ERR_UNSUPPORTED). */
 typedef struct {
   const void *kx, *ky, *kz;
   double ry, rz;
   const uint8_t *seal;
+  const void *tx, *ty, *tz;
 } tpfa_rock_t;
 
 /* State: TPFA_FP64 -> p is absolute pressure (double, Pa), pref ignored.

@@ -85,6 +85,14 @@ def _load():
         lib.oracle_eval_be_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                           C.c_double, C.c_double, vp, vp, vp, vp, C.c_double,
                                           C.c_double, vp, C.c_double, vp]
+        lib.oracle_eval_general.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                             C.c_double, C.c_double] + [vp] * 9 +
+                                            [C.c_double, C.c_double] + [vp] * 5)
+        lib.oracle_eval_general_cs.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                                C.c_double, C.c_double] + [vp] * 9 +
+                                               [C.c_double, C.c_double, vp, C.c_double, vp])
+        lib.oracle_eval_general.restype = C.c_int
+        lib.oracle_eval_general_cs.restype = C.c_int
         for fn in ("oracle_eval", "oracle_rows", "oracle_eval_ld", "oracle_eval_cs",
                    "oracle_hydrostatic", "oracle_residual10", "oracle_residual10_cs",
                    "oracle_eval_be", "oracle_eval_be_cs"):
@@ -277,6 +285,53 @@ def evaluate_be_cs(grid, fluid, kx, p, phi, p_prev, dt, cr, vp, *, ry=1.0, rz=1.
                                    float(dt), float(cr), _ptr(vp), float(h), _ptr(im))
     if rc != 0:
         raise ValueError("oracle_eval_be_cs rejected its arguments")
+    return im / h
+
+
+def _general_args(grid, p, kx, trans, seal, diag, accum, ry, rz):
+    shape = (grid.nz, grid.ny, grid.nx)
+    tx, ty, tz = (None, None, None) if trans is None else trans
+    tne, tse = (None, None) if diag is None else diag
+    acc = accum or {}
+    arrs = [_arr(a, np.float64, shape) for a in (kx, tx, ty, tz, tne, tse, p,
+                                                   acc.get("phi"), acc.get("p_prev"))]
+    seal = _arr(seal, np.uint8, shape)
+    kx, tx, ty, tz, tne, tse, p, phi, pn = arrs
+    head = [_ptr(kx), float(ry), float(rz), _ptr(seal), _ptr(tx), _ptr(ty), _ptr(tz), _ptr(tne),
+            _ptr(tse), _ptr(p), _ptr(phi), _ptr(pn), float(acc.get("dt", 1.0)),
+            float(acc.get("cr", 0.0))]
+    return shape, head, arrs + [seal]
+
+
+def evaluate_general(grid, fluid, p, *, kx=None, trans=None, ry=1.0, rz=1.0, seal=None,
+                     diag=None, accum=None, v=None, want=("r",)) -> dict:
+    """The residual in any input form: permeability (kx, ry, rz, seal) or face
+    transmissibilities ``trans`` = (tx, ty, tz); optional diagonal faces
+    ``diag`` = (tne, tse); optional accumulation ``accum`` = dict(phi, p_prev,
+    dt, cr). Outputs any of r, J, jv (needs v), scale."""
+    shape, head, keep = _general_args(grid, p, kx, trans, seal, diag, accum, ry, rz)
+    v = _arr(v, np.float64, shape)
+    bufs = {}
+    for key, sh in (("r", shape), ("J", (7,) + shape), ("jv", shape), ("scale", (2,) + shape)):
+        bufs[key] = np.empty(sh, np.float64) if key in want else None
+    rc = _load().oracle_eval_general(C.byref(_g(grid)), C.byref(_f(fluid)), *head, _ptr(v),
+                                     _ptr(bufs["r"]), _ptr(bufs["J"]), _ptr(bufs["jv"]),
+                                     _ptr(bufs["scale"]))
+    if rc != 0:
+        raise ValueError("oracle_eval_general rejected its arguments")
+    return {k: bufs[k] for k in want}
+
+
+def evaluate_general_cs(grid, fluid, p, vp, *, kx=None, trans=None, ry=1.0, rz=1.0, seal=None,
+                        diag=None, accum=None, h=1e-20) -> np.ndarray:
+    """Complex-step J vp of the general residual."""
+    shape, head, keep = _general_args(grid, p, kx, trans, seal, diag, accum, ry, rz)
+    vp = _arr(vp, np.float64, shape)
+    im = np.empty(shape)
+    rc = _load().oracle_eval_general_cs(C.byref(_g(grid)), C.byref(_f(fluid)), *head, _ptr(vp),
+                                        float(h), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_eval_general_cs rejected its arguments")
     return im / h
 
 

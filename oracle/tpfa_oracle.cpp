@@ -93,6 +93,9 @@ struct Problem {
   const int8_t* force;         // NULL or [3][N]: +1 / -1 forces the lower / upper cell upwind
   const S* tne = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j+1) of each cell
   const S* tse = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j-1) of each cell
+  const S* tx = nullptr;       // NULL, or the transmissibilities of the faces towards +x, +y, +z
+  const S* ty = nullptr;       //   given per cell (replace the harmonic average of k, the ratios
+  const S* tz = nullptr;       //   and the seal bits)
   const S* phi = nullptr;      // NULL or phi_ref per cell: adds the accumulation term of Eq. (2)
   const S* p_prev = nullptr;   // pressure of the previous time level (with phi)
   double dt = 0.0, cr = 0.0;   // time step (s) and rock compressibility (1/Pa) (with phi)
@@ -176,6 +179,11 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
     const int64_t right = side > 0 ? L : K;
     // the right end lies 1 + nx (face towards +y) or 1 - nx (towards -y) further in index
     out.T = (right - left == 1 + g.nx) ? pb.tne[left] : pb.tse[left];
+  } else if (pb.tx) {
+    // transmissibility given per face, stored on the face's lower cell
+    out.kK = out.kL = S(0);
+    const S* t = axis == 0 ? pb.tx : axis == 1 ? pb.ty : pb.tz;
+    out.T = t[lo];
   } else {
     // transmissibility (harmonic two-point form, closed if sealed)
     out.kK = perm(pb, axis, K);
@@ -403,6 +411,88 @@ int oracle_rows(const oracle_grid* g, const oracle_fluid* f, const double* kx,
     if (cells[q] < 0 || cells[q] >= N) return -1;
   Problem<double> pb{g, f, p, kx, ky, kz, ry, rz, seal, force};
   rows(pb, cells, n, r, J, scale, dphi);
+  return 0;
+}
+
+// Every input form at once: permeability (kx, ry, rz, seal) or given face
+// transmissibilities (tx, ty, tz: then kx and seal are NULL); optional
+// diagonal faces (tne, tse: the 10-flux stencil); optional accumulation term
+// (phi non-NULL: phi, p_prev, dt, cr); outputs r, J, jv (needs v) and scale
+// each optional.
+int oracle_eval_general(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                        double ry, double rz, const uint8_t* seal, const double* tx,
+                        const double* ty, const double* tz, const double* tne,
+                        const double* tse, const double* p, const double* phi,
+                        const double* p_prev, double dt, double cr, const double* v, double* r,
+                        double* J, double* jv, double* scale) {
+  const bool tin = tx || ty || tz;
+  if (!g || !f || !p || (!kx && !tin)) return -1;
+  if (tin && (!tx || !ty || !tz || kx || seal)) return -1;
+  if (!(g->nx > 0 && g->ny > 0 && g->nz > 0 && g->dx > 0 && g->dy > 0 && g->dz > 0 &&
+        f->mu > 0))
+    return -1;
+  if ((tne != nullptr) != (tse != nullptr)) return -1;
+  if (phi && (!p_prev || !(dt > 0.0))) return -1;
+  if (jv && !v) return -1;
+  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.tx = tx;
+  pb.ty = ty;
+  pb.tz = tz;
+  pb.tne = tne;
+  pb.tse = tse;
+  pb.phi = phi;
+  pb.p_prev = p_prev;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = r;
+  o.J = J;
+  o.v = v;
+  o.jv = jv;
+  o.scale = scale;
+  assemble(pb, o);
+  return 0;
+}
+
+// Complex-step J vp of the same general residual (transmissibilities and
+// porosity are real inputs).
+int oracle_eval_general_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                           double ry, double rz, const uint8_t* seal, const double* tx,
+                           const double* ty, const double* tz, const double* tne,
+                           const double* tse, const double* p, const double* phi,
+                           const double* p_prev, double dt, double cr, const double* vp,
+                           double h, double* r_im) {
+  const bool tin = tx || ty || tz;
+  if (!g || !f || !p || !vp || !r_im || (!kx && !tin)) return -1;
+  if (tin && (!tx || !ty || !tz || kx || seal)) return -1;
+  if (phi && (!p_prev || !(dt > 0.0))) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  auto widen = [N](const double* a) -> cplx* {
+    if (!a) return nullptr;
+    cplx* c = new cplx[N];
+    for (int64_t q = 0; q < N; ++q) c[q] = cplx(a[q], 0.0);
+    return c;
+  };
+  cplx* pc = new cplx[N];
+  for (int64_t q = 0; q < N; ++q) pc[q] = cplx(p[q], h * vp[q]);
+  cplx *kc = widen(kx), *xc = widen(tx), *yc = widen(ty), *zc = widen(tz), *nc = widen(tne),
+       *sc = widen(tse), *fc = widen(phi), *qc = widen(p_prev);
+  cplx* rc = new cplx[N];
+  Problem<cplx> pb{g, f, pc, kc, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.tx = xc;
+  pb.ty = yc;
+  pb.tz = zc;
+  pb.tne = nc;
+  pb.tse = sc;
+  pb.phi = fc;
+  pb.p_prev = qc;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t q = 0; q < N; ++q) r_im[q] = rc[q].imag();
+  for (cplx* a : {pc, kc, xc, yc, zc, nc, sc, fc, qc, rc}) delete[] a;
   return 0;
 }
 

@@ -41,7 +41,8 @@ class Fluid(C.Structure):
 
 class Rock(C.Structure):
     _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p),
-                ("ry", C.c_double), ("rz", C.c_double), ("seal", C.c_void_p)]
+                ("ry", C.c_double), ("rz", C.c_double), ("seal", C.c_void_p),
+                ("tx", C.c_void_p), ("ty", C.c_void_p), ("tz", C.c_void_p)]
 
 
 class State(C.Structure):

@@ -65,12 +65,21 @@ def _need(t, name, dtype, n, device):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _inputs(grid, kx, p, seal, pref):
+def _inputs(grid, kx, p, seal, pref, trans=None):
     n = int(grid.nx) * int(grid.ny) * int(grid.nz)
     prec = _prec(p)
     dt = p.dtype
     dev = p.device
     _need(p, "p", dt, n, None)
+    if trans is not None:
+        if kx is not None or seal is not None:
+            raise ValueError("give either kx (and seal) or trans=(tx, ty, tz), not both")
+        for name, t in zip(("tx", "ty", "tz"), trans):
+            if t is None:
+                raise ValueError(f"trans needs {name}")
+            _need(t, name, dt, n, dev)
+    elif kx is None:
+        raise ValueError("kx is required (or trans=(tx, ty, tz))")
     _need(kx, "kx", dt, n, dev)
     _need(seal, "seal", torch.uint8, n, dev)
     if prec == L.TPFA_FP32:
@@ -80,19 +89,21 @@ def _inputs(grid, kx, p, seal, pref):
     return n, prec, dt, dev
 
 
-def _rock(kx, seal, ry, rz) -> L.Rock:
-    return L.Rock(_ptr(kx), None, None, float(ry), float(rz), _ptr(seal))
+def _rock(kx, seal, ry, rz, trans=None) -> L.Rock:
+    tx, ty, tz = trans if trans is not None else (None, None, None)
+    return L.Rock(_ptr(kx), None, None, float(ry), float(rz), _ptr(seal), _ptr(tx), _ptr(ty),
+                  _ptr(tz))
 
 
 def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
-             tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+             trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                              C.byref(_rock(kx, seal, ry, rz)),
+                              C.byref(_rock(kx, seal, ry, rz, trans)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
                               _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return r
@@ -104,10 +115,10 @@ def _launch_ref(tile, kz_chunk, xcd_remap):
 
 
 def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r=True,
-             r_out=None, J_out=None, tile=None, kz_chunk=None, xcd_remap=False):
+             r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     r = None
     if want_r:
         r = r_out if r_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -116,7 +127,7 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r
     _need(J, "J_out", dt, 7 * n, dev)
     lib = L.load()
     L.check(lib.tpfa_jacobian(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                              C.byref(_rock(kx, seal, ry, rz)),
+                              C.byref(_rock(kx, seal, ry, rz, trans)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
                               _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return r, J
@@ -155,10 +166,10 @@ def _accum(accum, dt_, n, dev):
 
 
 def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
-                tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+                trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
     the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     acc = _accum(accum, dt, n, dev)
     if acc is None:
         raise ValueError("residual_be needs accum")
@@ -166,7 +177,7 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                 C.byref(_rock(kx, seal, ry, rz)),
+                                 C.byref(_rock(kx, seal, ry, rz, trans)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)),
             lib)
@@ -174,10 +185,10 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
 
 
 def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0,
-                want_r=True, r_out=None, J_out=None, tile=None, kz_chunk=None,
+                want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
                 xcd_remap=False):
     """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     acc = _accum(accum, dt, n, dev)
     if acc is None:
         raise ValueError("jacobian_be needs accum")
@@ -189,7 +200,7 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     _need(J, "J_out", dt, 7 * n, dev)
     lib = L.load()
     L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                 C.byref(_rock(kx, seal, ry, rz)),
+                                 C.byref(_rock(kx, seal, ry, rz, trans)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap),
                                  _stream(dev)), lib)
@@ -197,10 +208,10 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
 
 
 def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0,
-        want_r=False, out=None, r_out=None, tile=None, kz_chunk=None, xcd_remap=False):
+        want_r=False, out=None, r_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
     """Matrix-free J v of the flux residual, or of the backward-Euler residual
     when ``accum`` is given; returns (jv, r or None)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     _need(v, "v", dt, n, dev)
     acc = _accum(accum, dt, n, dev)
     jv = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -211,24 +222,24 @@ def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1
         _need(r, "r_out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_jvp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                         C.byref(_rock(kx, seal, ry, rz)), C.byref(L.State(_ptr(p), _ptr(pref))),
+                         C.byref(_rock(kx, seal, ry, rz, trans)), C.byref(L.State(_ptr(p), _ptr(pref))),
                          None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
                          _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return jv, r
 
 
 def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
-               tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+               trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
     faces with caller-supplied transmissibilities tne, tse)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     _need(tne, "tne", dt, n, dev)
     _need(tse, "tse", dt, n, dev)
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual10(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                C.byref(_rock(kx, seal, ry, rz)),
+                                C.byref(_rock(kx, seal, ry, rz, trans)),
                                 C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
                                 _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap),
                                 _stream(dev)), lib)

@@ -67,11 +67,18 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
   if (!st) return fail(TPFA_ERR_NULL, "state is NULL");
   if (prec != TPFA_FP64 && prec != TPFA_FP32)
     return fail(TPFA_ERR_PARAM, "unknown precision");
-  if (!rk->kx) return fail(TPFA_ERR_NULL, "rock.kx is NULL");
-  if (rk->ky || rk->kz)
-    return fail(TPFA_ERR_UNSUPPORTED, "ky/kz arrays are not supported; use ry/rz ratios");
-  if (!(rk->ry >= 0) || !(rk->rz >= 0) || !is_finite(rk->ry) || !is_finite(rk->rz))
-    return fail(TPFA_ERR_PARAM, "ry and rz must be finite and >= 0");
+  if (rk->tx || rk->ty || rk->tz) {
+    if (!rk->tx || !rk->ty || !rk->tz)
+      return fail(TPFA_ERR_NULL, "rock.tx, rock.ty and rock.tz are all required");
+    if (rk->kx || rk->ky || rk->kz || rk->seal)
+      return fail(TPFA_ERR_PARAM, "give either kx (and seal) or tx/ty/tz, not both");
+  } else {
+    if (!rk->kx) return fail(TPFA_ERR_NULL, "rock.kx is NULL");
+    if (rk->ky || rk->kz)
+      return fail(TPFA_ERR_UNSUPPORTED, "ky/kz arrays are not supported; use ry/rz ratios");
+    if (!(rk->ry >= 0) || !(rk->rz >= 0) || !is_finite(rk->ry) || !is_finite(rk->rz))
+      return fail(TPFA_ERR_PARAM, "ry and rz must be finite and >= 0");
+  }
   if (!st->p) return fail(TPFA_ERR_NULL, "state.p is NULL");
   if (prec == TPFA_FP32 && !st->pref)
     return fail(TPFA_ERR_UNSUPPORTED, "the FP32 precision form needs state.pref");
@@ -154,6 +161,9 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.pref = st.pref;
   a.kx = rk.kx;
   a.seal = rk.seal;
+  a.tx = rk.tx;
+  a.ty = rk.ty;
+  a.tz = rk.tz;
 }
 
 }  // namespace tpfa
@@ -192,8 +202,9 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   b.crf = a.crf;
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
-  const hipError_t e =
-      tpfa::launch_march(prec, mode, tile, b, static_cast<hipStream_t>(stream));
+  // the transmissibility form runs the same modes with the input flag
+  const tpfa::Mode m = rk->tx ? static_cast<tpfa::Mode>(mode | tpfa::MODE_TRANS) : mode;
+  const hipError_t e = tpfa::launch_march(prec, m, tile, b, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
 }
@@ -246,6 +257,8 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
     if (rc) return rc;
     if (!w) return fail(TPFA_ERR_NULL, "w is NULL");
     if (!grad_p && !grad_logk) return fail(TPFA_ERR_NULL, "grad_p and grad_logk are both NULL");
+    if (rock->tx)
+      return fail(TPFA_ERR_UNSUPPORTED, "the vector-Jacobian product needs the permeability form");
     tpfa::Args a{};
     a.w = w;
     a.gp = grad_p;
@@ -454,6 +467,9 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       const tpfa_model_t &md = models[m];
       int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
       if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
+      if (md.rock.tx)
+        return fail(TPFA_ERR_UNSUPPORTED,
+                    "model " + std::to_string(m) + ": the batch needs the permeability form");
       if (mode == TPFA_BATCH_JACOBIAN && !md.J)
         return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": J is NULL");
       if (mode == TPFA_BATCH_RESIDUAL && !md.r)

@@ -21,14 +21,20 @@ enum Mode : int {
   MODE_JVP = 6,
   MODE_JVP_BE = 7
 };
+// Flag added to a mode: the face transmissibilities are inputs (tx, ty, tz)
+// instead of the harmonic average of kx.
+constexpr int MODE_TRANS = 8;
+constexpr int mode_kind(int m) { return m & 7; }
+constexpr bool has_trans(int m) { return (m & MODE_TRANS) != 0; }
 constexpr int base_mode(int m) {
-  return m == MODE_RESIDUAL_BE ? MODE_RESIDUAL
-         : m == MODE_JACOBIAN_BE ? MODE_JACOBIAN
-         : m == MODE_JVP_BE      ? MODE_JVP
-                                 : m;
+  return mode_kind(m) == MODE_RESIDUAL_BE   ? MODE_RESIDUAL
+         : mode_kind(m) == MODE_JACOBIAN_BE ? MODE_JACOBIAN
+         : mode_kind(m) == MODE_JVP_BE      ? MODE_JVP
+                                            : mode_kind(m);
 }
 constexpr bool has_accumulation(int m) {
-  return m == MODE_RESIDUAL_BE || m == MODE_JACOBIAN_BE || m == MODE_JVP_BE;
+  return mode_kind(m) == MODE_RESIDUAL_BE || mode_kind(m) == MODE_JACOBIAN_BE ||
+         mode_kind(m) == MODE_JVP_BE;
 }
 
 // Tile table. A workgroup owns a TX x TY column block of one model and marches
@@ -76,6 +82,9 @@ struct Args {
   const void *w;      // cotangent (VJP) or direction v (JVP)
   const void *phi;    // reference porosity per cell (backward-Euler modes)
   const void *pprev;  // pressure of the previous time level, in the form of p
+  const void *tx;    // transmissibility input: faces towards +x, +y, +z
+  const void *ty;
+  const void *tz;
   const void *tne;   // 10-flux stencil: diagonal transmissibilities
   const void *tse;
   void *r;

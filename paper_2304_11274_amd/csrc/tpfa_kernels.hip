@@ -55,6 +55,7 @@ struct Cell {
   S w;         // cotangent (vector-Jacobian product only)
   S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
   S phi, pn;   // reference porosity and previous-level pressure (backward-Euler modes)
+  S tx, ty, tz;  // transmissibilities of the +x, +y, +z faces (transmissibility input)
   uint32_t s;  // seal bits
 };
 
@@ -180,6 +181,16 @@ __device__ __forceinline__ Face<float> face_h(const Args &a, float A2, float kLo
   return f;
 }
 
+// x or y face with a given transmissibility (transmissibility input).
+template <bool DERIV, class S>
+__device__ __forceinline__ Face<S> face_ht(const Args &a, S T, S pLo, S pUp, S lamLo, S lamUp) {
+  Face<S> f;
+  const S dphi = pLo - pUp;
+  const S cf = sizeof(S) == 8 ? S(a.cf) : S(a.cff);
+  upwind<S, DERIV, false>(f, T, dphi, dphi >= S(0), lamLo, lamUp, cf, S(1), S(-1));
+  return f;
+}
+
 // z face between planes k (Lo) and k+1 (Up): dPhi = (p_Lo - p_Up) + rho_avg G.
 // For FP32 `dpref` = pref[k] - pref[k+1] and the potential is formed in FP64.
 __device__ __forceinline__ double zpot(double pLo, double pUp, double, double ra, const Args &a) {
@@ -192,10 +203,13 @@ __device__ __forceinline__ double zpot(float pLo, float pUp, double dpref, float
 
 template <bool DERIV, bool VJP, class S>
 __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open, S pLo, S pUp,
-                                          double dpref, Props<S> Lo, Props<S> Up) {
+                                          double dpref, Props<S> Lo, Props<S> Up,
+                                          bool tin = false, S Tin = S(0)) {
   Face<S> f;
   S T;
-  if constexpr (sizeof(S) == 8)
+  if (tin)
+    T = open ? Tin : S(0);
+  else if constexpr (sizeof(S) == 8)
     T = trans64<VJP>(a.a2z, kLo, kUp, open, f);
   else
     T = trans32<VJP>(a.a2zf, kLo, kUp, open, f);
@@ -231,11 +245,11 @@ constexpr int kMaxLds = 160 * 1024;
 // face) it measured slower on MI355X and the two-sided form is kept.
 template <class S, int MODE, int TX, int TY>
 constexpr int share_lds_bytes() {
-  return 2 * (TX + 2) * (TY + 2) * (int)sizeof(S) * (MODE == MODE_RES10 ? 7 : 5);
+  return 2 * (TX + 2) * (TY + 2) * (int)sizeof(S) * (mode_kind(MODE) == MODE_RES10 ? 7 : 5);
 }
 template <class S, int MODE, int TX, int TY>
 constexpr bool tile_shares() {
-  return (base_mode(MODE) == MODE_RESIDUAL || MODE == MODE_RES10) && sizeof(S) == 8 &&
+  return (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) && sizeof(S) == 8 &&
          share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
 
@@ -246,7 +260,8 @@ template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
   constexpr int B = base_mode(MODE);
-  constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) + (MODE == MODE_RES10 ? 2 : 0);
+  constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) +
+                         (mode_kind(MODE) == MODE_RES10 ? 2 : 0) + (has_trans(MODE) ? 1 : 0);
   return tile_shares<S, MODE, TX, TY>() ? share_lds_bytes<S, MODE, TX, TY>()
                                         : 2 * HW * ((int)sizeof(S) * arrays + 1);
 }
@@ -342,7 +357,7 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
       double r = acc;
 #pragma unroll
       for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
-      if constexpr (MODE == MODE_RES10) {
+      if constexpr (mode_kind(MODE) == MODE_RES10) {
         // diagonals -x-y, +x+y, +x-y, -x+y: the cell is the upper index of the
         // first and third, the lower of the second and fourth
 #pragma unroll
@@ -387,7 +402,8 @@ struct Tile {
   static constexpr bool DERIV = BASE == MODE_JACOBIAN || VJP || JVP;
   static constexpr bool FP32 = sizeof(S) == 4;
 
-  static constexpr bool R10 = MODE == MODE_RES10;
+  static constexpr bool R10 = mode_kind(MODE) == MODE_RES10;
+  static constexpr bool TIN = has_trans(MODE);  // transmissibilities are inputs
   static constexpr bool SHARE = tile_shares<S, MODE, TX, TY>();
   static constexpr int NT = TX * TY;          // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
@@ -400,11 +416,13 @@ struct Tile {
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
   S *s_fx, *s_fy, *s_fne, *s_fse;  // shared-face fluxes (residual-only modes)
+  S *s_ty;  // transmissibility input, two-sided layout only: ty (tx is staged in s_k)
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
   bool own;
   bool tnv, tsv;       // 10-flux: the own cell's +x+y / +x-y diagonal face exists
+  bool txv, tyv;       // transmissibility input: the own cell's +x / +y face exists
   int ol;
   uint32_t cb, cs;     // byte offset of the own cell within a plane (S elements / seal bytes)
   bool hv[HC];         // halo cell q lies in the domain
@@ -420,7 +438,8 @@ struct Tile {
     s_w = s_l + 2 * HW;
     s_tn = s_w + (NEEDW ? 2 * HW : 0);
     s_ts = s_tn + (R10 ? 2 * HW : 0);
-    s_s = reinterpret_cast<uint8_t *>(s_ts + (R10 ? 2 * HW : 0));
+    s_ty = s_ts + (R10 ? 2 * HW : 0);
+    s_s = reinterpret_cast<uint8_t *>(s_ty + (TIN ? 2 * HW : 0));
     s_fx = s_l + 2 * HW;
     s_fy = s_fx + 2 * HW;
     s_fne = s_fy + 2 * HW;
@@ -435,6 +454,8 @@ struct Tile {
     const int i = bx * TX + tx, j = by * TY + ty;
     own = i < nx && j < ny;
     tnv = own && i + 1 < nx && j + 1 < ny;
+    txv = own && i + 1 < nx;
+    tyv = own && j + 1 < ny;
     tsv = own && i + 1 < nx && j >= 1;
     const uint32_t col = own ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
     ol = (ty + 1) * W + tx + 1;
@@ -488,8 +509,14 @@ struct Tile {
   // and gets k = 0, which closes every face that touches it (T = 0).
   __device__ __forceinline__ void load_at(Cell<S> &c, int k, bool ok, uint32_t b, uint32_t bs) const {
     c.p = at(static_cast<const S *>(a.p), plane, k, b);
-    const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
-    c.k = ok ? kx : S(0);
+    if (TIN) {
+      c.k = S(0);
+      c.tx = at(static_cast<const S *>(a.tx), plane, k, b);
+      c.ty = at(static_cast<const S *>(a.ty), plane, k, b);
+    } else {
+      const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
+      c.k = ok ? kx : S(0);
+    }
     c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
     if (NEEDW) c.w = at(static_cast<const S *>(a.w), plane, k, b);
     if (R10) {
@@ -503,6 +530,12 @@ struct Tile {
   // cell's own presence decides; the own cell checks its (i+1, j+-1) partner.
   __device__ __forceinline__ void load(Cell<S> &c, int k) const {
     load_at(c, k, own, cb, cs);
+    if (TIN) {
+      // a face with a cell outside the domain does not exist
+      c.tx = txv ? c.tx : S(0);
+      c.ty = tyv ? c.ty : S(0);
+      c.tz = at(static_cast<const S *>(a.tz), plane, k, cb);
+    }
     if (ACC) {
       c.phi = at(static_cast<const S *>(a.phi), plane, k, cb);
       c.pn = at(static_cast<const S *>(a.pprev), plane, k, cb);
@@ -517,6 +550,10 @@ struct Tile {
     for (int q = 0; q < HC; ++q)
       if (hl[q] >= 0) {
         load_at(h[q], k, hv[q], hb[q], hs[q]);
+        if (TIN) {
+          h[q].tx = hv[q] ? h[q].tx : S(0);
+          h[q].ty = hv[q] ? h[q].ty : S(0);
+        }
         if (R10) {
           h[q].tn = hv[q] ? h[q].tn : S(0);
           h[q].ts = hv[q] ? h[q].ts : S(0);
@@ -537,7 +574,7 @@ struct Tile {
       load(pr, kb - 1);
       const Props<S> dp = props(pr.p, xoff(kb - 1), a);
       f = face_z<DERIV, VJP>(a, pr.k, cur.k, (pr.s & 4u) == 0u, pr.p, cur.p, dpref(kb - 1), dp,
-                             dcur);
+                             dcur, TIN, pr.tz);
       f.w = pr.w;
     }
     return f;
@@ -563,7 +600,8 @@ struct Tile {
     // stage plane k: own cell and halo cell (absent cells stage zeros, which
     // make every face towards them closed: T = 0)
     s_p[b + ol] = c0.p;
-    s_k[b + ol] = c0.k;
+    s_k[b + ol] = TIN ? c0.tx : c0.k;
+    if (TIN && !SHARE) s_ty[b + ol] = c0.ty;
     s_l[b + ol] = d0.lam;
     s_s[b + ol] = (uint8_t)c0.s;
     if (NEEDW) s_w[b + ol] = c0.w;
@@ -577,7 +615,8 @@ struct Tile {
       const Props<S> dh = props(h0[q].p, xk, a);
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
-      s_k[l] = h0[q].k;
+      s_k[l] = TIN ? h0[q].tx : h0[q].k;
+      if (TIN && !SHARE) s_ty[l] = h0[q].ty;
       s_l[l] = dh.lam;
       s_s[l] = (uint8_t)h0[q].s;
       if (NEEDW) s_w[l] = h0[q].w;
@@ -607,15 +646,21 @@ struct Tile {
       if (NEEDW) wn[n] = s_w[q];
       const uint32_t bit = 1u << axis;
       const S A2 = axis == 0 ? A2x : A2y;
-      if (n & 1)
+      if constexpr (TIN) {
+        // the face's transmissibility is stored on its lower cell
+        const S T = (n & 1) ? (axis == 0 ? c0.tx : c0.ty) : (axis == 0 ? kn : s_ty[q]);
+        f[n] = (n & 1) ? face_ht<DERIV>(a, T, c0.p, pn, d0.lam, ln)
+                       : face_ht<DERIV>(a, T, pn, c0.p, ln, d0.lam);
+      } else if (n & 1) {
         f[n] = face_h<DERIV, VJP>(a, A2, c0.k, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
-      else
+      } else {
         f[n] = face_h<DERIV, VJP>(a, A2, kn, c0.k, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
+      }
     }
     f[4] = zm;
     wn[4] = zm.w;
     zp = face_z<DERIV, VJP>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
-                            has_pz ? dpref(k) : 0.0, d0, d1);
+                            has_pz ? dpref(k) : 0.0, d0, d1, TIN, c0.tz);
     zp.w = c0.w;
     f[5] = zp;
     wn[5] = c1.w;
@@ -658,6 +703,7 @@ struct Tile {
                                         S tX) const {
     const S pn = s_p[y], ln = s_l[y];
     if (dir == kPX || dir == kPY) {
+      if constexpr (TIN) return face_ht<false>(a, tX, pX, pn, lX, ln).F;
       const S A2 = dir == kPX ? A2x : A2y;
       const uint32_t bit = dir == kPX ? 1u : 2u;
       return face_h<false, false>(a, A2, kX, s_k[y], (sX & bit) == 0u, pX, pn, lX, ln).F;
@@ -708,7 +754,8 @@ struct Tile {
     }
 
     s_p[b + ol] = c0.p;
-    s_k[b + ol] = c0.k;
+    s_k[b + ol] = TIN ? c0.tx : c0.k;
+    if (TIN && !SHARE) s_ty[b + ol] = c0.ty;
     s_l[b + ol] = d0.lam;
     S hlam[HC];
 #pragma unroll
@@ -717,7 +764,8 @@ struct Tile {
       hlam[q] = props(h0[q].p, xk, a).lam;
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
-      s_k[l] = h0[q].k;
+      s_k[l] = TIN ? h0[q].tx : h0[q].k;
+      if (TIN && !SHARE) s_ty[l] = h0[q].ty;
       s_l[l] = hlam[q];
     }
     __syncthreads();
@@ -727,11 +775,11 @@ struct Tile {
 
     d1 = props(c1.p, xoff(has_pz ? k + 1 : k), a);
     zp = face_z<false, false>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
-                              has_pz ? dpref(k) : 0.0, d0, d1);
+                              has_pz ? dpref(k) : 0.0, d0, d1, TIN, c0.tz);
 
     const int o = b + ol;
-    pd.fpx = fwd_face(kPX, o + 1, c0.p, c0.k, d0.lam, c0.s, S(0));
-    pd.fpy = fwd_face(kPY, o + W, c0.p, c0.k, d0.lam, c0.s, S(0));
+    pd.fpx = fwd_face(kPX, o + 1, c0.p, c0.k, d0.lam, c0.s, c0.tx);
+    pd.fpy = fwd_face(kPY, o + W, c0.p, c0.k, d0.lam, c0.s, c0.ty);
     s_fx[o] = pd.fpx;
     s_fy[o] = pd.fpy;
     if constexpr (R10) {
@@ -753,8 +801,8 @@ struct Tile {
       if (role == 0u) continue;
       const int l = b + hl[q];
       const Cell<S> &h = h0[q];
-      if (role & kPX) s_fx[l] = fwd_face(kPX, l + 1, h.p, h.k, hlam[q], h.s, S(0));
-      if (role & kPY) s_fy[l] = fwd_face(kPY, l + W, h.p, h.k, hlam[q], h.s, S(0));
+      if (role & kPX) s_fx[l] = fwd_face(kPX, l + 1, h.p, h.k, hlam[q], h.s, h.tx);
+      if (role & kPY) s_fy[l] = fwd_face(kPY, l + W, h.p, h.k, hlam[q], h.s, h.ty);
       if (R10 && (role & kNE)) s_fne[l] = fwd_face(kNE, l + W + 1, h.p, h.k, hlam[q], h.s, h.tn);
       if (R10 && (role & kSE)) s_fse[l] = fwd_face(kSE, l - W + 1, h.p, h.k, hlam[q], h.s, h.ts);
     }
@@ -968,7 +1016,7 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
                         hipStream_t st) {
   if (a.nblocks <= 0) return hipSuccess;
   if (prec == TPFA_FP64) {
-    switch (mode) {
+    switch ((int)mode) {
       case MODE_RESIDUAL: return launch_t<double, MODE_RESIDUAL>(tile, a, st);
       case MODE_JACOBIAN: return launch_t<double, MODE_JACOBIAN>(tile, a, st);
       case MODE_RES10: return launch_t<double, MODE_RES10>(tile, a, st);
@@ -976,10 +1024,20 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
       case MODE_JACOBIAN_BE: return launch_t<double, MODE_JACOBIAN_BE>(tile, a, st);
       case MODE_JVP: return launch_t<double, MODE_JVP>(tile, a, st);
       case MODE_JVP_BE: return launch_t<double, MODE_JVP_BE>(tile, a, st);
-      default: return launch_t<double, MODE_VJP>(tile, a, st);
+      case MODE_RESIDUAL | MODE_TRANS: return launch_t<double, MODE_RESIDUAL | MODE_TRANS>(tile, a, st);
+      case MODE_JACOBIAN | MODE_TRANS: return launch_t<double, MODE_JACOBIAN | MODE_TRANS>(tile, a, st);
+      case MODE_RES10 | MODE_TRANS: return launch_t<double, MODE_RES10 | MODE_TRANS>(tile, a, st);
+      case MODE_RESIDUAL_BE | MODE_TRANS:
+        return launch_t<double, MODE_RESIDUAL_BE | MODE_TRANS>(tile, a, st);
+      case MODE_JACOBIAN_BE | MODE_TRANS:
+        return launch_t<double, MODE_JACOBIAN_BE | MODE_TRANS>(tile, a, st);
+      case MODE_JVP | MODE_TRANS: return launch_t<double, MODE_JVP | MODE_TRANS>(tile, a, st);
+      case MODE_JVP_BE | MODE_TRANS: return launch_t<double, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
+      case MODE_VJP: return launch_t<double, MODE_VJP>(tile, a, st);
+      default: return hipErrorInvalidValue;
     }
   }
-  switch (mode) {
+  switch ((int)mode) {
     case MODE_RESIDUAL: return launch_t<float, MODE_RESIDUAL>(tile, a, st);
     case MODE_JACOBIAN: return launch_t<float, MODE_JACOBIAN>(tile, a, st);
     case MODE_RES10: return launch_t<float, MODE_RES10>(tile, a, st);
@@ -987,7 +1045,17 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
     case MODE_JACOBIAN_BE: return launch_t<float, MODE_JACOBIAN_BE>(tile, a, st);
     case MODE_JVP: return launch_t<float, MODE_JVP>(tile, a, st);
     case MODE_JVP_BE: return launch_t<float, MODE_JVP_BE>(tile, a, st);
-    default: return launch_t<float, MODE_VJP>(tile, a, st);
+    case MODE_RESIDUAL | MODE_TRANS: return launch_t<float, MODE_RESIDUAL | MODE_TRANS>(tile, a, st);
+    case MODE_JACOBIAN | MODE_TRANS: return launch_t<float, MODE_JACOBIAN | MODE_TRANS>(tile, a, st);
+    case MODE_RES10 | MODE_TRANS: return launch_t<float, MODE_RES10 | MODE_TRANS>(tile, a, st);
+    case MODE_RESIDUAL_BE | MODE_TRANS:
+      return launch_t<float, MODE_RESIDUAL_BE | MODE_TRANS>(tile, a, st);
+    case MODE_JACOBIAN_BE | MODE_TRANS:
+      return launch_t<float, MODE_JACOBIAN_BE | MODE_TRANS>(tile, a, st);
+    case MODE_JVP | MODE_TRANS: return launch_t<float, MODE_JVP | MODE_TRANS>(tile, a, st);
+    case MODE_JVP_BE | MODE_TRANS: return launch_t<float, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
+    case MODE_VJP: return launch_t<float, MODE_VJP>(tile, a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -221,3 +221,22 @@ def test_backward_euler_and_jvp_validation(lib):
     st.pref = None
     assert lib.tpfa_jvp(*args, None, L.TPFA_FP32, DUMMY, DUMMY, None, None,
                         None) == L.TPFA_ERR_UNSUPPORTED
+
+
+def test_transmissibility_form_validation(lib):
+    g, f, _, st = good()
+    args = lambda rk: (C.byref(g), C.byref(f), C.byref(rk), C.byref(st))  # noqa: E731
+    D = DUMMY.value
+    ok = L.Rock(None, None, None, 1.0, 1.0, None, D, D, D)
+    for rk, code in ((L.Rock(None, None, None, 1.0, 1.0, None, D, None, D), L.TPFA_ERR_NULL),
+                     (L.Rock(D, None, None, 1.0, 1.0, None, D, D, D), L.TPFA_ERR_PARAM),
+                     (L.Rock(None, None, None, 1.0, 1.0, D, D, D, D), L.TPFA_ERR_PARAM)):
+        assert lib.tpfa_residual(*args(rk), L.TPFA_FP64, None, None, None) == code
+    # valid rock, but the VJP and the batch need the permeability form
+    assert lib.tpfa_residual_vjp(*args(ok), L.TPFA_FP64, DUMMY, DUMMY, DUMMY, None,
+                                 None) == L.TPFA_ERR_UNSUPPORTED
+    m = (L.Model * 1)()
+    m[0] = L.Model(g, f, ok, st, DUMMY.value, DUMMY.value, L.Launch(-1, 0, 0))
+    out = C.c_void_p()
+    assert lib.tpfa_batch_create(m, 1, L.TPFA_FP64, L.TPFA_BATCH_JACOBIAN, C.byref(out),
+                                 None) == L.TPFA_ERR_UNSUPPORTED
