@@ -43,6 +43,7 @@ BYTES_FP64_R = 8 + 8 + 1 + 8               # 25
 BYTES_FP32_R = 4 + 4 + 1 + 4               # 13
 BYTES_FP32_VJP = 4 + 4 + 1 + 4 + 4 + 4     # dp, kx, seal, w -> grad_p, grad_logk = 21
 BYTES_FP32_R10 = 4 + 4 + 4 + 4 + 4         # dp, kx, tne, tse -> r (no seals) = 20
+BYTES_FP32_R10T = 4 + 5 * 4 + 4            # dp, tx, ty, tz, tne, tse -> r = 28
 # backward-Euler forms: + phi_ref, p_prev (and v in, J v out for the product)
 BYTES_FP64_RBE = 8 + 8 + 1 + 8 + 8 + 8      # p, kx, seal, phi, p_prev -> r = 41
 BYTES_FP64_JVP = BYTES_FP64_RBE + 8 + 8     # + v -> J v = 57
@@ -412,10 +413,37 @@ def main():
             log(f"paper10 {nx_}x{ny_}x{nz_}: {rows[-1]} (set up {time.time() - t0:.1f} s)")
             del kp, dpp, tn, ts, rp
             torch.cuda.empty_cache()
+        # the paper's data model: all ten transmissibilities stored per face
+        nx_, ny_, nz_ = geomodel.PAPER10_SHAPES[-1]
+        gp_ = geomodel.Grid(nx_, ny_, nz_)
+        tr = geomodel.paper10_trans(nx_, ny_, nz_)
+        noise_p = geomodel.paper10(nx_, ny_, nz_).noise[0]
+        prp = tp.hydrostatic(gp_, fl)
+        dpp = up(noise_p)
+        tdev = {k: up(v) for k, v in tr.items()}
+        del tr, noise_p
+        rp = torch.empty(gp_.shape, dtype=torch.float32, device=dev)
+        kw = dict(pref=prp, out=rp, trans=(tdev["tx"], tdev["ty"], tdev["tz"]))
+        for _ in range(W):
+            tp.residual10(gp_, fl, None, dpp, tdev["tne"], tdev["tse"], **kw)
+        with Timer(torch) as tm:
+            for _ in range(K10):
+                tp.residual10(gp_, fl, None, dpp, tdev["tne"], tdev["tse"], **kw)
+        t = tm.ms / K10
+        Np = gp_.ncell
+        trans_row = {"grid": [nx_, ny_, nz_], "cells": Np, "ms_per_application": t,
+                     "s_per_1000": t, "cells_per_s": Np / (t / 1e3),
+                     "bytes_per_cell": BYTES_FP32_R10T,
+                     "algorithmic_GBps": BYTES_FP32_R10T * Np / (t / 1e3) / 1e9,
+                     "hbm_frac": BYTES_FP32_R10T * Np / (t / 1e3) / 1e9 / HBM_PEAK_GBS}
+        log(f"paper10 with given transmissibilities: {trans_row}")
+        del dpp, tdev, rp
+        torch.cuda.empty_cache()
         out["paper10"] = {"workload": "FP32 10-flux residual (6 TPFA faces + 4 in-plane "
                                       "diagonal faces), 1000 applications per mesh, no seals",
                           "applications": K10, "bytes_per_cell": BYTES_FP32_R10,
-                          "meshes": rows, "paper_750x994x246": PAPER10_CONTEXT}
+                          "meshes": rows, "given_transmissibilities_750x994x246": trans_row,
+                          "paper_750x994x246": PAPER10_CONTEXT}
 
     # ------------------------------------------- CPU baseline: the FP64 oracle
     if "cpu" in sections:

@@ -243,6 +243,21 @@ def paper10(nx: int = 750, ny: int = 994, nz: int = 246, seed: int = 8) -> Geomo
     return geo
 
 
+def paper10_trans(nx: int = 750, ny: int = 994, nz: int = 246, seed: int = 18) -> dict:
+    """All ten transmissibilities of the paper's data model (Sec. 5), one per
+    face: tx, ty, tz with ln t ~ N(ln(a_d r_d 1e-13), 1) (a_x = a_y = 2 m,
+    a_z = 50 m, r_z = 0.1) and the diagonal tne, tse as in paper10; float32."""
+    grid = Grid(nx, ny, nz)
+    out = {}
+    medians = {"tx": grid.dy * grid.dz / grid.dx * 1e-13, "ty": grid.dx * grid.dz / grid.dy * 1e-13,
+               "tz": 0.1 * grid.dx * grid.dy / grid.dz * 1e-13, "tne": 1e-13, "tse": 1e-13}
+    for key, s in zip(("tx", "ty", "tz", "tne", "tse"), np.random.SeedSequence(seed).spawn(5)):
+        t = np.random.default_rng(s).standard_normal(grid.shape, dtype=np.float32)
+        t += np.float32(math.log(medians[key]))
+        out[key] = np.exp(t)
+    return out
+
+
 def diagonal_t(grid: Grid, seed: int, zero_prob: float = 0.1) -> tuple:
     """Diagonal transmissibility fields (tne, tse), float64, for small grids:
     ln t ~ N(ln 1e-13, 1), with a fraction ``zero_prob`` of faces closed (t = 0)."""

@@ -269,6 +269,12 @@ constexpr int tile_lds_bytes() {
 // Lower-cell faces a halo cell evaluates for the tile in the shared-face form.
 constexpr uint32_t kPX = 1, kPY = 2, kNE = 4, kSE = 8;
 
+// Fields a staged cell needs beyond p: a halo cell serves only the faces it
+// shares with the tile, so each side of the ring loads only what those faces
+// read (the own cell loads everything).
+constexpr uint32_t kNeedK = 1, kNeedSeal = 2, kNeedTx = 4, kNeedTy = 8, kNeedTn = 16,
+                   kNeedTs = 32, kNeedW = 64, kNeedAll = 127;
+
 // Fluxes of a plane whose residual is completed at the next plane: its own
 // lower-cell faces (+x, +y, +x+y, +x-y) and its two z faces.
 template <class S>
@@ -412,6 +418,10 @@ struct Tile {
   // few registers) loads them two planes ahead, which measured faster on
   // MI355X there and slower everywhere else.
   static constexpr bool HALO2 = FP32 && BASE == MODE_JACOBIAN;
+  // Per-side halo loads (each side of the ring loads only the fields its faces
+  // read) save memory traffic but cost predicated branches: on MI355X they pay
+  // off for the FP64 Jacobian only.
+  static constexpr bool PICK = !FP32 && BASE == MODE_JACOBIAN;
 
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
@@ -427,6 +437,7 @@ struct Tile {
   uint32_t cb, cs;     // byte offset of the own cell within a plane (S elements / seal bytes)
   bool hv[HC];         // halo cell q lies in the domain
   uint32_t hr[HC];     // shared faces: lower-cell faces halo cell q evaluates (kPX | kPY | kNE | kSE)
+  uint32_t hn[HC];     // fields halo cell q loads (kNeed*)
   int hl[HC];          // its LDS slot, -1 if the thread stages no q-th halo cell
   uint32_t hb[HC], hs[HC];
   S A2x, A2y;
@@ -467,25 +478,30 @@ struct Tile {
       const int h = tid + q * NT;
       int hi = -1, hj = -1, l = -1;
       uint32_t role = 0;  // faces into the tile whose lower cell is this halo cell
+      uint32_t need = 0;  // fields those faces (and the tile's faces towards it) read
       if (h < TX) {  // bottom row: +y (and +x+y) faces
         hi = bx * TX + h;
         hj = by * TY - 1;
         l = h + 1;
         role = kPY | (R10 ? kNE : 0u);
+        need = kNeedK | kNeedSeal | kNeedTy | kNeedTn | kNeedW;
       } else if (h < 2 * TX) {  // top row: +x-y faces
         hi = bx * TX + h - TX;
         hj = by * TY + TY;
         l = (TY + 1) * W + h - TX + 1;
         role = R10 ? kSE : 0u;
+        need = kNeedK | kNeedTs | kNeedW;
       } else if (h < 2 * TX + TY) {  // left column: +x (and both diagonal) faces
         hi = bx * TX - 1;
         hj = by * TY + h - 2 * TX;
         l = (h - 2 * TX + 1) * W;
         role = kPX | (R10 ? kNE | kSE : 0u);
+        need = kNeedK | kNeedSeal | kNeedTx | kNeedTn | kNeedTs | kNeedW;
       } else if (h < 2 * TX + 2 * TY) {  // right column: none (the tile's lower cells)
         hi = bx * TX + TX;
         hj = by * TY + h - 2 * TX - TY;
         l = (h - 2 * TX - TY + 1) * W + TX + 1;
+        need = kNeedK | kNeedW;
       } else if (h < NH) {  // corners (10-flux stencil)
         const int c = h - 2 * TX - 2 * TY;
         const int cx = c & 1, cy = c >> 1;
@@ -493,8 +509,10 @@ struct Tile {
         hj = cy ? by * TY + TY : by * TY - 1;
         l = (cy ? TY + 1 : 0) * W + (cx ? TX + 1 : 0);
         role = c == 0 ? kNE : c == 2 ? kSE : 0u;
+        need = c == 0 ? kNeedTn : c == 2 ? kNeedTs : 0u;
       }
       hr[q] = SHARE ? role : 0u;
+      hn[q] = need;
       hl[q] = l;
       hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
       const uint32_t hcol = hv[q] ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
@@ -507,21 +525,23 @@ struct Tile {
 
   // A cell outside the domain reads the plane's first cell (any finite value)
   // and gets k = 0, which closes every face that touches it (T = 0).
-  __device__ __forceinline__ void load_at(Cell<S> &c, int k, bool ok, uint32_t b, uint32_t bs) const {
+  // Fields outside `need` keep their previous (finite) values; nothing reads them.
+  __device__ __forceinline__ void load_at(Cell<S> &c, int k, bool ok, uint32_t b, uint32_t bs,
+                                          uint32_t need = kNeedAll) const {
     c.p = at(static_cast<const S *>(a.p), plane, k, b);
     if (TIN) {
       c.k = S(0);
-      c.tx = at(static_cast<const S *>(a.tx), plane, k, b);
-      c.ty = at(static_cast<const S *>(a.ty), plane, k, b);
-    } else {
+      if (need & kNeedTx) c.tx = at(static_cast<const S *>(a.tx), plane, k, b);
+      if (need & kNeedTy) c.ty = at(static_cast<const S *>(a.ty), plane, k, b);
+    } else if (need & kNeedK) {
       const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
       c.k = ok ? kx : S(0);
     }
-    c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
-    if (NEEDW) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+    if (need & kNeedSeal) c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
+    if (NEEDW && (need & kNeedW)) c.w = at(static_cast<const S *>(a.w), plane, k, b);
     if (R10) {
-      c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
-      c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
+      if (need & kNeedTn) c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
+      if (need & kNeedTs) c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
     }
   }
   // A diagonal face exists when both its cells lie in the domain; otherwise its
@@ -549,7 +569,7 @@ struct Tile {
 #pragma unroll
     for (int q = 0; q < HC; ++q)
       if (hl[q] >= 0) {
-        load_at(h[q], k, hv[q], hb[q], hs[q]);
+        load_at(h[q], k, hv[q], hb[q], hs[q], PICK ? hn[q] : kNeedAll);
         if (TIN) {
           h[q].tx = hv[q] ? h[q].tx : S(0);
           h[q].ty = hv[q] ? h[q].ty : S(0);
