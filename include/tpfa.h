@@ -99,9 +99,12 @@ typedef struct {
 } tpfa_state_t;
 
 /* Optional launch shape (pass NULL for the defaults): tile = id from
-   tpfa_tile_shape(), or -1; kz_chunk = z planes marched by one workgroup
-   (0 = default); flags bit 0 selects the XCD-aware workgroup order (each of
-   the 8 XCDs takes one contiguous range of tiles). */
+   tpfa_tile_shape(), or -1 for the library's default launch; kz_chunk = z
+   planes marched by one workgroup (0 = default); flags bit 0 selects the
+   XCD-aware workgroup order (the tiles of each z chunk are split into 8
+   contiguous bands of tile rows, one per XCD). With tile = -1 (or NULL) the
+   library also sets that bit where it measured faster; with an explicit tile
+   the flags are taken as given. Results never depend on the launch shape. */
 typedef struct {
   int tile;
   int kz_chunk;

@@ -170,11 +170,24 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
 
 namespace {
 
-int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
+// The XCD band order is part of the library's default launch where it measured
+// faster on MI355X (FP32 Jacobian and residual, FP32 10-flux stencil with
+// permeability input); a caller that picks the tile also picks the flags.
+int default_flags(tpfa::Mode mode, tpfa_precision_t prec, bool trans) {
+  if (prec != TPFA_FP32 || trans) return 0;
+  const int b = tpfa::base_mode(mode);
+  return b == tpfa::MODE_JACOBIAN || b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10
+             ? TPFA_LAUNCH_XCD_REMAP
+             : 0;
+}
+
+int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, bool trans,
                    const tpfa_launch_t *launch, int &tile, int &kz, int &flags) {
-  tile = (launch && launch->tile >= 0) ? launch->tile : default_tile(g, mode, prec);
+  const bool dflt = !launch || launch->tile < 0;
+  tile = dflt ? default_tile(g, mode, prec) : launch->tile;
   kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode);
   flags = launch ? launch->flags : 0;
+  if (dflt) flags |= default_flags(mode, prec, trans);
   return TPFA_OK;
 }
 
@@ -182,7 +195,7 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
   int tile, kz, flags;
-  resolve_launch(*g, mode, prec, launch, tile, kz, flags);
+  resolve_launch(*g, mode, prec, rk->tx != nullptr, launch, tile, kz, flags);
   // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
   tpfa::Args b;
   tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
@@ -477,7 +490,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       int tile, kz, flags;
       resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                           : tpfa::MODE_RESIDUAL,
-                     prec, &md.launch, tile, kz, flags);
+                     prec, false, &md.launch, tile, kz, flags);
       if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +

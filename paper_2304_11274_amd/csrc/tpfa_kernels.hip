@@ -879,15 +879,18 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
 }
 
 // XCD-aware order: the hardware hands consecutive workgroup ids to the 8 XCDs
-// in turn; renumber so that XCD x processes one contiguous range of tiles
-// (x fastest, then y, then z chunk), which keeps a tile's halo neighbours in
-// the same L2.
+// in turn. With the remap flag, the tiles of each z chunk (dispatched
+// together, as in the plain order) are split into 8 contiguous bands of
+// tile rows and each band goes to one XCD, so a tile's x and y neighbours
+// mostly run on the same XCD and its halo lines are shared in that L2.
 __device__ __forceinline__ void decode_tile(const Args &a, int64_t b, int &bx, int &by, int &kb) {
   int64_t t = b;
   if (a.remap) {
-    const int64_t n = a.nblocks, q = n / 8, rem = n % 8;
-    const int64_t x = b % 8, l = b / 8;
-    t = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + l;
+    const int64_t C = (int64_t)a.ntx * a.nty;  // tiles per z chunk
+    const int64_t kc = b / C, u = b % C;
+    const int64_t q = C / 8, rem = C % 8;
+    const int64_t x = u % 8, l = u / 8;  // band x (one XCD), position l in it
+    t = kc * C + (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + l;
   }
   bx = (int)(t % a.ntx);
   t /= a.ntx;
