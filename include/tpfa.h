@@ -49,7 +49,7 @@ extern "C" {
 
 #define TPFA_OK 0
 #define TPFA_ERR_NULL (-1)        /* a required pointer is NULL */
-#define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, or nx*ny*nz overflows */
+#define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, nx*ny*nz overflows, or one x-y plane of an array holds 2^32 bytes or more */
 #define TPFA_ERR_PARAM (-3)       /* mu <= 0, cell size <= 0, negative ratio, non-finite constant */
 #define TPFA_ERR_UNSUPPORTED (-4) /* unsupported combination (see each call) */
 #define TPFA_ERR_HIP (-5)         /* HIP runtime error, detail in tpfa_last_error() */

@@ -67,6 +67,10 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
   if (!st) return fail(TPFA_ERR_NULL, "state is NULL");
   if (prec != TPFA_FP64 && prec != TPFA_FP32)
     return fail(TPFA_ERR_PARAM, "unknown precision");
+  // the kernels address a cell within its x-y plane with a 32-bit byte offset
+  const int64_t elem = prec == TPFA_FP64 ? 8 : 4;
+  if (g->nx * g->ny > (int64_t)(std::numeric_limits<uint32_t>::max() / elem))
+    return fail(TPFA_ERR_SHAPE, "an x-y plane of one array must hold fewer than 2^32 bytes");
   if (rk->tx || rk->ty || rk->tz) {
     if (!rk->tx || !rk->ty || !rk->tz)
       return fail(TPFA_ERR_NULL, "rock.tx, rock.ty and rock.tz are all required");

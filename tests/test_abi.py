@@ -240,3 +240,17 @@ def test_transmissibility_form_validation(lib):
     out = C.c_void_p()
     assert lib.tpfa_batch_create(m, 1, L.TPFA_FP64, L.TPFA_BATCH_JACOBIAN, C.byref(out),
                                  None) == L.TPFA_ERR_UNSUPPORTED
+
+
+def test_plane_size_limit(lib):
+    """A cell is addressed within its x-y plane by a 32-bit byte offset, so one
+    plane of one array must hold fewer than 2^32 bytes."""
+    g, f, rk, st = good()
+    g.nx, g.ny, g.nz = 2 ** 15, 2 ** 14, 1  # 2^29 cells: 2^32 bytes in FP64, 2^31 in FP32
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st))
+    assert lib.tpfa_residual(*args, L.TPFA_FP64, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+    st.pref = DUMMY.value
+    # FP32 passes the shape check and stops at the missing output
+    assert lib.tpfa_residual(*args, L.TPFA_FP32, None, None, None) == L.TPFA_ERR_NULL
+    g.ny = 2 ** 15  # 2^30 cells: 2^32 bytes in FP32
+    assert lib.tpfa_residual(*args, L.TPFA_FP32, DUMMY, None, None) == L.TPFA_ERR_SHAPE
