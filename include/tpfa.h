@@ -82,7 +82,8 @@ typedef struct {
    here once per face); entries on the last layer along a direction are
    ignored and T = 0 closes a face. Then kx, ky, kz and seal must be NULL and
    ry, rz are ignored. Supported by every entry point except
-   tpfa_residual_vjp and the batch (TPFA_ERR_UNSUPPORTED). */
+   tpfa_residual_vjp (use tpfa_residual_vjp_trans) and the batch
+   (TPFA_ERR_UNSUPPORTED). */
 typedef struct {
   const void *kx, *ky, *kz;
   double ry, rz;
@@ -182,6 +183,17 @@ int tpfa_jacobian_be(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
 int tpfa_jvp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock_t *rock,
              const tpfa_state_t *state, const tpfa_accum_t *accum, tpfa_precision_t prec,
              const void *v, void *jv, void *r, const tpfa_launch_t *launch, void *stream);
+
+/* Vector-Jacobian product in the transmissibility form (rock->tx, ty, tz
+   given; TPFA_ERR_UNSUPPORTED otherwise): grad_p = J^T w as in
+   tpfa_residual_vjp, and grad_logt[3][ncell] with grad_logt[a][idx] =
+   d(w.r)/d ln T of the face between idx and its +a neighbour (a = x, y, z;
+   0 where that face does not exist), i.e. (w_idx - w_nb) F of that face,
+   since F is linear in T. Either output may be NULL (not both). */
+int tpfa_residual_vjp_trans(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                            const tpfa_rock_t *rock, const tpfa_state_t *state,
+                            tpfa_precision_t prec, const void *w, void *grad_p,
+                            void *grad_logt, const tpfa_launch_t *launch, void *stream);
 
 /* Residual of the 10-flux stencil: the six faces above plus the four in-plane
    diagonal faces that the paper's kernel also evaluates (Sec. 3, Algorithm 1

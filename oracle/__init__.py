@@ -91,6 +91,12 @@ def _load():
         lib.oracle_eval_general_cs.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                                 C.c_double, C.c_double] + [vp] * 9 +
                                                [C.c_double, C.c_double, vp, C.c_double, vp])
+        lib.oracle_vjp_general.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid), vp,
+                                            C.c_double, C.c_double] + [vp] * 9)
+        lib.oracle_trans_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, vp, vp, vp, vp,
+                                        C.c_double, vp]
+        lib.oracle_vjp_general.restype = C.c_int
+        lib.oracle_trans_cs.restype = C.c_int
         lib.oracle_eval_general.restype = C.c_int
         lib.oracle_eval_general_cs.restype = C.c_int
         for fn in ("oracle_eval", "oracle_rows", "oracle_eval_ld", "oracle_eval_cs",
@@ -332,6 +338,40 @@ def evaluate_general_cs(grid, fluid, p, vp, *, kx=None, trans=None, ry=1.0, rz=1
                                         float(h), _ptr(im))
     if rc != 0:
         raise ValueError("oracle_eval_general_cs rejected its arguments")
+    return im / h
+
+
+def vjp_general(grid, fluid, p, w, *, kx=None, trans=None, ry=1.0, rz=1.0, seal=None):
+    """grad_p = J^T w in either rock form; with ``trans`` also grad_t [3, ...]
+    (gradient with respect to ln T of each cell's +x, +y, +z face) and its
+    scale (sum of |terms|). Returns (grad_p, grad_t, grad_t_scale)."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    tx, ty, tz = (None, None, None) if trans is None else trans
+    kx, tx, ty, tz, p, w = (_arr(a, np.float64, shape) for a in (kx, tx, ty, tz, p, w))
+    seal = _arr(seal, np.uint8, shape)
+    gp = np.empty(shape)
+    gt = np.empty((3,) + shape) if trans is not None else None
+    gs = np.empty((3,) + shape) if trans is not None else None
+    rc = _load().oracle_vjp_general(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), float(ry),
+                                    float(rz), _ptr(seal), _ptr(tx), _ptr(ty), _ptr(tz), _ptr(p),
+                                    _ptr(w), _ptr(gp), _ptr(gt), _ptr(gs))
+    if rc != 0:
+        raise ValueError("oracle_vjp_general rejected its arguments")
+    return gp, gt, gs
+
+
+def trans_cs(grid, fluid, p, trans, d, h=1e-20) -> np.ndarray:
+    """Complex-step derivative of the transmissibility-form residual along the
+    ln T direction d [3, ...]: returns d r / d(ln T) . d."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    tx, ty, tz = (_arr(a, np.float64, shape) for a in trans)
+    p = _arr(p, np.float64, shape)
+    d = np.ascontiguousarray(d, np.float64)
+    im = np.empty(shape)
+    rc = _load().oracle_trans_cs(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(tx), _ptr(ty),
+                                 _ptr(tz), _ptr(p), _ptr(d), float(h), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_trans_cs rejected its arguments")
     return im / h
 
 

@@ -253,6 +253,9 @@ struct Outputs {
   const double* w = nullptr;
   void* grad_p = nullptr;  // [N]
   void* grad_m = nullptr;  // [N] gradient with respect to ln kx
+  void* grad_t = nullptr;  // [3][N] gradient with respect to ln T of the +x, +y, +z face of
+                           //   each cell (transmissibility form: dF/d ln T = F)
+  double* grad_t_scale = nullptr;  // [3][N] sum of |terms| of grad_t
   double* scale = nullptr; // [2][N]: sum |F_KL|, sum |dF_KL/dp_K|
   double* dphi = nullptr;  // [3][N]: dPhi of the face (c, c + e_a) seen from c; NaN if absent
 };
@@ -265,6 +268,7 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
   S* J = static_cast<S*>(o.J);
   S* gp = static_cast<S*>(o.grad_p);
   S* gm = static_cast<S*>(o.grad_m);
+  S* gt = static_cast<S*>(o.grad_t);
 
   // r := 0 (Algorithm 1), and the other accumulators
   S* jv = static_cast<S*>(o.jv);
@@ -276,6 +280,10 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
       for (int e = 0; e < 7; ++e) J[e * N + c] = S(0);
     if (gp) gp[c] = S(0);
     if (gm) gm[c] = S(0);
+    if (gt)
+      for (int a = 0; a < 3; ++a) gt[a * N + c] = S(0);
+    if (o.grad_t_scale)
+      for (int a = 0; a < 3; ++a) o.grad_t_scale[a * N + c] = 0.0;
     if (o.scale) o.scale[c] = o.scale[N + c] = 0.0;
     if (o.dphi)
       for (int a = 0; a < 3; ++a) o.dphi[a * N + c] = NAN;
@@ -322,6 +330,13 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
               const S ksum = fl.kK + fl.kL;
               gm[K] += wK * (fl.F * fl.kL / ksum);
               gm[nb.L] += wK * (fl.F * fl.kK / ksum);
+            }
+            // given T: d r_K / d ln T_KL = F_KL; T is stored on the face's lower cell
+            if (gt && nb.axis < 3) {
+              const int64_t lo = K < nb.L ? K : nb.L;
+              gt[nb.axis * N + lo] += wK * fl.F;
+              if (o.grad_t_scale)
+                o.grad_t_scale[nb.axis * N + lo] += std::abs(real_part(wK * fl.F));
             }
           }
           if (o.scale) {
@@ -451,6 +466,60 @@ int oracle_eval_general(const oracle_grid* g, const oracle_fluid* f, const doubl
   o.jv = jv;
   o.scale = scale;
   assemble(pb, o);
+  return 0;
+}
+
+// Vector-Jacobian product with cotangent w in either rock form: grad_p = J^T w,
+// and in the transmissibility form grad_t[a][c] = d(w.r)/d ln T of the face
+// between c and its +a neighbour, with grad_t_scale the sum of |terms|.
+int oracle_vjp_general(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                       double ry, double rz, const uint8_t* seal, const double* tx,
+                       const double* ty, const double* tz, const double* p, const double* w,
+                       double* grad_p, double* grad_t, double* grad_t_scale) {
+  const bool tin = tx || ty || tz;
+  if (!g || !f || !p || !w || (!kx && !tin)) return -1;
+  if (tin && (!tx || !ty || !tz || kx || seal)) return -1;
+  if (grad_t && !tin) return -1;
+  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, nullptr};
+  pb.tx = tx;
+  pb.ty = ty;
+  pb.tz = tz;
+  Outputs o;
+  o.w = w;
+  o.grad_p = grad_p;
+  o.grad_t = grad_t;
+  o.grad_t_scale = grad_t_scale;
+  assemble(pb, o);
+  return 0;
+}
+
+// Complex-step directional derivative of the transmissibility-form residual
+// with respect to ln T along d = (dx, dy, dz) (one direction per face array):
+// r_im = Im r(T exp(i h d)).
+int oracle_trans_cs(const oracle_grid* g, const oracle_fluid* f, const double* tx,
+                    const double* ty, const double* tz, const double* p, const double* d,
+                    double h, double* r_im) {
+  if (!g || !f || !tx || !ty || !tz || !p || !d || !r_im) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  cplx* pc = new cplx[N];
+  cplx* t[3] = {new cplx[N], new cplx[N], new cplx[N]};
+  const double* src[3] = {tx, ty, tz};
+  cplx* rc = new cplx[N];
+  for (int64_t q = 0; q < N; ++q) {
+    pc[q] = cplx(p[q], 0.0);
+    for (int a = 0; a < 3; ++a) t[a][q] = src[a][q] * std::exp(cplx(0.0, h * d[a * N + q]));
+  }
+  Problem<cplx> pb{g, f, pc, nullptr, nullptr, nullptr, 1.0, 1.0, nullptr, nullptr};
+  pb.tx = t[0];
+  pb.ty = t[1];
+  pb.tz = t[2];
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t q = 0; q < N; ++q) r_im[q] = rc[q].imag();
+  delete[] pc;
+  for (cplx* a : t) delete[] a;
+  delete[] rc;
   return 0;
 }
 

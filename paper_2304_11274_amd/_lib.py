@@ -79,6 +79,8 @@ SIGNATURES = {
                                    vp, vp, P(Launch), vp]),
     "tpfa_jvp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int, vp, vp,
                            vp, P(Launch), vp]),
+    "tpfa_residual_vjp_trans": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp,
+                                          vp, P(Launch), vp]),
     "tpfa_residual10": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
                                   P(Launch), vp]),
     "tpfa_hydrostatic": (C.c_int, [P(Grid), P(Fluid), C.c_double, vp, vp]),

@@ -134,24 +134,28 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r
 
 
 def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
-                 want_p=True, want_logk=True, gp_out=None, gm_out=None, tile=None,
+                 want_p=True, want_logk=True, gp_out=None, gm_out=None, trans=None, tile=None,
                  kz_chunk=None, xcd_remap=False):
-    """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref)
+    """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None. With
+    ``trans`` = (tx, ty, tz) the second output is grad_logt [3, nz, ny, nx]:
+    d(w.r)/d ln T of each cell's +x, +y, +z face."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
     _need(w, "w", dt, n, dev)
+    planes = 3 if trans is not None else 1
     gp = gm = None
     if want_p:
         gp = gp_out if gp_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
         _need(gp, "gp_out", dt, n, dev)
     if want_logk:
-        gm = gm_out if gm_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
-        _need(gm, "gm_out", dt, n, dev)
+        shape = ((3,) if trans is not None else ()) + tuple(p.shape)
+        gm = gm_out if gm_out is not None else torch.empty(shape, dtype=dt, device=dev)
+        _need(gm, "gm_out", dt, planes * n, dev)
     lib = L.load()
-    L.check(lib.tpfa_residual_vjp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                  C.byref(_rock(kx, seal, ry, rz)),
-                                  C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w),
-                                  _ptr(gp), _ptr(gm), _launch_ref(tile, kz_chunk, xcd_remap),
-                                  _stream(dev)), lib)
+    fn = lib.tpfa_residual_vjp_trans if trans is not None else lib.tpfa_residual_vjp
+    L.check(fn(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
+               C.byref(_rock(kx, seal, ry, rz, trans)), C.byref(L.State(_ptr(p), _ptr(pref))),
+               prec, _ptr(w), _ptr(gp), _ptr(gm), _launch_ref(tile, kz_chunk, xcd_remap),
+               _stream(dev)), lib)
     return gp, gm
 
 

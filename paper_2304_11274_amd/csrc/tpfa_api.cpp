@@ -275,7 +275,8 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
     if (!w) return fail(TPFA_ERR_NULL, "w is NULL");
     if (!grad_p && !grad_logk) return fail(TPFA_ERR_NULL, "grad_p and grad_logk are both NULL");
     if (rock->tx)
-      return fail(TPFA_ERR_UNSUPPORTED, "the vector-Jacobian product needs the permeability form");
+      return fail(TPFA_ERR_UNSUPPORTED,
+                  "the transmissibility form has its own product: tpfa_residual_vjp_trans");
     tpfa::Args a{};
     a.w = w;
     a.gp = grad_p;
@@ -358,6 +359,29 @@ int tpfa_jvp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, const tpfa_rock
     a.r = r;
     return run(accum ? tpfa::MODE_JVP_BE : tpfa::MODE_JVP, grid, fluid, rock, state, prec,
                launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_residual_vjp_trans(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                            const tpfa_rock_t *rock, const tpfa_state_t *state,
+                            tpfa_precision_t prec, const void *w, void *grad_p, void *grad_logt,
+                            const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!rock->tx)
+      return fail(TPFA_ERR_UNSUPPORTED, "tpfa_residual_vjp_trans needs the transmissibility form");
+    if (!w) return fail(TPFA_ERR_NULL, "w is NULL");
+    if (!grad_p && !grad_logt) return fail(TPFA_ERR_NULL, "grad_p and grad_logt are both NULL");
+    tpfa::Args a{};
+    a.w = w;
+    a.gp = grad_p;
+    a.gm = grad_logt;
+    return run(tpfa::MODE_VJP, grid, fluid, rock, state, prec, launch, a, stream);
   } catch (const std::exception &e) {
     return fail(TPFA_ERR_HIP, e.what());
   } catch (...) {

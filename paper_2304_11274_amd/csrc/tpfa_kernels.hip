@@ -346,14 +346,28 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
       const double d = (double)c0.w - (double)wn[n];
       if (n & 1) {  // own cell is Lo
         gp = fma(d, (double)f[n].dLo, gp);
-        gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
+        if constexpr (!has_trans(MODE)) gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
       } else {      // own cell is Up
         gp = fma(-d, (double)f[n].dUp, gp);
-        gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
+        if constexpr (!has_trans(MODE)) gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
       }
     }
     if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
-    if (a.gm) st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
+    if constexpr (has_trans(MODE)) {
+      // given T: d(w.r)/d ln T of the +x, +y, +z face (own cell is its lower
+      // cell) is (w_C - w_N) F, stored as three planes [x, y, z]
+      if (a.gm) {
+        const size_t nc = (size_t)nz * plane;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int n = 2 * d + 1;
+          const double g = ((double)c0.w - (double)wn[n]) * (double)f[n].F;
+          st_nt(at_w(static_cast<S *>(a.gm), (size_t)d * nc + ko, cb), (S)g);
+        }
+      }
+    } else if (a.gm) {
+      st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
+    }
   } else {
     double acc = 0.0;
     S dacc = S(0);
@@ -1057,6 +1071,7 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
       case MODE_JVP | MODE_TRANS: return launch_t<double, MODE_JVP | MODE_TRANS>(tile, a, st);
       case MODE_JVP_BE | MODE_TRANS: return launch_t<double, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
       case MODE_VJP: return launch_t<double, MODE_VJP>(tile, a, st);
+      case MODE_VJP | MODE_TRANS: return launch_t<double, MODE_VJP | MODE_TRANS>(tile, a, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1078,6 +1093,7 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
     case MODE_JVP | MODE_TRANS: return launch_t<float, MODE_JVP | MODE_TRANS>(tile, a, st);
     case MODE_JVP_BE | MODE_TRANS: return launch_t<float, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
     case MODE_VJP: return launch_t<float, MODE_VJP>(tile, a, st);
+    case MODE_VJP | MODE_TRANS: return launch_t<float, MODE_VJP | MODE_TRANS>(tile, a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -254,3 +254,14 @@ def test_plane_size_limit(lib):
     assert lib.tpfa_residual(*args, L.TPFA_FP32, None, None, None) == L.TPFA_ERR_NULL
     g.ny = 2 ** 15  # 2^30 cells: 2^32 bytes in FP32
     assert lib.tpfa_residual(*args, L.TPFA_FP32, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+
+
+def test_vjp_trans_validation(lib):
+    g, f, rk, st = good()
+    D = DUMMY.value
+    tr = L.Rock(None, None, None, 1.0, 1.0, None, D, D, D)
+    args = lambda r: (C.byref(g), C.byref(f), C.byref(r), C.byref(st), L.TPFA_FP64)  # noqa: E731
+    assert lib.tpfa_residual_vjp_trans(*args(rk), DUMMY, DUMMY, DUMMY, None,
+                                       None) == L.TPFA_ERR_UNSUPPORTED
+    assert lib.tpfa_residual_vjp_trans(*args(tr), None, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual_vjp_trans(*args(tr), DUMMY, None, None, None, None) == L.TPFA_ERR_NULL

@@ -112,3 +112,49 @@ def test_trans_fp32(gpu, orc, shape):
     for n in range(1, 7):
         check(J[n], ref["J"][n], np.abs(ref["J"][n]), 1e-5, f"J plane {n}")
     check(r10, ref10["r"], ref10["scale"][0], 1e-5, "r10")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(3, 5, 7), (70, 9, 37), (129, 13, 3)],
+                         ids=lambda s: "x".join(map(str, s)) if isinstance(s, tuple) else s)
+def test_trans_vjp(gpu, orc, shape, prec):
+    geo, tr, _, be = trans_case(shape, 90 + sum(shape))
+    g = geo.grid
+    w = be["v"]
+    if prec == "fp64":
+        p = orc.pressure(geo)
+        kw = dict(trans=tuple(dev(t) for t in tr))
+        pd, wd, p_w, tw, w_w, tol = dev(p), dev(w), p, tr, w, 1e-12
+    else:
+        pref = orc.hydrostatic(g, geo.fluid)
+        dp = geo.dp32(0)
+        tr32 = tuple(t.astype(np.float32) for t in tr)
+        w32 = w.astype(np.float32)
+        kw = dict(trans=tuple(dev(t) for t in tr32), pref=dev(pref))
+        pd, wd = dev(dp), dev(w32)
+        p_w, tw, w_w, tol = (orc.widen_fp32(dp, pref), tuple(t.astype(np.float64) for t in tr32),
+                             w32.astype(np.float64), 1e-5)
+    print(f"transmissibility-form vjp {prec} {shape}", flush=True)
+    ref_gp, ref_gt, _ = orc.vjp_general(g, geo.fluid, p_w, w_w, trans=tw)
+    ev = orc.evaluate_general(g, geo.fluid, p_w, trans=tw, want=("J", "scale"))
+    from helpers import apply_JT, shift
+    gp_scale = apply_JT(np.abs(ev["J"]), np.abs(w_w))
+    # R16-style scale of the ln T gradient of a face: (|w_lo| + |w_hi|) times
+    # the larger flux scale sum |F| of its two cells (the FP32 z-face potential
+    # error, ~2e-3 Pa, is small against a cell's fluxes, not against a face
+    # whose own potential difference is a few Pa)
+    s, aw = ev["scale"][0], np.abs(w_w)
+    gt_scale = [(aw + shift(aw, 2 * a + 1)) * np.maximum(s, shift(s, 2 * a + 1))
+                for a in range(3)]
+    first = None
+    for tile in ((0, 3, 4) if prec == "fp64" else (None,)):
+        gp, gt = gpu.residual_vjp(g, geo.fluid, None, pd, wd, tile=tile, **kw)
+        gp, gt = host(gp), host(gt)
+        assert gt.shape == (3,) + g.shape
+        if first is None:
+            check(gp, ref_gp, gp_scale, tol, "grad_p")
+            for a in range(3):
+                check(gt[a], ref_gt[a], gt_scale[a], tol, f"grad ln T axis {a}")
+            first = (gp, gt)
+        else:
+            assert np.array_equal(gp, first[0]) and np.array_equal(gt, first[1]), tile

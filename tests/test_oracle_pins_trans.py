@@ -112,3 +112,51 @@ def test_general_matches_specialised_entries(orc):
     b = orc.evaluate_general(geo.grid, geo.fluid, p, kx=geo.kx, ry=geo.ry, rz=geo.rz,
                              seal=geo.seal, want=("r", "J"))
     assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["J"], b["J"])
+
+
+# ---------------------------------------------------------------------------
+# Vector-Jacobian product of the transmissibility form: grad_p = J^T w and the
+# gradient with respect to ln T of every face.
+# ---------------------------------------------------------------------------
+
+def test_vjp_trans_two_cell_closed_form(orc):
+    g = geomodel.Grid(2, 1, 1)
+    p = np.array([1.0e7, 1.01e7]).reshape(1, 1, 2)
+    tx = np.array([3.5e-13, 0.0]).reshape(1, 1, 2)
+    z = np.zeros((1, 1, 2))
+    w = np.array([0.7, -1.3]).reshape(1, 1, 2)
+    _, gt, _ = orc.vjp_general(g, FL, p, w, trans=(tx, z, z))
+    F = D(3.5e-13) * rho_dec(1.01e7) / D(FL.mu) * (D(1.0e7) - D(1.01e7))
+    want = (D(0.7) - D(-1.3)) * F
+    assert abs(gt[0].ravel()[0] - float(want)) <= 4e-16 * abs(float(want))
+    assert np.all(gt[0].ravel()[1:] == 0) and np.all(gt[1:] == 0)
+
+
+@pytest.mark.parametrize("shape", [(4, 3, 5), (6, 1, 3), (1, 5, 4)])
+def test_vjp_trans_dot_product_complex_step(orc, shape):
+    g = geomodel.Grid(*shape)
+    rng = np.random.default_rng(3 + sum(shape))
+    tr = tuple(rng.uniform(0, 6e-13, g.shape) for _ in range(3))
+    geo = geomodel.random_small(5, *shape)
+    p = orc.pressure(geo)
+    w = rng.standard_normal(g.shape)
+    d = rng.standard_normal((3,) + g.shape)
+    _, gt, gs = orc.vjp_general(g, geo.fluid, p, w, trans=tr)
+    jd = orc.trans_cs(g, geo.fluid, p, tr, d)    # (dr / d ln T) d by complex step
+    lhs, rhs = float(np.sum(gt * d)), float(np.sum(w * jd))
+    assert abs(lhs - rhs) <= 1e-13 * float(np.sum(gs * np.abs(d)))
+
+
+def test_vjp_trans_grad_p_is_sparse_JT_w(orc):
+    g = geomodel.Grid(7, 5, 4)
+    rng = np.random.default_rng(21)
+    tr = tuple(rng.uniform(0, 6e-13, g.shape) for _ in range(3))
+    geo = geomodel.random_small(6, 7, 5, 4)
+    p = orc.pressure(geo)
+    w = rng.standard_normal(g.shape)
+    gp, _, _ = orc.vjp_general(g, geo.fluid, p, w, trans=tr)
+    J = orc.evaluate_general(g, geo.fluid, p, trans=tr, want=("J",))["J"]
+    from helpers import apply_JT, sparse_J
+    ref = sparse_J(J).T @ w.ravel()
+    scale = apply_JT(np.abs(J), np.abs(w)).ravel()
+    assert np.all(np.abs(gp.ravel() - ref) <= 1e-14 * scale)
