@@ -366,6 +366,7 @@ class TPFAResidual(torch.autograd.Function):
         kx = torch.exp(logk)
         r = residual(grid, fluid, kx, p, seal=seal, pref=pref, ry=ry, rz=rz)
         ctx.save_for_backward(p, kx)
+        ctx.save_for_forward(p, kx)
         ctx.cfg = (grid, fluid, seal, pref, ry, rz)
         return r
 
@@ -377,3 +378,58 @@ class TPFAResidual(torch.autograd.Function):
                               rz=rz, want_p=ctx.needs_input_grad[0],
                               want_logk=ctx.needs_input_grad[1])
         return gp, gm, None, None, None, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dp, dlogk, *_):
+        """Forward mode with respect to p: the matrix-free Jacobian-vector
+        product kernel. (A tangent in ln kx is not provided: use reverse mode.)"""
+        if dlogk is not None and bool(dlogk.any()):  # zero tangents are passed too
+            raise NotImplementedError("forward-mode derivative with respect to ln kx; "
+                                      "use reverse mode (backward) for it")
+        p, kx = ctx.saved_tensors
+        grid, fluid, seal, pref, ry, rz = ctx.cfg
+        if dp is None:
+            return torch.zeros_like(p)
+        jv, _ = jvp(grid, fluid, kx, p, dp.contiguous(), seal=seal, pref=pref, ry=ry, rz=rz)
+        return jv
+
+
+class TPFATransResidual(torch.autograd.Function):
+    """r(p, ln T) in the transmissibility form, with a hand-written adjoint.
+
+    forward: T = exp(logt), logt of shape [3, nz, ny, nx] (the +x, +y, +z face
+    of every cell), then the residual kernel; backward: the vector-Jacobian
+    kernel of that form returns (J^T w, d(w.r)/d ln T). Forward mode in p uses
+    the Jacobian-vector product kernel. Non-tensor arguments: grid, fluid,
+    pref."""
+
+    @staticmethod
+    def forward(ctx, p, logt, grid, fluid, pref=None):
+        t = torch.exp(logt)
+        trans = (t[0], t[1], t[2])
+        r = residual(grid, fluid, None, p, pref=pref, trans=trans)
+        ctx.save_for_backward(p, t)
+        ctx.save_for_forward(p, t)
+        ctx.cfg = (grid, fluid, pref)
+        return r
+
+    @staticmethod
+    def backward(ctx, w):
+        p, t = ctx.saved_tensors
+        grid, fluid, pref = ctx.cfg
+        gp, gt = residual_vjp(grid, fluid, None, p, w.contiguous(), pref=pref,
+                              trans=(t[0], t[1], t[2]), want_p=ctx.needs_input_grad[0],
+                              want_logk=ctx.needs_input_grad[1])
+        return gp, gt, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dp, dlogt, *_):
+        if dlogt is not None and bool(dlogt.any()):  # zero tangents are passed too
+            raise NotImplementedError("forward-mode derivative with respect to ln T; "
+                                      "use reverse mode (backward) for it")
+        p, t = ctx.saved_tensors
+        grid, fluid, pref = ctx.cfg
+        if dp is None:
+            return torch.zeros_like(p)
+        jv, _ = jvp(grid, fluid, None, p, dp.contiguous(), pref=pref, trans=(t[0], t[1], t[2]))
+        return jv
