@@ -1,10 +1,13 @@
-// HIP kernels for the TPFA flux residual, Jacobian and vector-Jacobian
-// product on gfx950 (MI355X).
+// HIP kernels for the TPFA flux residual, its Jacobian, vector-Jacobian and
+// Jacobian-vector products on gfx950 (MI355X).
 //
 // Equations (paper Sec. 3): density Eq. (5), flux and potential difference
 // Eq. (3a)/(3b) (outflow orientation dPhi_KL = Phi_K - Phi_L), single-point
 // upwinding Eq. (4) with ties given to the lower linear index, residual
-// assembly of Algorithm 1 (sum of the fluxes of a cell's face neighbours).
+// assembly of Algorithm 1 (sum of the fluxes of a cell's face neighbours);
+// optionally the accumulation term of the backward-Euler residual Eq. (2),
+// the four in-plane diagonal faces the paper also computes, and face
+// transmissibilities given as inputs instead of computed from k.
 //
 // Design. The path is a radius-1 stencil whose HBM traffic is fixed by its
 // inputs (p, k, seal) and outputs (r and seven Jacobian planes), so nothing
@@ -21,20 +24,24 @@
 //  * loads and stores are x-fastest and coalesced (a 64-lane wave covers
 //    64 consecutive x cells when TX = 64); outputs are written once with
 //    non-temporal stores;
-//  * workgroups are numbered so that each of the 8 XCDs processes one
-//    contiguous range of tiles, keeping halo re-reads in that XCD's L2.
-// The cell-gather form writes only owned cells: no atomics, deterministic,
-// and the same tile body serves the single-grid kernels and the persistent
-// ensemble kernel, so both produce bit-identical results.
+//  * optionally, the tiles of each z chunk are split into one band of tile
+//    rows per XCD, so that halo lines are shared within one L2.
+// One tile body, specialised per mode at compile time, serves every entry
+// point, the persistent ensemble kernel and the grouped one. The cell-gather
+// form writes only owned cells: no atomics, deterministic, and every launch
+// shape gives bit-identical results.
 //
-// Precision. FP64: every quantity in double, operation order of the
-// definition (the flux of each face is formed as Ups * lambda * dPhi with
-// Ups = a * ((2 k_K k_L) / (k_K + k_L))). FP32 precision form: p_K =
-// pref[k] + dp_K is formed in FP64, so the potential difference and its
-// upwind decision are FP64; transmissibility, density (single-precision exp),
-// mobility and the flux/derivative products are FP32; the residual, the
-// Jacobian diagonal and the gradients are accumulated in FP64 and rounded
-// once on store.
+// Precision. FP64: every quantity in double; the flux of each face is formed
+// as (Ups * lambda) * dPhi with Ups = (2 a k_Lo) * (k_Up * (1 / (k_Lo + k_Up)))
+// and a reciprocal accurate to about one ulp, so every result agrees with the
+// definition's evaluation order to about 1e-16 relative. FP32 precision form: the z-face
+// potential difference is formed in FP64 from pref[k] - pref[k+1] and the
+// stored offsets dp, and decides the upwind cell in FP64; x-y faces subtract
+// offsets of one plane in float (whose sign is exact, so the upwind choice is
+// the FP64 one); transmissibility, density (single-precision exp), mobility,
+// the flux/derivative products and the Jacobian diagonal are FP32; the
+// residual, the gradients and J v are accumulated in FP64 and rounded once on
+// store.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -52,7 +59,7 @@ template <class S>
 struct Cell {
   S p;         // stored pressure value (absolute for FP64, offset from pref for FP32)
   S k;         // kx
-  S w;         // cotangent (vector-Jacobian product only)
+  S w;         // cotangent w (VJP) or direction v (JVP) of the product modes
   S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
   S phi, pn;   // reference porosity and previous-level pressure (backward-Euler modes)
   S tx, ty, tz;  // transmissibilities of the +x, +y, +z faces (transmissibility input)
@@ -98,7 +105,7 @@ __device__ __forceinline__ double rcp64(double x) {
 template <class C>
 struct Face {
   C F, dLo, dUp, qLo, qUp;
-  C w;  // z faces: cotangent of the lower cell (vector-Jacobian product only)
+  C w;  // z faces: w or v of the lower cell (product modes only)
 };
 
 // Transmissibility 2 a r k_Lo k_Up / (k_Lo + k_Up) (A2 = 2 a r), closed when
@@ -254,8 +261,9 @@ constexpr bool tile_shares() {
 }
 
 // Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
-// p, k, mobility, seal (and w for the vector-Jacobian product, the diagonal
-// transmissibilities for the 10-flux stencil), or the shared-face layout.
+// p, k (or t_x), mobility, seal, plus w / v for the product modes, t_ne and
+// t_se for the 10-flux stencil and t_y for the transmissibility form; or the
+// shared-face layout.
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
