@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI layer (tpfa_api.cpp) and the HIP
-// kernels (tpfa_kernels.hip, tpfa_batch.hip). Not installed.
+// kernels (tpfa_kernels.hip). Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,7 +90,7 @@ struct Args {
   void *r;
   void *J;
   void *gp;
-  void *gm;
+  void *gm;           // grad ln kx, or grad ln T [3][ncell] in the transmissibility form
   void *jv;           // J v (JVP modes)
 };
 
@@ -106,7 +106,7 @@ hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, doubl
 hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
                          hipStream_t stream);
 
-// Batched persistent kernel (tpfa_batch.hip).
+// Batched ensemble kernels (persistent and grouped schedules).
 struct WorkItem {
   int32_t model;
   int32_t bx, by, kb;
