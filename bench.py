@@ -168,10 +168,24 @@ def main():
         kw = dict(seal=seal, ry=geo.ry, rz=geo.rz, r_out=r, J_out=J)
         for s in range(W):
             tp.jacobian(g, fl, kx64, ps[s % 4], **kw)
+        # five equal chunks of the K timed steps, each bracketed by events on the
+        # same stream (no synchronisation inside the timed region): mean and
+        # SD of the per-step time over the chunks
+        n_chunks = 5 if K >= 5 else 1
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + 1)]
+        bounds = [K * c // n_chunks for c in range(n_chunks + 1)]
         with Timer(torch) as tm:
-            for s in range(K):
-                tp.jacobian(g, fl, kx64, ps[s % 4], **kw)
+            marks[0].record()
+            for c in range(n_chunks):
+                for s in range(bounds[c], bounds[c + 1]):
+                    tp.jacobian(g, fl, kx64, ps[s % 4], **kw)
+                marks[c + 1].record()
         res = rate(tm.ms, K, BYTES_FP64_RJ)
+        per = [marks[c].elapsed_time(marks[c + 1]) / (bounds[c + 1] - bounds[c])
+               for c in range(n_chunks)]
+        mean = sum(per) / len(per)
+        sd = (sum((x - mean) ** 2 for x in per) / max(1, len(per) - 1)) ** 0.5
+        out["ms_per_step_repeats"] = {"n": n_chunks, "mean": mean, "sd": sd, "chunks": per}
         out["value"] = res["cells_per_s"]
         out["ms_per_step"] = res["ms_per_step"]
         traffic = read_traffic()
