@@ -475,10 +475,17 @@ def main():
         dt, nc = slab(2)
         nzs = int(max(2, min(geo_c.grid.nz, 2 * args.cpu_seconds / max(dt, 1e-3))))
         dt, nc = slab(nzs)
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f_:
+                model = next(l.split(":", 1)[1].strip() for l in f_ if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         out["cpu_baseline"] = {"value": nc / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
                                "sample": f"512x512x{nzs} slab of the 512x512x256 workload "
                                          f"(FP64 residual + Jacobian, single-threaded plain "
-                                         f"oracle), {dt:.1f} s"}
+                                         f"oracle), {dt:.1f} s on {model}",
+                               "host_cores_available": len(os.sched_getaffinity(0))}
         log(f"cpu baseline: {out['cpu_baseline']}")
 
     print(json.dumps(out), flush=True)
