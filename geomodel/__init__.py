@@ -270,6 +270,20 @@ def diagonal_t(grid: Grid, seed: int, zero_prob: float = 0.1) -> tuple:
     return tuple(out)
 
 
+# Per-direction permeability arrays: the geomodel's kx with independent
+# log-normal anisotropy factors for ky and kz (kz around the recipe's 0.1 kx).
+def k3_fields(kx: np.ndarray, seed: int, sigma_y: float = 0.3, sigma_z: float = 0.5,
+              rz: float = 0.1) -> tuple:
+    """(kx, ky, kz), float64: ky = kx exp(sigma_y N(0, 1)), kz = rz kx
+    exp(sigma_z N(0, 1)), the two normal fields drawn in that order from
+    default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    kx = np.asarray(kx, dtype=np.float64)
+    ky = kx * np.exp(sigma_y * rng.standard_normal(kx.shape))
+    kz = rz * kx * np.exp(sigma_z * rng.standard_normal(kx.shape))
+    return kx, ky, kz
+
+
 # Backward-Euler inputs (accumulation term of Eq. (2)): reference porosity,
 # previous-level pressure noise and a Krylov direction.
 BE_DT = 86400.0   # one day (s)

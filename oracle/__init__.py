@@ -93,6 +93,12 @@ def _load():
                                                [C.c_double, C.c_double, vp, C.c_double, vp])
         lib.oracle_vjp_general.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                             C.c_double, C.c_double] + [vp] * 9)
+        lib.oracle_eval_k3.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid)] + [vp] * 9 +
+                                       [C.c_double, C.c_double] + [vp] * 9)
+        lib.oracle_eval_k3_cs.argtypes = ([C.POINTER(_Grid), C.POINTER(_Fluid)] + [vp] * 9 +
+                                          [C.c_double, C.c_double, vp, vp, C.c_double, vp])
+        lib.oracle_eval_k3.restype = C.c_int
+        lib.oracle_eval_k3_cs.restype = C.c_int
         lib.oracle_trans_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, vp, vp, vp, vp,
                                         C.c_double, vp]
         lib.oracle_vjp_general.restype = C.c_int
@@ -372,6 +378,57 @@ def trans_cs(grid, fluid, p, trans, d, h=1e-20) -> np.ndarray:
                                  _ptr(tz), _ptr(p), _ptr(d), float(h), _ptr(im))
     if rc != 0:
         raise ValueError("oracle_trans_cs rejected its arguments")
+    return im / h
+
+
+def _k3_args(grid, p, kx, ky, kz, seal, diag, accum):
+    shape = (grid.nz, grid.ny, grid.nx)
+    tne, tse = (None, None) if diag is None else diag
+    acc = accum or {}
+    arrs = [_arr(a, np.float64, shape) for a in (kx, ky, kz, tne, tse, p, acc.get("phi"),
+                                                   acc.get("p_prev"))]
+    seal = _arr(seal, np.uint8, shape)
+    kx, ky, kz, tne, tse, p, phi, pn = arrs
+    head = [_ptr(kx), _ptr(ky), _ptr(kz), _ptr(seal), _ptr(tne), _ptr(tse), _ptr(p), _ptr(phi),
+            _ptr(pn), float(acc.get("dt", 1.0)), float(acc.get("cr", 0.0))]
+    return shape, head, arrs + [seal]
+
+
+def evaluate_k3(grid, fluid, p, kx, ky, kz, *, seal=None, diag=None, accum=None, v=None,
+                w=None, want=("r",)) -> dict:
+    """Per-direction permeability form (kx, ky, kz per cell, no ratios), with
+    seal bits, optional diagonal faces ``diag`` = (tne, tse) and accumulation
+    ``accum`` = dict(phi, p_prev, dt, cr). Outputs any of r, J, jv (needs v),
+    scale, and with the cotangent w: grad_p = J^T w, grad_k3 [3, ...] =
+    d(w.r)/d ln k_a for a = x, y, z, grad_k3_scale (sum of |terms|)."""
+    shape, head, keep = _k3_args(grid, p, kx, ky, kz, seal, diag, accum)
+    v = _arr(v, np.float64, shape)
+    w = _arr(w, np.float64, shape)
+    bufs = {}
+    for key, sh in (("r", shape), ("J", (7,) + shape), ("jv", shape), ("scale", (2,) + shape),
+                    ("grad_p", shape), ("grad_k3", (3,) + shape),
+                    ("grad_k3_scale", (3,) + shape)):
+        bufs[key] = np.empty(sh, np.float64) if key in want else None
+    rc = _load().oracle_eval_k3(C.byref(_g(grid)), C.byref(_f(fluid)), *head, _ptr(v), _ptr(w),
+                                *(_ptr(bufs[k]) for k in ("r", "J", "jv", "scale", "grad_p",
+                                                          "grad_k3", "grad_k3_scale")))
+    if rc != 0:
+        raise ValueError("oracle_eval_k3 rejected its arguments")
+    return {k: bufs[k] for k in want}
+
+
+def evaluate_k3_cs(grid, fluid, p, kx, ky, kz, *, seal=None, diag=None, accum=None, vp=None,
+                   dk=None, h=1e-20) -> np.ndarray:
+    """Complex-step directional derivative of the per-direction form along
+    vp (pressure) and dk [3, ...] (ln kx, ln ky, ln kz): Im r / h."""
+    shape, head, keep = _k3_args(grid, p, kx, ky, kz, seal, diag, accum)
+    vp = _arr(vp, np.float64, shape)
+    dk = _arr(dk, np.float64, (3,) + shape)
+    im = np.empty(shape)
+    rc = _load().oracle_eval_k3_cs(C.byref(_g(grid)), C.byref(_f(fluid)), *head, _ptr(vp),
+                                   _ptr(dk), float(h), _ptr(im))
+    if rc != 0:
+        raise ValueError("oracle_eval_k3_cs rejected its arguments")
     return im / h
 
 

@@ -47,7 +47,8 @@
 //
 // Vector-Jacobian product with cotangent w: grad_p = J^T w and
 // grad_logk[j] = sum_K w_K d r_K / d ln(kx_j), where ky = ry kx and kz = rz kx
-// follow kx (ratios, not separate arrays).
+// follow kx (ratios, not separate arrays). With per-direction arrays kx, ky,
+// kz instead, grad_k3[a][j] = sum_K w_K d r_K / d ln(k_a,j) for a = x, y, z.
 //
 // Parity pins (tests/test_oracle_*.py): closed-form two-cell fluxes, the
 // continuous hydrostatic column, the c_f = 0 graph Laplacian built by SciPy,
@@ -256,6 +257,9 @@ struct Outputs {
   void* grad_t = nullptr;  // [3][N] gradient with respect to ln T of the +x, +y, +z face of
                            //   each cell (transmissibility form: dF/d ln T = F)
   double* grad_t_scale = nullptr;  // [3][N] sum of |terms| of grad_t
+  void* grad_k3 = nullptr; // [3][N] gradient with respect to ln kx, ln ky, ln kz (per-direction
+                           //   permeability arrays: each face depends on its own direction's k)
+  double* grad_k3_scale = nullptr;  // [3][N] sum of |terms| of grad_k3
   double* scale = nullptr; // [2][N]: sum |F_KL|, sum |dF_KL/dp_K|
   double* dphi = nullptr;  // [3][N]: dPhi of the face (c, c + e_a) seen from c; NaN if absent
 };
@@ -269,6 +273,7 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
   S* gp = static_cast<S*>(o.grad_p);
   S* gm = static_cast<S*>(o.grad_m);
   S* gt = static_cast<S*>(o.grad_t);
+  S* gk = static_cast<S*>(o.grad_k3);
 
   // r := 0 (Algorithm 1), and the other accumulators
   S* jv = static_cast<S*>(o.jv);
@@ -284,6 +289,10 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
       for (int a = 0; a < 3; ++a) gt[a * N + c] = S(0);
     if (o.grad_t_scale)
       for (int a = 0; a < 3; ++a) o.grad_t_scale[a * N + c] = 0.0;
+    if (gk)
+      for (int a = 0; a < 3; ++a) gk[a * N + c] = S(0);
+    if (o.grad_k3_scale)
+      for (int a = 0; a < 3; ++a) o.grad_k3_scale[a * N + c] = 0.0;
     if (o.scale) o.scale[c] = o.scale[N + c] = 0.0;
     if (o.dphi)
       for (int a = 0; a < 3; ++a) o.dphi[a * N + c] = NAN;
@@ -330,6 +339,18 @@ void assemble(const Problem<S>& pb, const Outputs& o) {
               const S ksum = fl.kK + fl.kL;
               gm[K] += wK * (fl.F * fl.kL / ksum);
               gm[nb.L] += wK * (fl.F * fl.kK / ksum);
+            }
+            // per-direction k: the face along axis a depends on k_a of its two
+            // cells only, d F / d ln k_a,K = F k_a,L / (k_a,K + k_a,L)
+            if (gk && nb.axis < 3 && real_part(fl.T) != 0.0) {
+              const S ksum = fl.kK + fl.kL;
+              const S tK = wK * (fl.F * fl.kL / ksum), tL = wK * (fl.F * fl.kK / ksum);
+              gk[nb.axis * N + K] += tK;
+              gk[nb.axis * N + nb.L] += tL;
+              if (o.grad_k3_scale) {
+                o.grad_k3_scale[nb.axis * N + K] += std::abs(real_part(tK));
+                o.grad_k3_scale[nb.axis * N + nb.L] += std::abs(real_part(tL));
+              }
             }
             // given T: d r_K / d ln T_KL = F_KL; T is stored on the face's lower cell
             if (gt && nb.axis < 3) {
@@ -731,6 +752,88 @@ int oracle_eval_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx
   delete[] pc;
   delete[] kc;
   delete[] rc;
+  return 0;
+}
+
+// Per-direction permeability form: kx, ky, kz given per cell (each face along
+// axis a takes the harmonic average of k_a of its two cells; no ratios), with
+// seal bits, optional diagonal faces (tne, tse), optional accumulation term
+// (phi non-NULL: phi, p_prev, dt, cr). Outputs r, J, jv (needs v), scale
+// ([2][N]), and with w: grad_p = J^T w, grad_k3[a][c] = d(w.r)/d ln k_a[c] and
+// grad_k3_scale (sum of |terms|); each optional.
+int oracle_eval_k3(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                   const double* ky, const double* kz, const uint8_t* seal, const double* tne,
+                   const double* tse, const double* p, const double* phi, const double* p_prev,
+                   double dt, double cr, const double* v, const double* w, double* r,
+                   double* J, double* jv, double* scale, double* grad_p, double* grad_k3,
+                   double* grad_k3_scale) {
+  if (!valid(g, f, p, kx) || !ky || !kz) return -1;
+  if ((tne != nullptr) != (tse != nullptr)) return -1;
+  if (phi && (!p_prev || !(dt > 0.0))) return -1;
+  if (jv && !v) return -1;
+  if ((grad_p || grad_k3 || grad_k3_scale) && !w) return -1;
+  Problem<double> pb{g, f, p, kx, ky, kz, 1.0, 1.0, seal, nullptr};
+  pb.tne = tne;
+  pb.tse = tse;
+  pb.phi = phi;
+  pb.p_prev = p_prev;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = r;
+  o.J = J;
+  o.v = v;
+  o.jv = jv;
+  o.scale = scale;
+  o.w = w;
+  o.grad_p = grad_p;
+  o.grad_k3 = grad_k3;
+  o.grad_k3_scale = grad_k3_scale;
+  assemble(pb, o);
+  return 0;
+}
+
+// Complex-step evaluation of the same form: p -> p + i h vp and
+// ln k_a -> ln k_a + i h dk[a] (a = x, y, z; vp and dk may each be NULL).
+// Im r / h is the directional derivative of r along (vp, dk).
+int oracle_eval_k3_cs(const oracle_grid* g, const oracle_fluid* f, const double* kx,
+                      const double* ky, const double* kz, const uint8_t* seal,
+                      const double* tne, const double* tse, const double* p, const double* phi,
+                      const double* p_prev, double dt, double cr, const double* vp,
+                      const double* dk, double h, double* r_im) {
+  if (!valid(g, f, p, kx) || !ky || !kz || !r_im) return -1;
+  if ((tne != nullptr) != (tse != nullptr)) return -1;
+  if (phi && (!p_prev || !(dt > 0.0))) return -1;
+  const int64_t N = g->nx * g->ny * g->nz;
+  auto widen = [N](const double* a) -> cplx* {
+    if (!a) return nullptr;
+    cplx* c = new cplx[N];
+    for (int64_t q = 0; q < N; ++q) c[q] = cplx(a[q], 0.0);
+    return c;
+  };
+  cplx* pc = new cplx[N];
+  cplx* kc[3] = {new cplx[N], new cplx[N], new cplx[N]};
+  const double* ks[3] = {kx, ky, kz};
+  for (int64_t q = 0; q < N; ++q) {
+    pc[q] = cplx(p[q], vp ? h * vp[q] : 0.0);
+    // exp(ln k + i h d) = k exp(i h d)
+    for (int a = 0; a < 3; ++a)
+      kc[a][q] = dk ? ks[a][q] * std::exp(cplx(0.0, h * dk[a * N + q])) : cplx(ks[a][q], 0.0);
+  }
+  cplx *nc = widen(tne), *sc = widen(tse), *fc = widen(phi), *qc = widen(p_prev);
+  cplx* rc = new cplx[N];
+  Problem<cplx> pb{g, f, pc, kc[0], kc[1], kc[2], 1.0, 1.0, seal, nullptr};
+  pb.tne = nc;
+  pb.tse = sc;
+  pb.phi = fc;
+  pb.p_prev = qc;
+  pb.dt = dt;
+  pb.cr = cr;
+  Outputs o;
+  o.r = rc;
+  assemble(pb, o);
+  for (int64_t q = 0; q < N; ++q) r_im[q] = rc[q].imag();
+  for (cplx* a : {pc, kc[0], kc[1], kc[2], nc, sc, fc, qc, rc}) delete[] a;
   return 0;
 }
 

@@ -44,6 +44,14 @@ int oracle_vjp_general(const oracle_grid*, const oracle_fluid*, const double*, d
                        const double*, const double*, double*, double*, double*);
 int oracle_trans_cs(const oracle_grid*, const oracle_fluid*, const double*, const double*,
                     const double*, const double*, const double*, double, double*);
+int oracle_eval_k3(const oracle_grid*, const oracle_fluid*, const double*, const double*,
+                   const double*, const uint8_t*, const double*, const double*, const double*,
+                   const double*, const double*, double, double, const double*, const double*,
+                   double*, double*, double*, double*, double*, double*, double*);
+int oracle_eval_k3_cs(const oracle_grid*, const oracle_fluid*, const double*, const double*,
+                      const double*, const uint8_t*, const double*, const double*,
+                      const double*, const double*, const double*, double, double,
+                      const double*, const double*, double, double*);
 }
 
 static double unif(uint64_t& s, double a, double b) {
@@ -103,6 +111,15 @@ int main() {
                                 gs.data()) != 0;
     fails += oracle_trans_cs(&g, &fl, t.data(), t.data() + N, t.data() + 2 * N, p.data(),
                              d.data(), 1e-20, ri.data()) != 0;
+    std::vector<double> gk(3 * N), gks(3 * N);
+    fails += oracle_eval_k3(&g, &fl, k.data(), t.data(), t.data() + N, seal.data(),
+                            t.data() + 2 * N, t.data() + 3 * N, p.data(), phi.data(), pn.data(),
+                            3600.0, 5e-10, v.data(), w.data(), r.data(), J.data(), jv.data(),
+                            sc.data(), gp.data(), gk.data(), gks.data()) != 0;
+    fails += oracle_eval_k3_cs(&g, &fl, k.data(), t.data(), t.data() + N, seal.data(),
+                               t.data() + 2 * N, t.data() + 3 * N, p.data(), phi.data(),
+                               pn.data(), 3600.0, 5e-10, v.data(), d.data(), 1e-20,
+                               ri.data()) != 0;
   }
   std::printf("oracle sanitizer driver: %d failed calls\n", fails);
   return fails == 0 ? 0 : 1;
