@@ -70,12 +70,15 @@ typedef struct {
   double rho0, cf, p0, mu;
 } tpfa_fluid_t;
 
-/* Rock, in one of two forms.
-   Permeability form: kx (m^2, dtype of the precision) is required. ky and kz
-   must be NULL: the y and z permeabilities are ry*kx and rz*kx (ry, rz >= 0)
-   and each face gets the two-point harmonic transmissibility. seal may be
-   NULL; bit a (0, 1, 2 = x, y, z) of seal[idx] closes the face between the
-   cell and its +a neighbour (bits on domain-boundary faces are ignored).
+/* Rock, in one of three forms.
+   Permeability form: kx (m^2, dtype of the precision) is required. With ky
+   and kz NULL the y and z permeabilities are ry*kx and rz*kx (ry, rz >= 0);
+   with ky and kz both given (per-direction form: arrays of the same layout
+   and dtype) each face along axis a takes k_a of its two cells and ry, rz
+   are ignored. Each face gets the two-point harmonic transmissibility
+   (Sec. 3). Only one of ky, kz: TPFA_ERR_NULL. seal may be NULL; bit a
+   (0, 1, 2 = x, y, z) of seal[idx] closes the face between the cell and its
+   +a neighbour (bits on domain-boundary faces are ignored).
    Transmissibility form: tx, ty, tz (m^3, dtype of the precision) give the
    transmissibility of the face between cell idx and its +x, +y, +z neighbour
    directly (the face-centred data the paper stores with each cell, Sec. 5,
@@ -83,7 +86,7 @@ typedef struct {
    ignored and T = 0 closes a face. Then kx, ky, kz and seal must be NULL and
    ry, rz are ignored. Supported by every entry point except
    tpfa_residual_vjp (use tpfa_residual_vjp_trans) and the batch
-   (TPFA_ERR_UNSUPPORTED). */
+   (TPFA_ERR_UNSUPPORTED); the batch also rejects the per-direction form. */
 typedef struct {
   const void *kx, *ky, *kz;
   double ry, rz;
@@ -134,8 +137,10 @@ int tpfa_jacobian(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
 /* Vector-Jacobian product of the residual with the cotangent w[ncell]:
    grad_p = J^T w (with respect to p, i.e. to dp in the precision form) and
    grad_logk[j] = sum_K w_K d r_K / d ln(kx_j), ky = ry kx and kz = rz kx
-   following kx. The upwind choice is recomputed, not stored. Either output may
-   be NULL (not both). Unsupported (TPFA_ERR_UNSUPPORTED) with ky/kz arrays. */
+   following kx. In the per-direction form (ky, kz arrays) grad_logk holds
+   three planes [3][ncell]: d(w.r)/d ln kx, ln ky, ln kz of each cell. The
+   upwind choice is recomputed, not stored. Either output may be NULL (not
+   both). The transmissibility form has tpfa_residual_vjp_trans. */
 int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                       const tpfa_rock_t *rock, const tpfa_state_t *state,
                       tpfa_precision_t prec, const void *w, void *grad_p,
@@ -238,8 +243,9 @@ typedef enum { TPFA_BATCH_RESIDUAL = 0, TPFA_BATCH_JACOBIAN = 1 } tpfa_batch_mod
 
 typedef struct tpfa_batch tpfa_batch_t; /* opaque */
 
-/* Builds the work list (one item per tile and z-chunk of every model, in
-   descending cost order) and the model table on the device (the batch owns
+/* Builds the work list (one item per tile and z-chunk of every model, models
+   in the given order, each in z-chunk, tile-row, tile order) and the model
+   table on the device (the batch owns
    these two device buffers and a work counter), and captures one persistent
    kernel launch into a HIP graph. `stream` orders the uploads. */
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
@@ -255,7 +261,8 @@ int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream);
    TPFA_SCHEDULE_PERSISTENT (default): one workgroup per CU slot, taking work
    items from a device counter until the list is drained;
    TPFA_SCHEDULE_GROUPED: one workgroup per work item, dispatched by the
-   hardware. Re-captures the batch's graph; results are identical. */
+   hardware, the list cut into 8 contiguous bands, one per XCD.
+   Re-captures the batch's graph; results are identical. */
 #define TPFA_SCHEDULE_PERSISTENT 0
 #define TPFA_SCHEDULE_GROUPED 1
 int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule);

@@ -65,12 +65,23 @@ def _need(t, name, dtype, n, device):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _inputs(grid, kx, p, seal, pref, trans=None):
+def _kyz(ky, kz):
+    if (ky is None) != (kz is None):
+        raise ValueError("ky and kz go together (per-direction permeability arrays)")
+    return None if ky is None else (ky, kz)
+
+
+def _inputs(grid, kx, p, seal, pref, trans=None, kyz=None):
     n = int(grid.nx) * int(grid.ny) * int(grid.nz)
     prec = _prec(p)
     dt = p.dtype
     dev = p.device
     _need(p, "p", dt, n, None)
+    if kyz is not None:
+        if trans is not None:
+            raise ValueError("give either permeabilities (kx, ky, kz) or trans, not both")
+        _need(kyz[0], "ky", dt, n, dev)
+        _need(kyz[1], "kz", dt, n, dev)
     if trans is not None:
         if kx is not None or seal is not None:
             raise ValueError("give either kx (and seal) or trans=(tx, ty, tz), not both")
@@ -89,21 +100,21 @@ def _inputs(grid, kx, p, seal, pref, trans=None):
     return n, prec, dt, dev
 
 
-def _rock(kx, seal, ry, rz, trans=None) -> L.Rock:
+def _rock(kx, seal, ry, rz, trans=None, ky=None, kz=None) -> L.Rock:
     tx, ty, tz = trans if trans is not None else (None, None, None)
-    return L.Rock(_ptr(kx), None, None, float(ry), float(rz), _ptr(seal), _ptr(tx), _ptr(ty),
-                  _ptr(tz))
+    return L.Rock(_ptr(kx), _ptr(ky), _ptr(kz), float(ry), float(rz), _ptr(seal), _ptr(tx),
+                  _ptr(ty), _ptr(tz))
 
 
-def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
              trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                              C.byref(_rock(kx, seal, ry, rz, trans)),
+                              C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
                               _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return r
@@ -114,11 +125,11 @@ def _launch_ref(tile, kz_chunk, xcd_remap):
     return None if ln is None else C.byref(ln)
 
 
-def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r=True,
+def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, want_r=True,
              r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = None
     if want_r:
         r = r_out if r_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -127,33 +138,34 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, want_r
     _need(J, "J_out", dt, 7 * n, dev)
     lib = L.load()
     L.check(lib.tpfa_jacobian(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                              C.byref(_rock(kx, seal, ry, rz, trans)),
+                              C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
                               _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return r, J
 
 
-def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
+def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
                  want_p=True, want_logk=True, gp_out=None, gm_out=None, trans=None, tile=None,
                  kz_chunk=None, xcd_remap=False):
     """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None. With
     ``trans`` = (tx, ty, tz) the second output is grad_logt [3, nz, ny, nx]:
-    d(w.r)/d ln T of each cell's +x, +y, +z face."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    d(w.r)/d ln T of each cell's +x, +y, +z face. With per-direction arrays
+    ``ky``, ``kz`` it is [3, nz, ny, nx]: d(w.r)/d ln kx, ln ky, ln kz."""
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     _need(w, "w", dt, n, dev)
-    planes = 3 if trans is not None else 1
+    planes = 3 if trans is not None or ky is not None else 1
     gp = gm = None
     if want_p:
         gp = gp_out if gp_out is not None else torch.empty(p.shape, dtype=dt, device=dev)
         _need(gp, "gp_out", dt, n, dev)
     if want_logk:
-        shape = ((3,) if trans is not None else ()) + tuple(p.shape)
+        shape = ((3,) if planes == 3 else ()) + tuple(p.shape)
         gm = gm_out if gm_out is not None else torch.empty(shape, dtype=dt, device=dev)
         _need(gm, "gm_out", dt, planes * n, dev)
     lib = L.load()
     fn = lib.tpfa_residual_vjp_trans if trans is not None else lib.tpfa_residual_vjp
     L.check(fn(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-               C.byref(_rock(kx, seal, ry, rz, trans)), C.byref(L.State(_ptr(p), _ptr(pref))),
+               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)), C.byref(L.State(_ptr(p), _ptr(pref))),
                prec, _ptr(w), _ptr(gp), _ptr(gm), _launch_ref(tile, kz_chunk, xcd_remap),
                _stream(dev)), lib)
     return gp, gm
@@ -169,11 +181,11 @@ def _accum(accum, dt_, n, dev):
     return L.Accum(_ptr(phi), _ptr(p_prev), float(accum["dt"]), float(accum.get("cr", 0.0)))
 
 
-def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
                 trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
     the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     acc = _accum(accum, dt, n, dev)
     if acc is None:
         raise ValueError("residual_be needs accum")
@@ -181,18 +193,18 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                 C.byref(_rock(kx, seal, ry, rz, trans)),
+                                 C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)),
             lib)
     return r
 
 
-def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0,
+def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
                 want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
                 xcd_remap=False):
     """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     acc = _accum(accum, dt, n, dev)
     if acc is None:
         raise ValueError("jacobian_be needs accum")
@@ -204,18 +216,18 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     _need(J, "J_out", dt, 7 * n, dev)
     lib = L.load()
     L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                 C.byref(_rock(kx, seal, ry, rz, trans)),
+                                 C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap),
                                  _stream(dev)), lib)
     return r, J
 
 
-def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0,
+def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
         want_r=False, out=None, r_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
     """Matrix-free J v of the flux residual, or of the backward-Euler residual
     when ``accum`` is given; returns (jv, r or None)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     _need(v, "v", dt, n, dev)
     acc = _accum(accum, dt, n, dev)
     jv = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -226,24 +238,24 @@ def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1
         _need(r, "r_out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_jvp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                         C.byref(_rock(kx, seal, ry, rz, trans)), C.byref(L.State(_ptr(p), _ptr(pref))),
+                         C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)), C.byref(L.State(_ptr(p), _ptr(pref))),
                          None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
                          _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
     return jv, r
 
 
-def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, out=None,
+def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
                trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
     faces with caller-supplied transmissibilities tne, tse)."""
-    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans)
+    n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     _need(tne, "tne", dt, n, dev)
     _need(tse, "tse", dt, n, dev)
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
     _need(r, "out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_residual10(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                                C.byref(_rock(kx, seal, ry, rz, trans)),
+                                C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                 C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
                                 _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap),
                                 _stream(dev)), lib)
@@ -432,4 +444,46 @@ class TPFATransResidual(torch.autograd.Function):
         if dp is None:
             return torch.zeros_like(p)
         jv, _ = jvp(grid, fluid, None, p, dp.contiguous(), pref=pref, trans=(t[0], t[1], t[2]))
+        return jv
+
+
+class TPFAAnisoResidual(torch.autograd.Function):
+    """r(p, ln k) in the per-direction permeability form, with a hand-written
+    adjoint.
+
+    forward: k = exp(logk3), logk3 of shape [3, nz, ny, nx] (ln kx, ln ky,
+    ln kz of every cell), then the residual kernel; backward: the
+    vector-Jacobian kernel returns (J^T w, d(w.r)/d ln k per direction).
+    Forward mode in p uses the Jacobian-vector product kernel. Non-tensor
+    arguments: grid, fluid, seal, pref."""
+
+    @staticmethod
+    def forward(ctx, p, logk3, grid, fluid, seal=None, pref=None):
+        k = torch.exp(logk3)
+        r = residual(grid, fluid, k[0], p, seal=seal, pref=pref, ky=k[1], kz=k[2])
+        ctx.save_for_backward(p, k)
+        ctx.save_for_forward(p, k)
+        ctx.cfg = (grid, fluid, seal, pref)
+        return r
+
+    @staticmethod
+    def backward(ctx, w):
+        p, k = ctx.saved_tensors
+        grid, fluid, seal, pref = ctx.cfg
+        gp, gk = residual_vjp(grid, fluid, k[0], p, w.contiguous(), seal=seal, pref=pref,
+                              ky=k[1], kz=k[2], want_p=ctx.needs_input_grad[0],
+                              want_logk=ctx.needs_input_grad[1])
+        return gp, gk, None, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dp, dlogk3, *_):
+        if dlogk3 is not None and bool(dlogk3.any()):  # zero tangents are passed too
+            raise NotImplementedError("forward-mode derivative with respect to ln k; "
+                                      "use reverse mode (backward) for it")
+        p, k = ctx.saved_tensors
+        grid, fluid, seal, pref = ctx.cfg
+        if dp is None:
+            return torch.zeros_like(p)
+        jv, _ = jvp(grid, fluid, k[0], p, dp.contiguous(), seal=seal, pref=pref, ky=k[1],
+                    kz=k[2])
         return jv

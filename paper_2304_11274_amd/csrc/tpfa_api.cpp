@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -78,9 +79,11 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
       return fail(TPFA_ERR_PARAM, "give either kx (and seal) or tx/ty/tz, not both");
   } else {
     if (!rk->kx) return fail(TPFA_ERR_NULL, "rock.kx is NULL");
-    if (rk->ky || rk->kz)
-      return fail(TPFA_ERR_UNSUPPORTED, "ky/kz arrays are not supported; use ry/rz ratios");
-    if (!(rk->ry >= 0) || !(rk->rz >= 0) || !is_finite(rk->ry) || !is_finite(rk->rz))
+    if ((rk->ky != nullptr) != (rk->kz != nullptr))
+      return fail(TPFA_ERR_NULL, "rock.ky and rock.kz go together (both arrays or both NULL)");
+    // with ky and kz arrays the ratios are not used
+    if (!rk->ky &&
+        (!(rk->ry >= 0) || !(rk->rz >= 0) || !is_finite(rk->ry) || !is_finite(rk->rz)))
       return fail(TPFA_ERR_PARAM, "ry and rz must be finite and >= 0");
   }
   if (!st->p) return fail(TPFA_ERR_NULL, "state.p is NULL");
@@ -148,9 +151,11 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.cf = f.cf;
   a.p0 = f.p0;
   a.mu = f.mu;
+  // per-direction arrays carry their own scale: no ratios then
+  const bool k3 = rk.ky != nullptr;
   a.a2x = 2.0 * a.ax;
-  a.a2y = 2.0 * a.ay * rk.ry;
-  a.a2z = 2.0 * a.az * rk.rz;
+  a.a2y = 2.0 * a.ay * (k3 ? 1.0 : rk.ry);
+  a.a2z = 2.0 * a.az * (k3 ? 1.0 : rk.rz);
   a.inv_mu = 1.0 / f.mu;
   a.G = g.gk * g.dz;
   a.hc = 0.5 * f.cf * a.G;
@@ -164,6 +169,8 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.p = st.p;
   a.pref = st.pref;
   a.kx = rk.kx;
+  a.ky = rk.ky;
+  a.kz = rk.kz;
   a.seal = rk.seal;
   a.tx = rk.tx;
   a.ty = rk.ty;
@@ -195,6 +202,16 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   return TPFA_OK;
 }
 
+// Output store kind: the FP32 kernels write with ordinary stores unless every
+// output row starts on a 128-byte line (row length and output base pointers);
+// the FP64 kernels always write non-temporal (measured faster either way).
+void set_store_kind(tpfa::Args &a, tpfa_precision_t prec) {
+  bool lines = ((int64_t)a.nx * 4) % 128 == 0;
+  for (const void *q : {a.r, a.J, a.gp, a.gm, a.jv})
+    if (q && reinterpret_cast<uintptr_t>(q) % 128 != 0) lines = false;
+  a.plain = prec == TPFA_FP32 && !lines ? 1 : 0;
+}
+
 int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t *rk,
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
@@ -217,10 +234,12 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   b.cr = a.cr;
   b.vdtf = a.vdtf;
   b.crf = a.crf;
+  set_store_kind(b, prec);
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
-  // the transmissibility form runs the same modes with the input flag
-  const tpfa::Mode m = rk->tx ? static_cast<tpfa::Mode>(mode | tpfa::MODE_TRANS) : mode;
+  // the transmissibility and per-direction forms run the same modes with a flag
+  const int form = rk->tx ? tpfa::MODE_TRANS : rk->ky ? tpfa::MODE_K3 : 0;
+  const tpfa::Mode m = static_cast<tpfa::Mode>(mode | form);
   const hipError_t e = tpfa::launch_march(prec, m, tile, b, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
@@ -499,18 +518,15 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     if (mode != TPFA_BATCH_RESIDUAL && mode != TPFA_BATCH_JACOBIAN)
       return fail(TPFA_ERR_PARAM, "unknown batch mode");
     std::vector<tpfa::Args> args(n_models);
-    struct Item {
-      tpfa::WorkItem w;
-      int64_t cells;
-    };
-    std::vector<Item> items;
+    std::vector<tpfa::WorkItem> wl;
     for (int m = 0; m < n_models; ++m) {
       const tpfa_model_t &md = models[m];
       int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
       if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
-      if (md.rock.tx)
-        return fail(TPFA_ERR_UNSUPPORTED,
-                    "model " + std::to_string(m) + ": the batch needs the permeability form");
+      if (md.rock.tx || md.rock.ky)
+        return fail(TPFA_ERR_UNSUPPORTED, "model " + std::to_string(m) +
+                                              ": the batch needs the permeability form with "
+                                              "ry, rz ratios");
       if (mode == TPFA_BATCH_JACOBIAN && !md.J)
         return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": J is NULL");
       if (mode == TPFA_BATCH_RESIDUAL && !md.r)
@@ -526,25 +542,16 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       tpfa::make_args(args[m], md.grid, md.fluid, md.rock, md.state, tile, kz, flags);
       args[m].r = md.r;
       args[m].J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
+      // natural order: a tile's x neighbours follow it, so they run together
+      // and share their halo cells and the output lines at their common edge
+      // in L2
       const tpfa::Args &a = args[m];
-      const tpfa::TileShape ts = tpfa::kTiles[tile];
       for (int bz = 0; bz < a.nzc; ++bz)
         for (int by = 0; by < a.nty; ++by)
-          for (int bx = 0; bx < a.ntx; ++bx) {
-            const int64_t cx = std::min<int64_t>(ts.tx, a.nx - (int64_t)bx * ts.tx);
-            const int64_t cy = std::min<int64_t>(ts.ty, a.ny - (int64_t)by * ts.ty);
-            const int64_t cz = std::min<int64_t>(a.kz_chunk, a.nz - (int64_t)bz * a.kz_chunk);
-            items.push_back({{m, bx, by, bz * a.kz_chunk}, cx * cy * cz});
-          }
+          for (int bx = 0; bx < a.ntx; ++bx) wl.push_back({m, bx, by, bz * a.kz_chunk});
+      if (wl.size() > (size_t)std::numeric_limits<uint32_t>::max() / 2)
+        return fail(TPFA_ERR_SHAPE, "too many work items");
     }
-    if (items.size() > (size_t)std::numeric_limits<uint32_t>::max() / 2)
-      return fail(TPFA_ERR_SHAPE, "too many work items");
-    // full-size items first in natural order (neighbouring tiles of one model
-    // run together and share their halos in L2), partial items fill the tail
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item &x, const Item &y) { return x.cells > y.cells; });
-    std::vector<tpfa::WorkItem> wl(items.size());
-    for (size_t q = 0; q < items.size(); ++q) wl[q] = items[q].w;
 
     tpfa_batch *b = new tpfa_batch;
     b->prec = prec;

@@ -24,8 +24,17 @@ enum Mode : int {
 // Flag added to a mode: the face transmissibilities are inputs (tx, ty, tz)
 // instead of the harmonic average of kx.
 constexpr int MODE_TRANS = 8;
+// Flag added to an FP32 mode: the outputs are written with ordinary stores
+// instead of non-temporal ones (grids whose rows do not start on 128-byte
+// lines).
+constexpr int MODE_PLAIN = 16;
+// Flag added to a mode: per-direction permeability arrays (kx, ky, kz), each
+// face taking the harmonic average of its own direction's k (no ratios).
+constexpr int MODE_K3 = 32;
 constexpr int mode_kind(int m) { return m & 7; }
 constexpr bool has_trans(int m) { return (m & MODE_TRANS) != 0; }
+constexpr bool has_plain_stores(int m) { return (m & MODE_PLAIN) != 0; }
+constexpr bool has_k3(int m) { return (m & MODE_K3) != 0; }
 constexpr int base_mode(int m) {
   return mode_kind(m) == MODE_RESIDUAL_BE   ? MODE_RESIDUAL
          : mode_kind(m) == MODE_JACOBIAN_BE ? MODE_JACOBIAN
@@ -56,7 +65,7 @@ struct Args {
   int32_t ntx, nty, nzc;  // tiles along x, y and z chunks
   int32_t remap;      // 1: XCD-aware workgroup order
   int32_t tile;       // index into kTiles
-  int32_t pad_;
+  int32_t plain;      // 1: ordinary output stores (FP32 rows off 128-byte lines)
   int64_t plane;      // nx * ny
   int64_t nblocks;    // ntx * nty * nzc
   // transmissibility geometric factors a_d and directional ratios (y, z)
@@ -78,6 +87,8 @@ struct Args {
   const void *p;
   const double *pref;
   const void *kx;
+  const void *ky;     // per-direction form: y and z permeabilities (else NULL)
+  const void *kz;
   const uint8_t *seal;
   const void *w;      // cotangent (VJP) or direction v (JVP)
   const void *phi;    // reference porosity per cell (backward-Euler modes)
@@ -90,7 +101,8 @@ struct Args {
   void *r;
   void *J;
   void *gp;
-  void *gm;           // grad ln kx, or grad ln T [3][ncell] in the transmissibility form
+  void *gm;           // grad ln kx; grad ln T [3][ncell] in the transmissibility form,
+                      // grad ln kx, ln ky, ln kz [3][ncell] in the per-direction form
   void *jv;           // J v (JVP modes)
 };
 

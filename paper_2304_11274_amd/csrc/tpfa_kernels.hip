@@ -63,6 +63,7 @@ struct Cell {
   S tn, ts;    // diagonal transmissibilities (10-flux stencil only)
   S phi, pn;   // reference porosity and previous-level pressure (backward-Euler modes)
   S tx, ty, tz;  // transmissibilities of the +x, +y, +z faces (transmissibility input)
+  S ky, kz;    // y and z permeabilities (per-direction form; k holds kx)
   uint32_t s;  // seal bits
 };
 
@@ -235,9 +236,18 @@ __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open
 template <class T>
 using gptr = __attribute__((address_space(1))) T *;
 
-template <class T>
-__device__ __forceinline__ void st_nt(T *p, T v) {
-  __builtin_nontemporal_store(v, (gptr<T>)p);
+// Output store: non-temporal, or ordinary with the MODE_PLAIN flag. Where the
+// rows of a grid do not start on 128-byte lines, the line at a tile's x edge
+// is shared with the neighbouring tile; ordinary stores let the two parts meet
+// in L2 before the line is written back, which measured much faster on MI355X
+// for the FP32 kernels (a 64-cell FP32 row touches three lines, two of them
+// partial) and slower for FP64 (five lines, two partial).
+template <int MODE, class T>
+__device__ __forceinline__ void st_out(T *p, T v) {
+  if constexpr (has_plain_stores(MODE))
+    *(gptr<T>)p = v;
+  else
+    __builtin_nontemporal_store(v, (gptr<T>)p);
 }
 
 // LDS of one workgroup (gfx950: 160 KiB per CU, all of it addressable by one
@@ -257,19 +267,20 @@ constexpr int share_lds_bytes() {
 template <class S, int MODE, int TX, int TY>
 constexpr bool tile_shares() {
   return (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) && sizeof(S) == 8 &&
-         share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
+         !has_k3(MODE) && share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
 
 // Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
 // p, k (or t_x), mobility, seal, plus w / v for the product modes, t_ne and
-// t_se for the 10-flux stencil and t_y for the transmissibility form; or the
-// shared-face layout.
+// t_se for the 10-flux stencil, t_y for the transmissibility form and k_y for
+// the per-direction form; or the shared-face layout.
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
   constexpr int B = base_mode(MODE);
   constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) +
-                         (mode_kind(MODE) == MODE_RES10 ? 2 : 0) + (has_trans(MODE) ? 1 : 0);
+                         (mode_kind(MODE) == MODE_RES10 ? 2 : 0) +
+                         (has_trans(MODE) || has_k3(MODE) ? 1 : 0);
   return tile_shares<S, MODE, TX, TY>() ? share_lds_bytes<S, MODE, TX, TY>()
                                         : 2 * HW * ((int)sizeof(S) * arrays + 1);
 }
@@ -281,7 +292,7 @@ constexpr uint32_t kPX = 1, kPY = 2, kNE = 4, kSE = 8;
 // shares with the tile, so each side of the ring loads only what those faces
 // read (the own cell loads everything).
 constexpr uint32_t kNeedK = 1, kNeedSeal = 2, kNeedTx = 4, kNeedTy = 8, kNeedTn = 16,
-                   kNeedTs = 32, kNeedW = 64, kNeedAll = 127;
+                   kNeedTs = 32, kNeedW = 64, kNeedKy = 128, kNeedAll = 255;
 
 // Fluxes of a plane whose residual is completed at the next plane: its own
 // lower-cell faces (+x, +y, +x+y, +x-y) and its two z faces.
@@ -348,20 +359,35 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
   const size_t ko = (size_t)k * plane;
   if constexpr (BASE == MODE_VJP) {
     // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
-    double gp = 0.0, gm = 0.0;
+    // per-direction form: the faces of axis d feed the ln k_d gradient only
+    double gp = 0.0, gm = 0.0, gq[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < 6; ++n) {
       const double d = (double)c0.w - (double)wn[n];
       if (n & 1) {  // own cell is Lo
         gp = fma(d, (double)f[n].dLo, gp);
-        if constexpr (!has_trans(MODE)) gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
+        if constexpr (has_k3(MODE))
+          gq[n >> 1] = fma(d, (double)(f[n].F * f[n].qUp), gq[n >> 1]);
+        else if constexpr (!has_trans(MODE))
+          gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
       } else {      // own cell is Up
         gp = fma(-d, (double)f[n].dUp, gp);
-        if constexpr (!has_trans(MODE)) gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
+        if constexpr (has_k3(MODE))
+          gq[n >> 1] = fma(-d, (double)(f[n].F * f[n].qLo), gq[n >> 1]);
+        else if constexpr (!has_trans(MODE))
+          gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
       }
     }
-    if (a.gp) st_nt(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
-    if constexpr (has_trans(MODE)) {
+    if (a.gp) st_out<MODE>(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
+    if constexpr (has_k3(MODE)) {
+      // d(w.r)/d ln kx, ln ky, ln kz of the own cell, three planes [x, y, z]
+      if (a.gm) {
+        const size_t nc = (size_t)nz * plane;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          st_out<MODE>(at_w(static_cast<S *>(a.gm), (size_t)d * nc + ko, cb), (S)gq[d]);
+      }
+    } else if constexpr (has_trans(MODE)) {
       // given T: d(w.r)/d ln T of the +x, +y, +z face (own cell is its lower
       // cell) is (w_C - w_N) F, stored as three planes [x, y, z]
       if (a.gm) {
@@ -370,11 +396,11 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
         for (int d = 0; d < 3; ++d) {
           const int n = 2 * d + 1;
           const double g = ((double)c0.w - (double)wn[n]) * (double)f[n].F;
-          st_nt(at_w(static_cast<S *>(a.gm), (size_t)d * nc + ko, cb), (S)g);
+          st_out<MODE>(at_w(static_cast<S *>(a.gm), (size_t)d * nc + ko, cb), (S)g);
         }
       }
     } else if (a.gm) {
-      st_nt(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
+      st_out<MODE>(at_w(static_cast<S *>(a.gm), ko, cb), (S)gm);
     }
   } else {
     double acc = 0.0;
@@ -391,7 +417,7 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
 #pragma unroll
         for (int n = 0; n < 4; ++n) r = (n & 1) ? r + (double)fd[n] : r - (double)fd[n];
       }
-      if (a.r) st_nt(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
+      if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
     }
     if constexpr (BASE == MODE_JACOBIAN) {
       S *J = static_cast<S *>(a.J);
@@ -399,10 +425,10 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
       S dg = dacc;
 #pragma unroll
       for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
-      st_nt(at_w(J, ko, cb), dg);
+      st_out<MODE>(at_w(J, ko, cb), dg);
 #pragma unroll
       for (int n = 0; n < 6; ++n)
-        st_nt(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
+        st_out<MODE>(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
     }
     if constexpr (BASE == MODE_JVP) {
       // (J v)_C = dacc v_C + sum over faces of dF_CN/dp_C v_C + dF_CN/dp_N v_N,
@@ -414,7 +440,7 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
         const S dN = (n & 1) ? f[n].dUp : -f[n].dLo;
         jv = jv + (double)(dC * c0.w + dN * wn[n]);
       }
-      st_nt(at_w(static_cast<S *>(a.jv), ko, cb), (S)jv);
+      st_out<MODE>(at_w(static_cast<S *>(a.jv), ko, cb), (S)jv);
     }
   }
 }
@@ -432,6 +458,8 @@ struct Tile {
 
   static constexpr bool R10 = mode_kind(MODE) == MODE_RES10;
   static constexpr bool TIN = has_trans(MODE);  // transmissibilities are inputs
+  static constexpr bool K3 = has_k3(MODE);      // per-direction permeability arrays
+  static constexpr bool YF = TIN || K3;         // a y-face field is staged (t_y or k_y)
   static constexpr bool SHARE = tile_shares<S, MODE, TX, TY>();
   static constexpr int NT = TX * TY;          // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
@@ -448,7 +476,8 @@ struct Tile {
   const Args &a;
   S *s_p, *s_k, *s_l, *s_w, *s_tn, *s_ts;
   S *s_fx, *s_fy, *s_fne, *s_fse;  // shared-face fluxes (residual-only modes)
-  S *s_ty;  // transmissibility input, two-sided layout only: ty (tx is staged in s_k)
+  S *s_yf;  // y-face field, two-sided layout only: t_y (transmissibility input; t_x is
+            // staged in s_k) or k_y (per-direction form; k_x is staged in s_k)
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
@@ -471,8 +500,8 @@ struct Tile {
     s_w = s_l + 2 * HW;
     s_tn = s_w + (NEEDW ? 2 * HW : 0);
     s_ts = s_tn + (R10 ? 2 * HW : 0);
-    s_ty = s_ts + (R10 ? 2 * HW : 0);
-    s_s = reinterpret_cast<uint8_t *>(s_ty + (TIN ? 2 * HW : 0));
+    s_yf = s_ts + (R10 ? 2 * HW : 0);
+    s_s = reinterpret_cast<uint8_t *>(s_yf + (YF ? 2 * HW : 0));
     s_fx = s_l + 2 * HW;
     s_fy = s_fx + 2 * HW;
     s_fne = s_fy + 2 * HW;
@@ -506,13 +535,13 @@ struct Tile {
         hj = by * TY - 1;
         l = h + 1;
         role = kPY | (R10 ? kNE : 0u);
-        need = kNeedK | kNeedSeal | kNeedTy | kNeedTn | kNeedW;
+        need = (K3 ? kNeedKy : kNeedK) | kNeedSeal | kNeedTy | kNeedTn | kNeedW;
       } else if (h < 2 * TX) {  // top row: +x-y faces
         hi = bx * TX + h - TX;
         hj = by * TY + TY;
         l = (TY + 1) * W + h - TX + 1;
         role = R10 ? kSE : 0u;
-        need = kNeedK | kNeedTs | kNeedW;
+        need = (K3 ? kNeedKy : kNeedK) | kNeedTs | kNeedW;
       } else if (h < 2 * TX + TY) {  // left column: +x (and both diagonal) faces
         hi = bx * TX - 1;
         hj = by * TY + h - 2 * TX;
@@ -555,9 +584,15 @@ struct Tile {
       c.k = S(0);
       if (need & kNeedTx) c.tx = at(static_cast<const S *>(a.tx), plane, k, b);
       if (need & kNeedTy) c.ty = at(static_cast<const S *>(a.ty), plane, k, b);
-    } else if (need & kNeedK) {
-      const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
-      c.k = ok ? kx : S(0);
+    } else {
+      if (need & kNeedK) {
+        const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
+        c.k = ok ? kx : S(0);
+      }
+      if (K3 && (need & kNeedKy)) {
+        const S ky = at(static_cast<const S *>(a.ky), plane, k, b);
+        c.ky = ok ? ky : S(0);
+      }
     }
     if (need & kNeedSeal) c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
     if (NEEDW && (need & kNeedW)) c.w = at(static_cast<const S *>(a.w), plane, k, b);
@@ -578,6 +613,7 @@ struct Tile {
       c.ty = tyv ? c.ty : S(0);
       c.tz = at(static_cast<const S *>(a.tz), plane, k, cb);
     }
+    if (K3) c.kz = at(static_cast<const S *>(a.kz), plane, k, cb);
     if (ACC) {
       c.phi = at(static_cast<const S *>(a.phi), plane, k, cb);
       c.pn = at(static_cast<const S *>(a.pprev), plane, k, cb);
@@ -615,8 +651,8 @@ struct Tile {
       Cell<S> pr;
       load(pr, kb - 1);
       const Props<S> dp = props(pr.p, xoff(kb - 1), a);
-      f = face_z<DERIV, VJP>(a, pr.k, cur.k, (pr.s & 4u) == 0u, pr.p, cur.p, dpref(kb - 1), dp,
-                             dcur, TIN, pr.tz);
+      f = face_z<DERIV, VJP>(a, K3 ? pr.kz : pr.k, K3 ? cur.kz : cur.k, (pr.s & 4u) == 0u,
+                             pr.p, cur.p, dpref(kb - 1), dp, dcur, TIN, pr.tz);
       f.w = pr.w;
     }
     return f;
@@ -643,7 +679,7 @@ struct Tile {
     // make every face towards them closed: T = 0)
     s_p[b + ol] = c0.p;
     s_k[b + ol] = TIN ? c0.tx : c0.k;
-    if (TIN && !SHARE) s_ty[b + ol] = c0.ty;
+    if (YF && !SHARE) s_yf[b + ol] = TIN ? c0.ty : c0.ky;
     s_l[b + ol] = d0.lam;
     s_s[b + ol] = (uint8_t)c0.s;
     if (NEEDW) s_w[b + ol] = c0.w;
@@ -658,7 +694,7 @@ struct Tile {
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
       s_k[l] = TIN ? h0[q].tx : h0[q].k;
-      if (TIN && !SHARE) s_ty[l] = h0[q].ty;
+      if (YF && !SHARE) s_yf[l] = TIN ? h0[q].ty : h0[q].ky;
       s_l[l] = dh.lam;
       s_s[l] = (uint8_t)h0[q].s;
       if (NEEDW) s_w[l] = h0[q].w;
@@ -682,7 +718,10 @@ struct Tile {
       const int axis = n >> 1;
       const int q = b + sl[n];
       const S pn = s_p[q];
-      const S kn = s_k[q];
+      // k of the neighbour along this face's direction (k_y from its own
+      // array in the per-direction form)
+      const S kn = (K3 && axis == 1) ? s_yf[q] : s_k[q];
+      const S kc = (K3 && axis == 1) ? c0.ky : c0.k;
       const S ln = s_l[q];
       const uint32_t sn = s_s[q];
       if (NEEDW) wn[n] = s_w[q];
@@ -690,19 +729,20 @@ struct Tile {
       const S A2 = axis == 0 ? A2x : A2y;
       if constexpr (TIN) {
         // the face's transmissibility is stored on its lower cell
-        const S T = (n & 1) ? (axis == 0 ? c0.tx : c0.ty) : (axis == 0 ? kn : s_ty[q]);
+        const S T = (n & 1) ? (axis == 0 ? c0.tx : c0.ty) : (axis == 0 ? kn : s_yf[q]);
         f[n] = (n & 1) ? face_ht<DERIV>(a, T, c0.p, pn, d0.lam, ln)
                        : face_ht<DERIV>(a, T, pn, c0.p, ln, d0.lam);
       } else if (n & 1) {
-        f[n] = face_h<DERIV, VJP>(a, A2, c0.k, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
+        f[n] = face_h<DERIV, VJP>(a, A2, kc, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
       } else {
-        f[n] = face_h<DERIV, VJP>(a, A2, kn, c0.k, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
+        f[n] = face_h<DERIV, VJP>(a, A2, kn, kc, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
       }
     }
     f[4] = zm;
     wn[4] = zm.w;
-    zp = face_z<DERIV, VJP>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
-                            has_pz ? dpref(k) : 0.0, d0, d1, TIN, c0.tz);
+    zp = face_z<DERIV, VJP>(a, K3 ? c0.kz : c0.k, K3 ? c1.kz : c1.k,
+                            has_pz && (c0.s & 4u) == 0u, c0.p, c1.p, has_pz ? dpref(k) : 0.0,
+                            d0, d1, TIN, c0.tz);
     zp.w = c0.w;
     f[5] = zp;
     wn[5] = c1.w;
@@ -775,7 +815,7 @@ struct Tile {
       r = r - (double)pd.fse;
       r = r + (double)s_fse[bq + ol + W - 1];
     }
-    if (a.r) st_nt(at_w(static_cast<S *>(a.r), (size_t)k * plane, cb), (S)r);
+    if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), (size_t)k * plane, cb), (S)r);
   }
 
   // One plane k in the shared-face form: stage, complete plane k-1, evaluate
@@ -797,7 +837,6 @@ struct Tile {
 
     s_p[b + ol] = c0.p;
     s_k[b + ol] = TIN ? c0.tx : c0.k;
-    if (TIN && !SHARE) s_ty[b + ol] = c0.ty;
     s_l[b + ol] = d0.lam;
     S hlam[HC];
 #pragma unroll
@@ -807,7 +846,6 @@ struct Tile {
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
       s_k[l] = TIN ? h0[q].tx : h0[q].k;
-      if (TIN && !SHARE) s_ty[l] = h0[q].ty;
       s_l[l] = hlam[q];
     }
     __syncthreads();
@@ -949,8 +987,39 @@ constexpr int persist_lds_bytes() {
                                : TILE == 2 ? a2 : (a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2));
 }
 
-// TILE = 0, 1, 2: every model uses that 256-thread tile (one code path, fewer
-// registers); TILE = kMixedTiles: the tile is read per model.
+// One work item of an ensemble. TILE = 0, 1, 2: every model uses that
+// 256-thread tile (one code path, fewer registers); TILE = kMixedTiles: the
+// tile is read per model.
+template <class S, int MODE, int TILE>
+__device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, char *smem) {
+  if constexpr (TILE == 0) {
+    march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
+  } else if constexpr (TILE == 1) {
+    march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
+  } else if constexpr (TILE == 2) {
+    march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
+  } else {
+    switch (m.tile) {
+      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
+      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
+      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
+    }
+  }
+}
+
+// The FP32 ensemble writes with ordinary stores: ensemble models mostly have
+// rows off 128-byte lines, where these measured much faster, and a per-model
+// choice (both tile bodies in one kernel) cost more registers than it saved
+// on the few aligned models.
+template <class S, int MODE, int TILE>
+__device__ __forceinline__ void run_item(const Args &m, const WorkItem &w, char *smem) {
+  if constexpr (sizeof(S) == 4)
+    march_item<S, MODE | MODE_PLAIN, TILE>(m, w, smem);
+  else
+    march_item<S, MODE, TILE>(m, w, smem);
+}
+
+// The persistent kernel; TILE as for march_item.
 template <class S, int MODE, int TILE>
 __global__ void __launch_bounds__(kPersistThreads)
     persistent_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items,
@@ -969,19 +1038,7 @@ __global__ void __launch_bounds__(kPersistThreads)
     if (threadIdx.x == 0) nxt = atomicAdd(&counter[0], 1u);
     const WorkItem w = items[it];
     const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
-    if constexpr (TILE == 0) {
-      march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
-    } else if constexpr (TILE == 1) {
-      march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
-    } else if constexpr (TILE == 2) {
-      march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
-    } else {
-      switch (m.tile) {
-        case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
-        case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
-        default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
-      }
-    }
+    run_item<S, MODE, TILE>(m, w, smem);
     __syncthreads();  // LDS (and s_item) are reused by the next item
     if (threadIdx.x == 0) s_item = nxt;
     __syncthreads();
@@ -1057,76 +1114,66 @@ static hipError_t launch_t(int tile, const Args &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Every mode kind with the flags F (MODE_TRANS or MODE_K3, MODE_PLAIN) of one
+// instance set.
+template <class S, int F>
+static hipError_t launch_kind(int kind, int tile, const Args &a, hipStream_t st) {
+  switch (kind) {
+    case MODE_RESIDUAL: return launch_t<S, MODE_RESIDUAL | F>(tile, a, st);
+    case MODE_JACOBIAN: return launch_t<S, MODE_JACOBIAN | F>(tile, a, st);
+    case MODE_VJP: return launch_t<S, MODE_VJP | F>(tile, a, st);
+    case MODE_RES10: return launch_t<S, MODE_RES10 | F>(tile, a, st);
+    case MODE_RESIDUAL_BE: return launch_t<S, MODE_RESIDUAL_BE | F>(tile, a, st);
+    case MODE_JACOBIAN_BE: return launch_t<S, MODE_JACOBIAN_BE | F>(tile, a, st);
+    case MODE_JVP: return launch_t<S, MODE_JVP | F>(tile, a, st);
+    case MODE_JVP_BE: return launch_t<S, MODE_JVP_BE | F>(tile, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &a,
                         hipStream_t st) {
   if (a.nblocks <= 0) return hipSuccess;
+  const int kind = mode_kind(mode);
+  const int rock = mode & (MODE_TRANS | MODE_K3);
   if (prec == TPFA_FP64) {
-    switch ((int)mode) {
-      case MODE_RESIDUAL: return launch_t<double, MODE_RESIDUAL>(tile, a, st);
-      case MODE_JACOBIAN: return launch_t<double, MODE_JACOBIAN>(tile, a, st);
-      case MODE_RES10: return launch_t<double, MODE_RES10>(tile, a, st);
-      case MODE_RESIDUAL_BE: return launch_t<double, MODE_RESIDUAL_BE>(tile, a, st);
-      case MODE_JACOBIAN_BE: return launch_t<double, MODE_JACOBIAN_BE>(tile, a, st);
-      case MODE_JVP: return launch_t<double, MODE_JVP>(tile, a, st);
-      case MODE_JVP_BE: return launch_t<double, MODE_JVP_BE>(tile, a, st);
-      case MODE_RESIDUAL | MODE_TRANS: return launch_t<double, MODE_RESIDUAL | MODE_TRANS>(tile, a, st);
-      case MODE_JACOBIAN | MODE_TRANS: return launch_t<double, MODE_JACOBIAN | MODE_TRANS>(tile, a, st);
-      case MODE_RES10 | MODE_TRANS: return launch_t<double, MODE_RES10 | MODE_TRANS>(tile, a, st);
-      case MODE_RESIDUAL_BE | MODE_TRANS:
-        return launch_t<double, MODE_RESIDUAL_BE | MODE_TRANS>(tile, a, st);
-      case MODE_JACOBIAN_BE | MODE_TRANS:
-        return launch_t<double, MODE_JACOBIAN_BE | MODE_TRANS>(tile, a, st);
-      case MODE_JVP | MODE_TRANS: return launch_t<double, MODE_JVP | MODE_TRANS>(tile, a, st);
-      case MODE_JVP_BE | MODE_TRANS: return launch_t<double, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
-      case MODE_VJP: return launch_t<double, MODE_VJP>(tile, a, st);
-      case MODE_VJP | MODE_TRANS: return launch_t<double, MODE_VJP | MODE_TRANS>(tile, a, st);
+    switch (rock) {
+      case 0: return launch_kind<double, 0>(kind, tile, a, st);
+      case MODE_TRANS: return launch_kind<double, MODE_TRANS>(kind, tile, a, st);
+      case MODE_K3: return launch_kind<double, MODE_K3>(kind, tile, a, st);
       default: return hipErrorInvalidValue;
     }
   }
-  switch ((int)mode) {
-    case MODE_RESIDUAL: return launch_t<float, MODE_RESIDUAL>(tile, a, st);
-    case MODE_JACOBIAN: return launch_t<float, MODE_JACOBIAN>(tile, a, st);
-    case MODE_RES10: return launch_t<float, MODE_RES10>(tile, a, st);
-    case MODE_RESIDUAL_BE: return launch_t<float, MODE_RESIDUAL_BE>(tile, a, st);
-    case MODE_JACOBIAN_BE: return launch_t<float, MODE_JACOBIAN_BE>(tile, a, st);
-    case MODE_JVP: return launch_t<float, MODE_JVP>(tile, a, st);
-    case MODE_JVP_BE: return launch_t<float, MODE_JVP_BE>(tile, a, st);
-    case MODE_RESIDUAL | MODE_TRANS: return launch_t<float, MODE_RESIDUAL | MODE_TRANS>(tile, a, st);
-    case MODE_JACOBIAN | MODE_TRANS: return launch_t<float, MODE_JACOBIAN | MODE_TRANS>(tile, a, st);
-    case MODE_RES10 | MODE_TRANS: return launch_t<float, MODE_RES10 | MODE_TRANS>(tile, a, st);
-    case MODE_RESIDUAL_BE | MODE_TRANS:
-      return launch_t<float, MODE_RESIDUAL_BE | MODE_TRANS>(tile, a, st);
-    case MODE_JACOBIAN_BE | MODE_TRANS:
-      return launch_t<float, MODE_JACOBIAN_BE | MODE_TRANS>(tile, a, st);
-    case MODE_JVP | MODE_TRANS: return launch_t<float, MODE_JVP | MODE_TRANS>(tile, a, st);
-    case MODE_JVP_BE | MODE_TRANS: return launch_t<float, MODE_JVP_BE | MODE_TRANS>(tile, a, st);
-    case MODE_VJP: return launch_t<float, MODE_VJP>(tile, a, st);
-    case MODE_VJP | MODE_TRANS: return launch_t<float, MODE_VJP | MODE_TRANS>(tile, a, st);
+  if (a.plain) {
+    switch (rock) {
+      case 0: return launch_kind<float, MODE_PLAIN>(kind, tile, a, st);
+      case MODE_TRANS: return launch_kind<float, MODE_TRANS | MODE_PLAIN>(kind, tile, a, st);
+      case MODE_K3: return launch_kind<float, MODE_K3 | MODE_PLAIN>(kind, tile, a, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (rock) {
+    case 0: return launch_kind<float, 0>(kind, tile, a, st);
+    case MODE_TRANS: return launch_kind<float, MODE_TRANS>(kind, tile, a, st);
+    case MODE_K3: return launch_kind<float, MODE_K3>(kind, tile, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // One workgroup per work item, dispatched by the hardware: the alternative
-// schedule of an ensemble launch (no counter, no item loop).
+// schedule of an ensemble launch (no counter, no item loop). The work list is
+// cut into 8 contiguous bands, one per XCD (workgroup ids go to the XCDs in
+// turn), so neighbouring tiles of a model run on one XCD and meet in its L2.
 template <class S, int MODE, int TILE>
 __global__ void __launch_bounds__(kPersistThreads)
     grouped_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items) {
   __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
-  const WorkItem w = items[blockIdx.x];
+  const uint32_t n = gridDim.x, q = n / 8, rem = n % 8;
+  const uint32_t x = blockIdx.x % 8, l = blockIdx.x / 8;
+  const uint32_t it = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + l;
+  const WorkItem w = items[it];
   const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
-  if constexpr (TILE == 0) {
-    march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
-  } else if constexpr (TILE == 1) {
-    march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
-  } else if constexpr (TILE == 2) {
-    march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
-  } else {
-    switch (m.tile) {
-      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
-      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
-      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
-    }
-  }
+  run_item<S, MODE, TILE>(m, w, smem);
 }
 
 template <class S, int MODE>

@@ -141,10 +141,12 @@ def _flip_force(dphi_faces, ties):
     return force
 
 
-def compare_full(orc, grid, fluid, kx, p, r_gpu, J_gpu, *, tol, tau, ry, rz, seal):
-    """Full-grid comparison of r (and J if given). Returns a report dict."""
+def compare_full(orc, grid, fluid, kx, p, r_gpu, J_gpu, *, tol, tau, ry, rz, seal, ky=None,
+                 kz=None):
+    """Full-grid comparison of r (and J if given); ky, kz: per-direction
+    permeability arrays (then ry, rz are not used). Returns a report dict."""
     want = ("r", "J", "scale", "dphi")
-    ref = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, want=want)
+    ref = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, ky=ky, kz=kz, want=want)
     r_gpu = None if r_gpu is None else np.asarray(r_gpu, np.float64).reshape(ref["r"].shape)
     J_gpu = None if J_gpu is None else np.asarray(J_gpu, np.float64).reshape(ref["J"].shape)
     err = _errs(r_gpu, J_gpu, ref)
@@ -156,7 +158,7 @@ def compare_full(orc, grid, fluid, kx, p, r_gpu, J_gpu, *, tol, tau, ry, rz, sea
         assert not (bad & ~touch).any(), (
             f"{int((bad & ~touch).sum())} cells differ by up to {err[bad & ~touch].max():.3e} "
             "away from any upwind tie")
-        alt = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal,
+        alt = orc.evaluate(grid, fluid, kx, p, ry=ry, rz=rz, seal=seal, ky=ky, kz=kz,
                            force=_flip_force(ref["dphi"], ties), want=("r", "J", "scale"))
         err2 = _errs(r_gpu, J_gpu, alt)
         still = bad & (err2 > tol)

@@ -85,8 +85,8 @@ def case(name, code, **mut):
     case("ry-negative", L.TPFA_ERR_PARAM, ry=-1.0),
     case("rz-nan", L.TPFA_ERR_PARAM, rz=math.nan),
     case("kx-null", L.TPFA_ERR_NULL, kx=None),
-    case("ky-array", L.TPFA_ERR_UNSUPPORTED, ky=DUMMY),
-    case("kz-array", L.TPFA_ERR_UNSUPPORTED, kz=DUMMY),
+    case("ky-without-kz", L.TPFA_ERR_NULL, ky=DUMMY),
+    case("kz-without-ky", L.TPFA_ERR_NULL, kz=DUMMY),
     case("p-null", L.TPFA_ERR_NULL, p=None),
     case("fp32-no-pref", L.TPFA_ERR_UNSUPPORTED, prec=L.TPFA_FP32),
     case("unknown-precision", L.TPFA_ERR_PARAM, prec=7),
@@ -132,10 +132,10 @@ def test_jacobian_and_vjp_validation(lib):
     assert lib.tpfa_jacobian(*args, DUMMY, None, None, None) == L.TPFA_ERR_NULL
     assert lib.tpfa_residual_vjp(*args, None, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL
     assert lib.tpfa_residual_vjp(*args, DUMMY, None, None, None, None) == L.TPFA_ERR_NULL
-    rk2 = L.Rock(DUMMY.value, DUMMY.value, None, 1.0, 1.0, None)
+    rk2 = L.Rock(DUMMY.value, DUMMY.value, None, 1.0, 1.0, None)  # ky without kz
     assert lib.tpfa_residual_vjp(C.byref(g), C.byref(f), C.byref(rk2), C.byref(st),
                                  L.TPFA_FP64, DUMMY, DUMMY, DUMMY, None,
-                                 None) == L.TPFA_ERR_UNSUPPORTED
+                                 None) == L.TPFA_ERR_NULL
     g.nz = 0
     assert lib.tpfa_jacobian(*args, DUMMY, DUMMY, None, None) == L.TPFA_ERR_SHAPE
 
@@ -237,6 +237,27 @@ def test_transmissibility_form_validation(lib):
                                  None) == L.TPFA_ERR_UNSUPPORTED
     m = (L.Model * 1)()
     m[0] = L.Model(g, f, ok, st, DUMMY.value, DUMMY.value, L.Launch(-1, 0, 0))
+    out = C.c_void_p()
+    assert lib.tpfa_batch_create(m, 1, L.TPFA_FP64, L.TPFA_BATCH_JACOBIAN, C.byref(out),
+                                 None) == L.TPFA_ERR_UNSUPPORTED
+
+
+def test_per_direction_form_validation(lib):
+    """ky and kz go together, the ratios are not checked in that form (a
+    negative ry fails only without the arrays), and the batch rejects it."""
+    g, f, _, st = good()
+    args = lambda rk: (C.byref(g), C.byref(f), C.byref(rk), C.byref(st))  # noqa: E731
+    D = DUMMY.value
+    assert lib.tpfa_residual(*args(L.Rock(D, None, None, -1.0, 1.0, None, None, None, None)),
+                             L.TPFA_FP64, None, None, None) == L.TPFA_ERR_PARAM
+    # with the arrays the ratios are ignored: the next failure is the NULL output
+    assert lib.tpfa_residual(*args(L.Rock(D, D, D, -1.0, math.nan, None, None, None, None)),
+                             L.TPFA_FP64, None, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_residual(*args(L.Rock(D, D, D, 1.0, 1.0, None, D, D, D)), L.TPFA_FP64,
+                             DUMMY, None, None) == L.TPFA_ERR_PARAM
+    m = (L.Model * 1)()
+    m[0] = L.Model(g, f, L.Rock(D, D, D, 1.0, 1.0, None, None, None, None), st, DUMMY.value,
+                   DUMMY.value, L.Launch(-1, 0, 0))
     out = C.c_void_p()
     assert lib.tpfa_batch_create(m, 1, L.TPFA_FP64, L.TPFA_BATCH_JACOBIAN, C.byref(out),
                                  None) == L.TPFA_ERR_UNSUPPORTED

@@ -122,6 +122,39 @@ def test_fp32_precision_form(gpu, orc, shape):
             assert np.array_equal(r, ref[0]) and np.array_equal(J, ref[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_output_store_kinds_bitwise(gpu, orc, prec):
+    """64-cell rows start on 128-byte lines: with 128-byte-aligned outputs the
+    FP32 kernels store non-temporal, with outputs one element off a line they
+    use ordinary stores (FP64 stores non-temporal in both). Either way the
+    same values land in every cell, for the Jacobian and the VJP."""
+    geo = small((64, 6, 9))
+    shape = geo.grid.shape
+    n = int(np.prod(shape))
+    if prec == "fp64":
+        p, kx, pref, dt = orc.pressure(geo), geo.kx, None, torch.float64
+    else:
+        pref, dp, kx, _, _ = fp32_inputs(orc, geo)
+        p, dt, pref = dp, torch.float32, dev(pref)
+    args = (geo.grid, geo.fluid, dev(kx), dev(p))
+    kw = dict(seal=dev(geo.seal), pref=pref, ry=geo.ry, rz=geo.rz)
+    print(f"store kinds {prec}", flush=True)
+
+    def off(planes):  # a contiguous view one element past a fresh allocation
+        return torch.empty(planes * n + 1, dtype=dt, device="cuda")[1:].view(
+            ((planes,) if planes > 1 else ()) + shape)
+
+    r0, J0 = gpu.jacobian(*args, **kw)
+    r1, J1 = gpu.jacobian(*args, r_out=off(1), J_out=off(7), **kw)
+    assert r1.data_ptr() % 128 != 0
+    assert torch.equal(r0, r1) and torch.equal(J0, J1)
+    w = dev(np.random.default_rng(3).standard_normal(shape).astype(
+        np.float64 if prec == "fp64" else np.float32))
+    g0 = gpu.residual_vjp(*args, w, **kw)
+    g1 = gpu.residual_vjp(*args, w, gp_out=off(1), gm_out=off(1), **kw)
+    assert torch.equal(g0[0], g1[0]) and torch.equal(g0[1], g1[1])
+
+
 def test_hydrostatic_and_offsets(gpu, orc):
     for gk, top, nz in ((9.81, 1e7, 256), (-9.81, 2e7, 40), (0.0, 1e7, 5)):
         g = geomodel.Grid(3, 2, nz, gk=gk)
