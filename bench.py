@@ -17,12 +17,15 @@ The same run also times, as extra fields of the JSON line:
   adjoint  - FP32 forward residual + vector-Jacobian product on 256 x 256 x 128
   newton   - the backward-Euler residual of Eq. (2) and the matrix-free J v (the
              operator of a Newton-Krylov step) on 512 x 512 x 256, FP64 and FP32
+  aniso    - residual + Jacobian with per-direction permeability arrays (kx, ky,
+             kz) on 512 x 512 x 256, FP64 and FP32
   paper10  - the paper's own workload (Sec. 7): 1000 applications of the FP32
              10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
   cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
 The roofline object is for the dominant kernel, the FP64 Jacobian kernel.
 
-    python bench.py [--steps K] [--warmup W] [--sections fp64,fp32,res,batched,adjoint,cpu]
+    python bench.py [--steps K] [--warmup W] [--sections fp64,fp32,res,newton,aniso,batched,
+                                                           adjoint,paper10,cpu]
 """
 import argparse
 import hashlib
@@ -49,9 +52,13 @@ BYTES_FP64_RBE = 8 + 8 + 1 + 8 + 8 + 8      # p, kx, seal, phi, p_prev -> r = 41
 BYTES_FP64_JVP = BYTES_FP64_RBE + 8 + 8     # + v -> J v = 57
 BYTES_FP32_JVP = 4 + 4 + 1 + 4 + 4 + 4 + 4 + 4  # = 29
 BYTES_SPMV_FP64 = 7 * 8 + 8 + 8             # stored J, v -> J v = 72
+BYTES_FP64_RJ_K3 = BYTES_FP64_RJ + 8 + 8    # + ky, kz arrays = 97
+BYTES_FP32_RJ_K3 = BYTES_FP32_RJ + 4 + 4    # + ky, kz arrays = 49
 # the paper's wall times for 1000 applications on 750 x 994 x 246 (Sec. 7, Table 1)
 PAPER10_CONTEXT = {"cs2_s": 0.0823, "a100_raja_s": 16.8378, "a100_cuda_s": 14.6573}
-KERNEL_SRC = os.path.join(ROOT, "paper_2304_11274_amd", "csrc", "tpfa_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2304_11274_amd", "csrc", f)
+               for f in ("tpfa_tile.h", "tpfa_kernels.hip", "tpfa_march_f64.hip",
+                         "tpfa_march_f32.hip", "tpfa_march_f32_plain.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tpfa_jacobian_fp64_512x512x256_traffic.txt")
 
 
@@ -60,8 +67,11 @@ def log(*a):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -106,7 +116,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="fp64,fp32,res,newton,batched,adjoint,paper10,cpu")
+    ap.add_argument("--sections",
+                    default="fp64,fp32,res,newton,aniso,batched,adjoint,paper10,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -281,6 +292,41 @@ def main():
         out["newton"] = res
         log(f"newton: {res}")
         del phi64, step, v64, dp32, pn32, acc32, k32, v32, jv32
+        torch.cuda.empty_cache()
+
+    # --------------- per-direction permeability arrays (kx, ky, kz), r + J
+    if "aniso" in sections:
+        _, ky_h, kz_h = geomodel.k3_fields(geo.kx, 31)
+        ky64, kz64 = up(ky_h), up(kz_h)
+        del ky_h, kz_h
+        p64 = (pref[:, None, None] + noise[0]).contiguous()
+        r = torch.empty(g.shape, dtype=torch.float64, device=dev)
+        J = torch.empty((7,) + g.shape, dtype=torch.float64, device=dev)
+        res = {"ky_kz": "ky = kx exp(0.3 N(0,1)), kz = 0.1 kx exp(0.5 N(0,1)), seed 31"}
+        kw_ = dict(seal=seal, ky=ky64, kz=kz64, r_out=r, J_out=J)
+        for _ in range(W):
+            tp.jacobian(g, fl, kx64, p64, **kw_)
+        with Timer(torch) as tm:
+            for _ in range(KA):
+                tp.jacobian(g, fl, kx64, p64, **kw_)
+        res["fp64_rj"] = rate(tm.ms, KA, BYTES_FP64_RJ_K3)
+        del r, J, p64
+        torch.cuda.empty_cache()
+        k3_32 = (kx64.float(), ky64.float(), kz64.float())
+        del ky64, kz64
+        dp32 = noise[0].float()
+        r = torch.empty(g.shape, dtype=torch.float32, device=dev)
+        J = torch.empty((7,) + g.shape, dtype=torch.float32, device=dev)
+        kw_ = dict(seal=seal, pref=pref, ky=k3_32[1], kz=k3_32[2], r_out=r, J_out=J)
+        for _ in range(W):
+            tp.jacobian(g, fl, k3_32[0], dp32, **kw_)
+        with Timer(torch) as tm:
+            for _ in range(KA):
+                tp.jacobian(g, fl, k3_32[0], dp32, **kw_)
+        res["fp32_rj"] = rate(tm.ms, KA, BYTES_FP32_RJ_K3)
+        out["aniso"] = res
+        log(f"aniso: {res}")
+        del r, J, k3_32, dp32
         torch.cuda.empty_cache()
 
     # streaming-copy ceiling of this machine (torch copy kernel, context only)

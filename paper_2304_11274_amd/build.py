@@ -27,7 +27,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-command-line-argument"]
 
-SOURCES = ["tpfa_kernels.hip", "tpfa_api.cpp"]
+# the single-grid kernels are split by precision and store kind so that the
+# translation units compile in parallel
+SOURCES = ["tpfa_march_f64.hip", "tpfa_march_f32.hip", "tpfa_march_f32_plain.hip",
+           "tpfa_kernels.hip", "tpfa_api.cpp"]
 
 
 def _compile(src: str) -> str:

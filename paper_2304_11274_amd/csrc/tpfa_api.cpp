@@ -101,14 +101,18 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
 // 750x994x246): the Jacobian and the FP32 residual run best with 64x8 tiles,
 // the vector-Jacobian / Jacobian-vector products (more registers) and the FP64
 // residual (shared faces, more LDS) with 64x4, the 10-flux stencil with 128x4
-// on grids at least 128 cells wide; narrow grids take narrower tiles.
-int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec) {
+// on grids at least 128 cells wide; narrow grids take narrower tiles. The
+// FP64 Jacobian of the per-direction form (`form` = MODE_K3) needs more than
+// 128 VGPRs, which leaves one 512-thread workgroup per CU: 64x4 measured 20%
+// faster there.
+int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
   const int b = tpfa::base_mode(mode);
   if (mode == tpfa::MODE_RES10) return g.nx >= 128 ? 4 : 0;
   if (b == tpfa::MODE_VJP || b == tpfa::MODE_JVP) return 0;
   if (b == tpfa::MODE_RESIDUAL && prec == TPFA_FP64) return 0;
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && form == tpfa::MODE_K3) return 0;
   return 3;
 }
 
@@ -184,22 +188,28 @@ namespace {
 // The XCD band order is part of the library's default launch where it measured
 // faster on MI355X (FP32 Jacobian and residual, FP32 10-flux stencil with
 // permeability input); a caller that picks the tile also picks the flags.
-int default_flags(tpfa::Mode mode, tpfa_precision_t prec, bool trans) {
-  if (prec != TPFA_FP32 || trans) return 0;
+int default_flags(tpfa::Mode mode, tpfa_precision_t prec, int form) {
+  if (prec != TPFA_FP32 || form == tpfa::MODE_TRANS) return 0;
   const int b = tpfa::base_mode(mode);
   return b == tpfa::MODE_JACOBIAN || b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10
              ? TPFA_LAUNCH_XCD_REMAP
              : 0;
 }
 
-int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, bool trans,
+// `form`: 0 (permeability with ratios), MODE_TRANS or MODE_K3.
+int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form,
                    const tpfa_launch_t *launch, int &tile, int &kz, int &flags) {
   const bool dflt = !launch || launch->tile < 0;
-  tile = dflt ? default_tile(g, mode, prec) : launch->tile;
+  tile = dflt ? default_tile(g, mode, prec, form) : launch->tile;
   kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode);
   flags = launch ? launch->flags : 0;
-  if (dflt) flags |= default_flags(mode, prec, trans);
+  if (dflt) flags |= default_flags(mode, prec, form);
   return TPFA_OK;
+}
+
+// The rock form's mode flag: MODE_TRANS, MODE_K3 or 0.
+int rock_form(const tpfa_rock_t &rk) {
+  return rk.tx ? tpfa::MODE_TRANS : rk.ky ? tpfa::MODE_K3 : 0;
 }
 
 // Output store kind: the FP32 kernels write with ordinary stores unless every
@@ -216,7 +226,8 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
   int tile, kz, flags;
-  resolve_launch(*g, mode, prec, rk->tx != nullptr, launch, tile, kz, flags);
+  const int form = rock_form(*rk);
+  resolve_launch(*g, mode, prec, form, launch, tile, kz, flags);
   // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
   tpfa::Args b;
   tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
@@ -238,7 +249,6 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
   // the transmissibility and per-direction forms run the same modes with a flag
-  const int form = rk->tx ? tpfa::MODE_TRANS : rk->ky ? tpfa::MODE_K3 : 0;
   const tpfa::Mode m = static_cast<tpfa::Mode>(mode | form);
   const hipError_t e = tpfa::launch_march(prec, m, tile, b, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -534,7 +544,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       int tile, kz, flags;
       resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                           : tpfa::MODE_RESIDUAL,
-                     prec, false, &md.launch, tile, kz, flags);
+                     prec, 0, &md.launch, tile, kz, flags);
       if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +

@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI layer (tpfa_api.cpp) and the HIP
-// kernels (tpfa_kernels.hip). Not installed.
+// kernels (tpfa_tile.h, tpfa_kernels.hip, tpfa_march_*.hip). Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -1,0 +1,16 @@
+// FP64 single-grid march kernels: every mode kind x rock form (ratios,
+// given transmissibilities, per-direction permeability) x tile shape.
+#include "tpfa_tile.h"
+
+namespace tpfa {
+
+hipError_t launch_march_f64(int kind, int form, int tile, const Args &a, hipStream_t st) {
+  switch (form) {
+    case 0: return launch_kind<double, 0>(kind, tile, a, st);
+    case MODE_TRANS: return launch_kind<double, MODE_TRANS | 0>(kind, tile, a, st);
+    case MODE_K3: return launch_kind<double, MODE_K3 | 0>(kind, tile, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tpfa
