@@ -245,9 +245,10 @@ typedef struct tpfa_batch tpfa_batch_t; /* opaque */
 
 /* Builds the work list (one item per tile and z-chunk of every model, models
    in the given order, each in z-chunk, tile-row, tile order) and the model
-   table on the device (the batch owns
-   these two device buffers and a work counter), and captures one persistent
-   kernel launch into a HIP graph. `stream` orders the uploads. */
+   table on the device (the batch owns these two device buffers and a block
+   of work counters), and captures one persistent kernel launch into a HIP
+   graph.
+   `stream` orders the uploads. */
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
                       tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream);
 
@@ -257,12 +258,13 @@ int tpfa_batch_run(tpfa_batch_t *batch, void *stream);
 /* The same persistent kernel launched directly, without the graph. */
 int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream);
 
-/* How the one launch of a batch covers its work list:
+/* How the one launch of a batch covers its work list, cut into 8
+   contiguous bands, one per XCD (so that neighbouring tiles share an L2):
    TPFA_SCHEDULE_PERSISTENT (default): one workgroup per CU slot, taking work
-   items from a device counter until the list is drained;
+   items from its XCD's band (a device counter per band), then from the other
+   bands once that one is drained, until the list is drained;
    TPFA_SCHEDULE_GROUPED: one workgroup per work item, dispatched by the
-   hardware, the list cut into 8 contiguous bands, one per XCD.
-   Re-captures the batch's graph; results are identical. */
+   hardware. Re-captures the batch's graph; results are identical. */
 #define TPFA_SCHEDULE_PERSISTENT 0
 #define TPFA_SCHEDULE_GROUPED 1
 int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule);

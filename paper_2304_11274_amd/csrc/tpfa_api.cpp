@@ -580,7 +580,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     hipError_t e;
     if ((e = hipMalloc(&b->d_models, sizeof(tpfa::Args) * args.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_items, sizeof(tpfa::WorkItem) * wl.size())) != hipSuccess ||
-        (e = hipMalloc(&b->d_counter, 2 * sizeof(unsigned int))) != hipSuccess) {
+        (e = hipMalloc(&b->d_counter, tpfa::kCounterWords * sizeof(unsigned int))) != hipSuccess) {
       batch_free(b);
       return hip_fail(e, "batch allocation");
     }
@@ -588,7 +588,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
                             hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(b->d_items, wl.data(), sizeof(tpfa::WorkItem) * wl.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemsetAsync(b->d_counter, 0, 2 * sizeof(unsigned int), st)) != hipSuccess ||
+        (e = hipMemsetAsync(b->d_counter, 0, tpfa::kCounterWords * sizeof(unsigned int), st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
       batch_free(b);
       return hip_fail(e, "batch upload");

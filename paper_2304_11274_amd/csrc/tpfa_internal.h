@@ -118,7 +118,15 @@ hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, doubl
 hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
                          hipStream_t stream);
 
-// Batched ensemble kernels (persistent and grouped schedules).
+// Batched ensemble kernels (persistent and grouped schedules). The work list
+// is cut into one band per XCD; the persistent schedule keeps one claim
+// counter per band plus a count of finished workgroups, each counter on its
+// own 128-byte line (kCounterStride words apart) so that the bands' atomics
+// do not contend for one line.
+constexpr int kXcds = 8;
+constexpr int kBatchCounters = kXcds + 1;
+constexpr int kCounterStride = 32;
+constexpr int kCounterWords = kBatchCounters * kCounterStride;
 struct WorkItem {
   int32_t model;
   int32_t bx, by, kb;

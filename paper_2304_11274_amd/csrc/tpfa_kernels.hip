@@ -7,13 +7,42 @@
 namespace tpfa {
 
 // ----------------------------------------------------------------------------
-// Persistent ensemble kernel: 256-thread workgroups take work items (one tile
-// and z chunk of one model) from a device counter until the list is drained.
-// The last workgroup to finish resets the counters, so the next launch (or
-// graph replay) on the stream starts from zero without a memset node.
+// Ensemble kernels. The work list (one item per tile and z chunk of a model,
+// neighbouring tiles next to each other) is cut into kXcds contiguous bands,
+// one per XCD: workgroup ids go to the XCDs in turn, so workgroup b runs on
+// XCD b % kXcds, and a band's tiles share halo cells and the output lines at
+// their common edges in that XCD's L2.
+// Persistent schedule: 256-thread workgroups take items from their own band's
+// device counter, then from the other bands once it is drained. The last
+// workgroup to finish resets the counters, so the next launch (or graph
+// replay) on the stream starts from zero without a memset node.
 // ----------------------------------------------------------------------------
 constexpr int kPersistThreads = 256;
 constexpr int kMixedTiles = 3;  // TILE value of the kernel that switches shape per model
+
+// Band x of a list of n items: [start, start + len).
+__device__ __forceinline__ void band_range(uint32_t n, uint32_t x, uint32_t &start,
+                                           uint32_t &len) {
+  const uint32_t q = n / kXcds, rem = n % kXcds;
+  start = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
+  len = q + (x < rem ? 1u : 0u);
+}
+
+// Next item of a persistent workgroup (thread 0 only): from band `band`
+// while it lasts, then from the following bands in turn; `left` counts the
+// bands not yet found drained. Returns n once every band is drained.
+__device__ __forceinline__ uint32_t claim_item(unsigned int *counter, uint32_t n,
+                                               uint32_t &band, int &left) {
+  while (left > 0) {
+    uint32_t start, len;
+    band_range(n, band, start, len);
+    const uint32_t i = atomicAdd(&counter[band * kCounterStride], 1u);
+    if (i < len) return start + i;
+    band = (band + 1) % kXcds;
+    --left;
+  }
+  return n;
+}
 
 template <class S, int MODE, int TILE>
 constexpr int persist_lds_bytes() {
@@ -29,18 +58,18 @@ constexpr int persist_lds_bytes() {
 // 256-thread tile (one code path, fewer registers); TILE = kMixedTiles: the
 // tile is read per model.
 template <class S, int MODE, int TILE>
-__device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, char *smem) {
+__device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, char *smem, int tid) {
   if constexpr (TILE == 0) {
-    march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem);
+    march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem, tid);
   } else if constexpr (TILE == 1) {
-    march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem);
+    march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem, tid);
   } else if constexpr (TILE == 2) {
-    march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem);
+    march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem, tid);
   } else {
     switch (m.tile) {
-      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem); break;
-      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem); break;
-      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem); break;
+      case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem, tid); break;
+      case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem, tid); break;
+      default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem, tid); break;
     }
   }
 }
@@ -50,46 +79,66 @@ __device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, cha
 // choice (both tile bodies in one kernel) cost more registers than it saved
 // on the few aligned models.
 template <class S, int MODE, int TILE>
-__device__ __forceinline__ void run_item(const Args &m, const WorkItem &w, char *smem) {
+__device__ __forceinline__ void run_item(const Args &m, const WorkItem &w, char *smem, int tid) {
   if constexpr (sizeof(S) == 4)
-    march_item<S, MODE | MODE_PLAIN, TILE>(m, w, smem);
+    march_item<S, MODE | MODE_PLAIN, TILE>(m, w, smem, tid);
   else
-    march_item<S, MODE, TILE>(m, w, smem);
+    march_item<S, MODE, TILE>(m, w, smem, tid);
 }
 
-// The persistent kernel; TILE as for march_item.
+// The persistent kernel; TILE as for march_item. Thread 0 claims the next
+// item before the current one is processed; the claim state (band, bands
+// left) and the claimed index live in LDS, so no register is held across the
+// tile body (those would cost the tile registers, hence occupancy).
 template <class S, int MODE, int TILE>
 __global__ void __launch_bounds__(kPersistThreads)
     persistent_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items,
                       int64_t n_items, unsigned int *counter) {
   __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
-  __shared__ unsigned int s_item;
-  if (threadIdx.x == 0) s_item = atomicAdd(&counter[0], 1u);
+  __shared__ unsigned int s_next[2];  // claimed items, alternating per iteration
+  __shared__ unsigned int s_band;
+  __shared__ int s_left;
+  const uint32_t n = (uint32_t)n_items;
+  if (threadIdx.x == 0) {
+    uint32_t band = blockIdx.x % kXcds;  // the band of this workgroup's XCD
+    int left = kXcds;
+    s_next[0] = claim_item(counter, n, band, left);
+    s_band = band;
+    s_left = left;
+  }
   __syncthreads();
   // the item index is uniform: keep it (and everything read through it) in
   // scalar registers
-  unsigned int it = __builtin_amdgcn_readfirstlane(s_item);
-  for (;;) {
-    if ((int64_t)it >= n_items) break;
-    // claim the next item now; its index is only needed after this one
-    unsigned int nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(&counter[0], 1u);
+  unsigned int it = __builtin_amdgcn_readfirstlane(s_next[0]);
+  for (int q = 1;; q ^= 1) {
+    if (it >= n) break;
+    // claim the next item now; its index is only needed after this one. The
+    // slot written here was last read before the previous barrier.
+    if (threadIdx.x == 0) {
+      uint32_t band = s_band;
+      int left = s_left;
+      s_next[q] = claim_item(counter, n, band, left);
+      s_band = band;
+      s_left = left;
+    }
     const WorkItem w = items[it];
     const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
-    run_item<S, MODE, TILE>(m, w, smem);
-    __syncthreads();  // LDS (and s_item) are reused by the next item
-    if (threadIdx.x == 0) s_item = nxt;
-    __syncthreads();
-    it = __builtin_amdgcn_readfirstlane(s_item);
+    // the thread index passes an empty asm per item: otherwise the compiler
+    // hoists the tile's index arithmetic out of the item loop and keeps it
+    // live across it (six more VGPRs in FP32, one wave per SIMD fewer)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    run_item<S, MODE, TILE>(m, w, smem, tid);
+    __syncthreads();  // the tile's LDS is reused by the next item; s_next[q] is visible
+    it = __builtin_amdgcn_readfirstlane(s_next[q]);
   }
-  // workgroup done: the last one out resets both counters for the next launch
+  // workgroup done (its last claim found every band drained): the last one
+  // out resets every counter for the next launch
   if (threadIdx.x == 0) {
     __threadfence();
-    const unsigned int done = atomicAdd(&counter[1], 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&counter[0], 0u);
-      atomicExch(&counter[1], 0u);
-    }
+    const unsigned int done = atomicAdd(&counter[kXcds * kCounterStride], 1u);
+    if (done == gridDim.x - 1)
+      for (int c = 0; c < kBatchCounters; ++c) atomicExch(&counter[c * kCounterStride], 0u);
   }
 }
 
@@ -144,19 +193,18 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
 }
 
 // One workgroup per work item, dispatched by the hardware: the alternative
-// schedule of an ensemble launch (no counter, no item loop). The work list is
-// cut into 8 contiguous bands, one per XCD (workgroup ids go to the XCDs in
-// turn), so neighbouring tiles of a model run on one XCD and meet in its L2.
+// schedule of an ensemble launch (no counter, no item loop), with the same
+// bands: the workgroups of band x are the ids b with b % kXcds = x.
 template <class S, int MODE, int TILE>
 __global__ void __launch_bounds__(kPersistThreads)
     grouped_kernel(const Args *__restrict__ models, const WorkItem *__restrict__ items) {
   __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
-  const uint32_t n = gridDim.x, q = n / 8, rem = n % 8;
-  const uint32_t x = blockIdx.x % 8, l = blockIdx.x / 8;
-  const uint32_t it = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + l;
-  const WorkItem w = items[it];
+  // workgroup b is item l = b / kXcds of band b % kXcds (l < that band's length)
+  uint32_t start, len;
+  band_range(gridDim.x, blockIdx.x % kXcds, start, len);
+  const WorkItem w = items[start + blockIdx.x / kXcds];
   const Args m = models[__builtin_amdgcn_readfirstlane(w.model)];
-  run_item<S, MODE, TILE>(m, w, smem);
+  run_item<S, MODE, TILE>(m, w, smem, threadIdx.x);
 }
 
 template <class S, int MODE>

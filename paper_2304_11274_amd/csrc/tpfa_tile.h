@@ -495,7 +495,8 @@ struct Tile {
   uint32_t hb[HC], hs[HC];
   S A2x, A2y;
 
-  __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem) : a(a_) {
+  __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem, int tid_)
+      : a(a_) {
     s_p = reinterpret_cast<S *>(smem);
     s_k = s_p + 2 * HW;
     s_l = s_k + 2 * HW;
@@ -513,7 +514,7 @@ struct Tile {
     kb = kb_;
     ke = min(kb + a.kz_chunk, nz);
     plane = (size_t)a.plane;
-    const int tid = threadIdx.x;
+    const int tid = tid_;
     const int tx = tid % TX, ty = tid / TX;
     const int i = bx * TX + tx, j = by * TY + ty;
     own = i < nx && j < ny;
@@ -892,9 +893,13 @@ struct Tile {
 };
 
 
+// One tile: columns of block (bx, by), planes from kb. `tid`: the thread's
+// index in the workgroup (threadIdx.x, passed in so that a caller looping over
+// tiles can keep it from being hoisted).
 template <class S, int MODE, int TX, int TY>
-__device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem) {
-  const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem);
+__device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem,
+                                           int tid = threadIdx.x) {
+  const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem, tid);
   // own column at planes k, k+1, k+2, halo cell at k, k+1 (and k+2 with HALO2),
   // z faces (k-1,k), (k,k+1)
   using T = Tile<S, MODE, TX, TY>;
