@@ -188,9 +188,12 @@ def _row_errs(r_gpu, J_gpu, r, J, s):
     return e
 
 
-def compare_rows(orc, grid, fluid, kx, p, cells, r_rows, J_rows, *, tol, tau, ry, rz, seal):
-    """Comparison of sampled cells (r_rows[n], J_rows[7, n] from the GPU)."""
-    r, J, s, d = orc.rows(grid, fluid, kx, p, cells, ry=ry, rz=rz, seal=seal, with_dphi=True)
+def compare_rows(orc, grid, fluid, kx, p, cells, r_rows, J_rows, *, tol, tau, ry, rz, seal,
+                 ky=None, kz=None):
+    """Comparison of sampled cells (r_rows[n], J_rows[7, n] from the GPU); ky,
+    kz: per-direction permeability arrays."""
+    r, J, s, d = orc.rows(grid, fluid, kx, p, cells, ry=ry, rz=rz, seal=seal, ky=ky, kz=kz,
+                          with_dphi=True)
     err = _row_errs(r_rows, J_rows, r, J, s)
     with np.errstate(invalid="ignore"):
         tie = np.abs(d) <= tau  # [6, n]
@@ -210,8 +213,8 @@ def compare_rows(orc, grid, fluid, kx, p, cells, r_rows, J_rows, *, tol, tau, ry
                 lower = cells[q] if plus else cells[q] - strides[axis]
                 dlow = d[n, q] if plus else -d[n, q]  # potential seen from the lower cell
                 force[axis, lower] = -1 if dlow >= 0 else 1
-        r2, J2, s2 = orc.rows(grid, fluid, kx, p, cells[bad], ry=ry, rz=rz, seal=seal,
-                              force=force.reshape((3,) + shape))
+        r2, J2, s2 = orc.rows(grid, fluid, kx, p, cells[bad], ry=ry, rz=rz, seal=seal, ky=ky,
+                              kz=kz, force=force.reshape((3,) + shape))
         e2 = _row_errs(None if r_rows is None else r_rows[bad],
                        None if J_rows is None else J_rows[:, bad], r2, J2, s2)
         assert np.all(e2 <= tol), f"{int((e2 > tol).sum())} tie cells match neither choice"

@@ -5,6 +5,8 @@ benchmark times (library defaults; autotuned tiles for the ensemble):
   same geomodel: sampled cells (random, plus every domain face, edge and
   corner class) against the oracle evaluated cell by cell, and an invariant
   over the whole grid (the columns of J sum to zero);
+* the same grid with per-direction permeability arrays (the benchmark's
+  k_y, k_z recipe), FP64 and FP32, sampled cells against the oracle;
 * 256 x 256 x 128 FP32 residual and vector-Jacobian product against the full
   oracle evaluation;
 * the 64-model uneven ensemble in one persistent launch: every model bitwise
@@ -99,6 +101,36 @@ def test_fullsize_fp32_jacobian(gpu, orc, big):
                        tol=TOL32, tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
     print("fp32 full size:", rep)
     assert rep["max_err"] <= TOL32
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fullsize_per_direction_jacobian(gpu, orc, big, prec):
+    geo, pref = big
+    print(f"512x512x256 {prec} jacobian, per-direction k", flush=True)
+    k3 = geomodel.k3_fields(geo.kx, 31)
+    if prec == "fp64":
+        p, ks, kw, tol = pref[:, None, None] + geo.noise[0], k3, {}, TOL64
+        tau = 1e-9 * np.abs(p).max()
+        p_dev = dev(p)
+    else:
+        dp = geo.dp32(0)
+        ks = tuple(k.astype(np.float32) for k in k3)
+        p, kw, tol, tau = orc.widen_fp32(dp, pref), dict(pref=dev(pref)), TOL32, TAU32
+        p_dev = dev(dp)
+    r, J = gpu.jacobian(geo.grid, geo.fluid, dev(ks[0]), p_dev, seal=dev(geo.seal),
+                        ky=dev(ks[1]), kz=dev(ks[2]), **kw)
+    torch.cuda.synchronize()
+    colsum_check(J.double(), 1e-14 if prec == "fp64" else 1e-6)
+    cells = sample_cells(geo.grid, 20000, 13 if prec == "fp64" else 14)
+    idx = torch.from_numpy(cells).cuda()
+    r_s = r.view(-1)[idx].double().cpu().numpy()
+    J_s = J.view(7, -1)[:, idx].double().cpu().numpy()
+    del r, J
+    kw3 = tuple(k.astype(np.float64) for k in ks)
+    rep = compare_rows(orc, geo.grid, geo.fluid, kw3[0], p, cells, r_s, J_s, tol=tol, tau=tau,
+                       ry=1.0, rz=1.0, seal=geo.seal, ky=kw3[1], kz=kw3[2])
+    print(f"{prec} per-direction full size:", rep)
+    assert rep["max_err"] <= tol
 
 
 def test_fullsize_adjoint(gpu, orc):
