@@ -163,7 +163,7 @@ def main():
                                  "4 rotating pressure fields",
                      "cells": N, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
                      "sigma_lnk": 1.5, "ry": 1.0, "rz": 0.1, "seal_fraction": 0.01,
-                     "launch": "library default (64x8 tiles, 16 z-planes per workgroup)"}
+                     "launch": "library default (64x8 tiles, 32 z-planes per workgroup)"}
 
     def rate(ms, k, bytes_per_cell):
         t = ms / 1e3 / k

@@ -113,11 +113,22 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
   if (b == tpfa::MODE_VJP || b == tpfa::MODE_JVP) return 0;
   if (b == tpfa::MODE_RESIDUAL && prec == TPFA_FP64) return 0;
   if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && form == tpfa::MODE_K3) return 0;
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && (g.nx * 8) % 128 != 0) {
+    // rows off 128-byte lines: 128-wide tiles halve the partial lines at tile
+    // edges (10-15% faster on 500- and 750-wide grids) where they waste no
+    // more lanes than 64-wide ones
+    const int64_t w64 = (g.nx + 63) / 64 * 64, w128 = (g.nx + 127) / 128 * 128;
+    if (w128 <= w64) return 4;
+  }
   return 3;
 }
 
-int default_kz(tpfa::Mode mode) {
-  return tpfa::base_mode(mode) == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10 ? 32 : 16;
+// z planes per workgroup: 32 for the residual-only modes and the FP64
+// Jacobian (0.7% faster than 16 there), 16 for the other products.
+int default_kz(tpfa::Mode mode, tpfa_precision_t prec) {
+  const int b = tpfa::base_mode(mode);
+  if (b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10) return 32;
+  return b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 ? 32 : 16;
 }
 
 int hip_fail(hipError_t e, const char *what) {
@@ -201,7 +212,7 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
                    const tpfa_launch_t *launch, int &tile, int &kz, int &flags) {
   const bool dflt = !launch || launch->tile < 0;
   tile = dflt ? default_tile(g, mode, prec, form) : launch->tile;
-  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode);
+  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode, prec);
   flags = launch ? launch->flags : 0;
   if (dflt) flags |= default_flags(mode, prec, form);
   return TPFA_OK;
