@@ -104,7 +104,8 @@ typedef struct {
 
 /* Optional launch shape (pass NULL for the defaults): tile = id from
    tpfa_tile_shape(), or -1 for the library's default launch; kz_chunk = z
-   planes marched by one workgroup (0 = default); flags bit 0 selects the
+   planes marched by one workgroup (0 = default, which a single-grid call
+   shortens on small grids until the launch fills the GPU); flags bit 0 selects the
    XCD-aware workgroup order (the tiles of each z chunk are split into 8
    contiguous bands of tile rows, one per XCD). With tile = -1 (or NULL) the
    library also sets that bit where it measured faster; with an explicit tile

@@ -207,12 +207,35 @@ int default_flags(tpfa::Mode mode, tpfa_precision_t prec, int form) {
              : 0;
 }
 
-// `form`: 0 (permeability with ratios), MODE_TRANS or MODE_K3.
+// Waves of one full residency of MI355X at 8 waves per SIMD (256 CUs x 4
+// SIMDs x 8).
+constexpr int64_t kFillWaves = 256 * 4 * 8;
+
+// Small grids: the default z chunk is halved (down to 4 planes) until a
+// single-grid launch has at least kFillWaves waves, so that the chip is
+// filled (256x256x128 FP32 residual: 0.054 -> 0.039 ms; 128x128x64: the
+// residual, VJP and Jacobian 1.6-2.4x faster). Every chunk size computes the
+// same values.
+int fill_kz(const tpfa_grid_t &g, int tile, int kz) {
+  const tpfa::TileShape ts = tpfa::kTiles[tile];
+  const int64_t tiles = ((g.nx + ts.tx - 1) / ts.tx) * ((g.ny + ts.ty - 1) / ts.ty);
+  const int64_t waves = ts.threads / 64;
+  while (kz > 4 && tiles * ((g.nz + kz - 1) / kz) * waves < kFillWaves) kz /= 2;
+  return kz;
+}
+
+// `form`: 0 (permeability with ratios), MODE_TRANS or MODE_K3. `fill`: adapt
+// the default z chunk to small grids (single-grid launches; an ensemble fills
+// the chip with its models).
 int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form,
-                   const tpfa_launch_t *launch, int &tile, int &kz, int &flags) {
+                   const tpfa_launch_t *launch, int &tile, int &kz, int &flags,
+                   bool fill = true) {
   const bool dflt = !launch || launch->tile < 0;
   tile = dflt ? default_tile(g, mode, prec, form) : launch->tile;
-  kz = (launch && launch->kz_chunk > 0) ? launch->kz_chunk : default_kz(mode, prec);
+  if (launch && launch->kz_chunk > 0)
+    kz = launch->kz_chunk;
+  else
+    kz = fill ? fill_kz(g, tile, default_kz(mode, prec)) : default_kz(mode, prec);
   flags = launch ? launch->flags : 0;
   if (dflt) flags |= default_flags(mode, prec, form);
   return TPFA_OK;
@@ -555,7 +578,7 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       int tile, kz, flags;
       resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                           : tpfa::MODE_RESIDUAL,
-                     prec, 0, &md.launch, tile, kz, flags);
+                     prec, 0, &md.launch, tile, kz, flags, false);
       if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
