@@ -534,6 +534,14 @@ def main():
                                "host_cores_available": len(os.sched_getaffinity(0))}
         log(f"cpu baseline: {out['cpu_baseline']}")
 
+    rf = out.get("roofline")
+    if rf is not None:
+        # the same kernel against this box's own streaming-copy rate, and the
+        # counter-measured HBM bytes per launch as a rate
+        if out.get("copy_ceiling_GBps"):
+            rf["frac_of_copy_ceiling"] = rf["achieved"] / out["copy_ceiling_GBps"]
+        if rf.get("traffic") and out.get("ms_per_step"):
+            rf["traffic_GBps"] = rf["traffic"] / (out["ms_per_step"] / 1e3) / 1e9
     print(json.dumps(out), flush=True)
 
 
