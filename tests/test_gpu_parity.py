@@ -291,6 +291,41 @@ def test_autograd_fp32_matches_oracle_vjp(gpu, orc):
 # Batched ensemble
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("shapes", [[(2, 2, 2)], [(3, 1, 2), (1, 1, 1), (5, 4, 3)],
+                                    [(70, 9, 37)] * 9],
+                         ids=["one-item", "three-items", "nine-models"])
+def test_ensemble_few_items(gpu, orc, shapes):
+    """Fewer work items than XCD bands (so bands without items, and fewer
+    persistent workgroups than bands), one item per model, and a batch whose
+    bands all hold several items: both schedules, repeated graph replays (the
+    claim counters are reset by the last workgroup of each launch), bitwise
+    equal to single launches."""
+    members, singles = [], []
+    for m, shape in enumerate(shapes):
+        geo = small(shape, seed=40 + m)
+        p = orc.pressure(geo)
+        d = dict(grid=geo.grid, fluid=geo.fluid, kx=dev(geo.kx), p=dev(p), seal=dev(geo.seal),
+                 ry=geo.ry, rz=geo.rz, tile=0, kz_chunk=64)
+        members.append(d)
+        singles.append(gpu.jacobian(d["grid"], d["fluid"], d["kx"], d["p"], seal=d["seal"],
+                                    ry=d["ry"], rz=d["rz"], tile=0, kz_chunk=64))
+    print(f"ensemble of {len(shapes)} models", flush=True)
+    ens = gpu.Ensemble(members)
+    n_items, n_wg = ens.info()
+    assert 1 <= n_wg <= max(n_items, 1)
+    for schedule in ("persistent", "grouped", "persistent"):
+        ens.set_schedule(schedule)
+        for replay in range(4):
+            for q in range(len(members)):
+                ens.r[q].fill_(float("nan"))
+                ens.J[q].fill_(float("nan"))
+            ens.run(graph=(replay != 2))
+            torch.cuda.synchronize()
+            for q, (r, J) in enumerate(singles):
+                assert torch.equal(ens.r[q], r) and torch.equal(ens.J[q], J), (schedule, replay, q)
+    ens.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_ensemble_matches_single_launches_and_oracle(gpu, orc, prec):
     models = geomodel.ensemble(n_models=12, scale=0.2)
