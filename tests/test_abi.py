@@ -186,6 +186,11 @@ def test_python_binding_rejects_host_tensors():
         tp.residual(g, geomodel.Fluid(), t, t)
     with pytest.raises(TypeError):
         tp.residual(g, geomodel.Fluid(), t, t.to(torch.int32))
+    # per-direction arrays go together (checked before any tensor is used)
+    with pytest.raises(ValueError, match="ky and kz"):
+        tp.jacobian(g, geomodel.Fluid(), t, t, ky=t)
+    with pytest.raises(ValueError, match="ky and kz"):
+        tp.residual_vjp(g, geomodel.Fluid(), t, t, t, kz=t)
 
 
 def test_residual10_validation(lib):
