@@ -109,11 +109,18 @@ typedef struct {
    XCD-aware workgroup order (the tiles of each z chunk are split into 8
    contiguous bands of tile rows, one per XCD). With tile = -1 (or NULL) the
    library also sets that bit where it measured faster; with an explicit tile
-   the flags are taken as given. Results never depend on the launch shape. */
+   the flags are taken as given. Results never depend on the launch shape.
+   Row range (y slab): with y_end > 0, only the cells of rows
+   y_begin <= j < y_end (0 <= y_begin < y_end <= ny) are computed and their
+   outputs written; the grid's other rows are read as neighbours (a halo) and
+   their outputs are left untouched. This is one GPU's launch in a y-slab
+   decomposition, on its slab plus one halo row per side. y_begin = y_end = 0:
+   every row. */
 typedef struct {
   int tile;
   int kz_chunk;
   int flags;
+  int64_t y_begin, y_end;
 } tpfa_launch_t;
 
 #define TPFA_LAUNCH_XCD_REMAP 1

@@ -55,7 +55,8 @@ class Accum(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("tile", C.c_int), ("kz_chunk", C.c_int), ("flags", C.c_int)]
+    _fields_ = [("tile", C.c_int), ("kz_chunk", C.c_int), ("flags", C.c_int),
+                ("y_begin", C.c_int64), ("y_end", C.c_int64)]
 
 
 class Model(C.Structure):

@@ -29,11 +29,14 @@ def _fluid(f) -> L.Fluid:
     return L.Fluid(float(f.rho0), float(f.cf), float(f.p0), float(f.mu))
 
 
-def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap: bool):
-    if tile is None and kz_chunk is None and not xcd_remap:
+def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap: bool, rows=None):
+    """``rows`` = (y_begin, y_end): compute and write only those rows (a y slab;
+    the grid's other rows are read as its halo)."""
+    if tile is None and kz_chunk is None and not xcd_remap and rows is None:
         return None
+    y0, y1 = (0, 0) if rows is None else (int(rows[0]), int(rows[1]))
     return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
-                    L.TPFA_LAUNCH_XCD_REMAP if xcd_remap else 0)
+                    L.TPFA_LAUNCH_XCD_REMAP if xcd_remap else 0, y0, y1)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -106,8 +109,9 @@ def _rock(kx, seal, ry, rz, trans=None, ky=None, kz=None) -> L.Rock:
                   _ptr(ty), _ptr(tz))
 
 
-def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
-             trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
+             out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
+             rows=None) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = out if out is not None else torch.empty(p.shape, dtype=dt, device=dev)
@@ -116,17 +120,18 @@ def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
     L.check(lib.tpfa_residual(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
-                              _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+                              _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
     return r
 
 
-def _launch_ref(tile, kz_chunk, xcd_remap):
-    ln = _launch(tile, kz_chunk, xcd_remap)
+def _launch_ref(tile, kz_chunk, xcd_remap, rows=None):
+    ln = _launch(tile, kz_chunk, xcd_remap, rows)
     return None if ln is None else C.byref(ln)
 
 
-def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, want_r=True,
-             r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
+def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
+             want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
+             xcd_remap=False, rows=None):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -140,13 +145,13 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
     L.check(lib.tpfa_jacobian(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
-                              _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+                              _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
     return r, J
 
 
 def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
                  want_p=True, want_logk=True, gp_out=None, gm_out=None, trans=None, tile=None,
-                 kz_chunk=None, xcd_remap=False):
+                 kz_chunk=None, xcd_remap=False, rows=None):
     """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None. With
     ``trans`` = (tx, ty, tz) the second output is grad_logt [3, nz, ny, nx]:
     d(w.r)/d ln T of each cell's +x, +y, +z face. With per-direction arrays
@@ -165,9 +170,9 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     lib = L.load()
     fn = lib.tpfa_residual_vjp_trans if trans is not None else lib.tpfa_residual_vjp
     L.check(fn(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)), C.byref(L.State(_ptr(p), _ptr(pref))),
-               prec, _ptr(w), _ptr(gp), _ptr(gm), _launch_ref(tile, kz_chunk, xcd_remap),
-               _stream(dev)), lib)
+               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
+               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w), _ptr(gp), _ptr(gm),
+               _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
     return gp, gm
 
 
@@ -181,8 +186,9 @@ def _accum(accum, dt_, n, dev):
     return L.Accum(_ptr(phi), _ptr(p_prev), float(accum["dt"]), float(accum.get("cr", 0.0)))
 
 
-def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
-                trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
+                kz=None, out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
+                rows=None) -> torch.Tensor:
     """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
     the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -195,14 +201,14 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     L.check(lib.tpfa_residual_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
-                                 _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)),
-            lib)
+                                 _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
+                                 _stream(dev)), lib)
     return r
 
 
-def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
-                want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
-                xcd_remap=False):
+def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
+                kz=None, want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
+                xcd_remap=False, rows=None):
     """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     acc = _accum(accum, dt, n, dev)
@@ -218,13 +224,14 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
     L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
-                                 _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap),
+                                 _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap, rows),
                                  _stream(dev)), lib)
     return r, J
 
 
-def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
-        want_r=False, out=None, r_out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False):
+def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
+        kz=None, want_r=False, out=None, r_out=None, trans=None, tile=None, kz_chunk=None,
+        xcd_remap=False, rows=None):
     """Matrix-free J v of the flux residual, or of the backward-Euler residual
     when ``accum`` is given; returns (jv, r or None)."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -238,14 +245,16 @@ def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1
         _need(r, "r_out", dt, n, dev)
     lib = L.load()
     L.check(lib.tpfa_jvp(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
-                         C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)), C.byref(L.State(_ptr(p), _ptr(pref))),
+                         C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
+                         C.byref(L.State(_ptr(p), _ptr(pref))),
                          None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
-                         _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap), _stream(dev)), lib)
+                         _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
     return jv, r
 
 
-def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None, out=None,
-               trans=None, tile=None, kz_chunk=None, xcd_remap=False) -> torch.Tensor:
+def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
+               kz=None, out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
+               rows=None) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
     faces with caller-supplied transmissibilities tne, tse)."""
     n, prec, dt, dev = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -257,7 +266,7 @@ def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz
     L.check(lib.tpfa_residual10(C.byref(_grid(grid)), C.byref(_fluid(fluid)),
                                 C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                 C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
-                                _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap),
+                                _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
                                 _stream(dev)), lib)
     return r
 
@@ -328,7 +337,8 @@ class Ensemble:
             arr[m] = L.Model(_grid(g), _fluid(d["fluid"]),
                              _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                              L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
-                             L.Launch(int(d.get("tile", -1)), int(d.get("kz_chunk", 0)), 0))
+                             _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"))
+                             or L.Launch(-1, 0, 0, 0, 0))
         self.prec = prec
         self._handle = C.c_void_p()
         self._lib = L.load()
@@ -339,7 +349,8 @@ class Ensemble:
 
     def set_schedule(self, schedule: str):
         """'persistent' (work counter) or 'grouped' (one workgroup per item)."""
-        code = {"persistent": L.TPFA_SCHEDULE_PERSISTENT, "grouped": L.TPFA_SCHEDULE_GROUPED}[schedule]
+        code = {"persistent": L.TPFA_SCHEDULE_PERSISTENT,
+                "grouped": L.TPFA_SCHEDULE_GROUPED}[schedule]
         L.check(self._lib.tpfa_batch_set_schedule(self._handle, code), self._lib)
         self.schedule = schedule
 

@@ -93,6 +93,9 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
     if (launch->tile < -1 || launch->tile >= tpfa::kNumTiles)
       return fail(TPFA_ERR_TILE, "unknown tile id");
     if (launch->kz_chunk < 0) return fail(TPFA_ERR_TILE, "kz_chunk must be >= 0");
+    if ((launch->y_begin != 0 || launch->y_end != 0) &&
+        !(launch->y_begin >= 0 && launch->y_begin < launch->y_end && launch->y_end <= g->ny))
+      return fail(TPFA_ERR_PARAM, "row range must satisfy 0 <= y_begin < y_end <= ny");
   }
   return TPFA_OK;
 }
@@ -140,15 +143,18 @@ int hip_fail(hipError_t e, const char *what) {
 namespace tpfa {
 
 void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
-               const tpfa_state_t &st, int tile, int kz_chunk, int flags) {
+               const tpfa_state_t &st, int tile, int kz_chunk, int flags, int64_t y0,
+               int64_t y1) {
   std::memset(&a, 0, sizeof(a));
   const TileShape ts = kTiles[tile];
   a.nx = (int32_t)g.nx;
   a.ny = (int32_t)g.ny;
   a.nz = (int32_t)g.nz;
+  a.y0 = (int32_t)y0;
+  a.y1 = (int32_t)y1;
   a.kz_chunk = (int32_t)std::min<int64_t>(kz_chunk, g.nz);
   a.ntx = (int32_t)((g.nx + ts.tx - 1) / ts.tx);
-  a.nty = (int32_t)((g.ny + ts.ty - 1) / ts.ty);
+  a.nty = (int32_t)((y1 - y0 + ts.ty - 1) / ts.ty);
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
   a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : 0;
   a.tile = tile;
@@ -216,9 +222,9 @@ constexpr int64_t kFillWaves = 256 * 4 * 8;
 // filled (256x256x128 FP32 residual: 0.054 -> 0.039 ms; 128x128x64: the
 // residual, VJP and Jacobian 1.6-2.4x faster). Every chunk size computes the
 // same values.
-int fill_kz(const tpfa_grid_t &g, int tile, int kz) {
+int fill_kz(const tpfa_grid_t &g, int64_t rows, int tile, int kz) {
   const tpfa::TileShape ts = tpfa::kTiles[tile];
-  const int64_t tiles = ((g.nx + ts.tx - 1) / ts.tx) * ((g.ny + ts.ty - 1) / ts.ty);
+  const int64_t tiles = ((g.nx + ts.tx - 1) / ts.tx) * ((rows + ts.ty - 1) / ts.ty);
   const int64_t waves = ts.threads / 64;
   while (kz > 4 && tiles * ((g.nz + kz - 1) / kz) * waves < kFillWaves) kz /= 2;
   return kz;
@@ -226,16 +232,19 @@ int fill_kz(const tpfa_grid_t &g, int tile, int kz) {
 
 // `form`: 0 (permeability with ratios), MODE_TRANS or MODE_K3. `fill`: adapt
 // the default z chunk to small grids (single-grid launches; an ensemble fills
-// the chip with its models).
+// the chip with its models). [y0, y1): the rows computed.
 int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form,
-                   const tpfa_launch_t *launch, int &tile, int &kz, int &flags,
-                   bool fill = true) {
+                   const tpfa_launch_t *launch, int &tile, int &kz, int &flags, int64_t &y0,
+                   int64_t &y1, bool fill = true) {
   const bool dflt = !launch || launch->tile < 0;
   tile = dflt ? default_tile(g, mode, prec, form) : launch->tile;
+  const bool rows = launch && launch->y_end > 0;
+  y0 = rows ? launch->y_begin : 0;
+  y1 = rows ? launch->y_end : g.ny;
   if (launch && launch->kz_chunk > 0)
     kz = launch->kz_chunk;
   else
-    kz = fill ? fill_kz(g, tile, default_kz(mode, prec)) : default_kz(mode, prec);
+    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec)) : default_kz(mode, prec);
   flags = launch ? launch->flags : 0;
   if (dflt) flags |= default_flags(mode, prec, form);
   return TPFA_OK;
@@ -260,11 +269,12 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
         const tpfa_state_t *st, tpfa_precision_t prec, const tpfa_launch_t *launch,
         tpfa::Args &a, void *stream) {
   int tile, kz, flags;
+  int64_t y0, y1;
   const int form = rock_form(*rk);
-  resolve_launch(*g, mode, prec, form, launch, tile, kz, flags);
+  resolve_launch(*g, mode, prec, form, launch, tile, kz, flags, y0, y1);
   // a.r, a.J, a.w, a.gp, a.gm were set by the caller; keep them
   tpfa::Args b;
-  tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags);
+  tpfa::make_args(b, *g, *f, *rk, *st, tile, kz, flags, y0, y1);
   b.r = a.r;
   b.J = a.J;
   b.w = a.w;
@@ -576,14 +586,15 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
       if (mode == TPFA_BATCH_RESIDUAL && !md.r)
         return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": r is NULL");
       int tile, kz, flags;
+      int64_t y0, y1;
       resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                           : tpfa::MODE_RESIDUAL,
-                     prec, 0, &md.launch, tile, kz, flags, false);
+                     prec, 0, &md.launch, tile, kz, flags, y0, y1, false);
       if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
       if (tpfa::kTiles[tile].threads != 256)
         return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
                                        ": batched tiles must be 256-thread tiles");
-      tpfa::make_args(args[m], md.grid, md.fluid, md.rock, md.state, tile, kz, flags);
+      tpfa::make_args(args[m], md.grid, md.fluid, md.rock, md.state, tile, kz, flags, y0, y1);
       args[m].r = md.r;
       args[m].J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
       // natural order: a tile's x neighbours follow it, so they run together

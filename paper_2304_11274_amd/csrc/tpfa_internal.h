@@ -66,6 +66,7 @@ struct Args {
   int32_t remap;      // 1: XCD-aware workgroup order
   int32_t tile;       // index into kTiles
   int32_t plain;      // 1: ordinary output stores (FP32 rows off 128-byte lines)
+  int32_t y0, y1;     // rows computed and written: [y0, y1) (others are read only)
   int64_t plane;      // nx * ny
   int64_t nblocks;    // ntx * nty * nzc
   // transmissibility geometric factors a_d and directional ratios (y, z)
@@ -108,7 +109,8 @@ struct Args {
 
 // Fills the derived fields of `a` from the ABI structs (host only).
 void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
-               const tpfa_state_t &st, int tile, int kz_chunk, int flags);
+               const tpfa_state_t &st, int tile, int kz_chunk, int flags, int64_t y0,
+               int64_t y1);
 
 // Launchers (host). Return hipSuccess or the launch error.
 hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &a,

@@ -483,7 +483,8 @@ struct Tile {
   uint8_t *s_s;
   size_t plane;
   int nz, kb, ke;
-  bool own;
+  bool inside;         // the thread's cell lies in the grid (staged as a real cell)
+  bool own;            // ... and in the launch's row range (its outputs are written)
   bool tnv, tsv;       // 10-flux: the own cell's +x+y / +x-y diagonal face exists
   bool txv, tyv;       // transmissibility input: the own cell's +x / +y face exists
   int ol;
@@ -516,13 +517,17 @@ struct Tile {
     plane = (size_t)a.plane;
     const int tid = tid_;
     const int tx = tid % TX, ty = tid / TX;
-    const int i = bx * TX + tx, j = by * TY + ty;
-    own = i < nx && j < ny;
-    tnv = own && i + 1 < nx && j + 1 < ny;
-    txv = own && i + 1 < nx;
-    tyv = own && j + 1 < ny;
-    tsv = own && i + 1 < nx && j >= 1;
-    const uint32_t col = own ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
+    // tile rows start at the launch's first row y0; rows of the grid outside
+    // [y0, y1) are read as neighbours (a halo) but not written
+    const int jb = a.y0 + by * TY;
+    const int i = bx * TX + tx, j = jb + ty;
+    inside = i < nx && j < ny;
+    own = inside && j < a.y1;
+    tnv = inside && i + 1 < nx && j + 1 < ny;
+    txv = inside && i + 1 < nx;
+    tyv = inside && j + 1 < ny;
+    tsv = inside && i + 1 < nx && j >= 1;
+    const uint32_t col = inside ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
     ol = (ty + 1) * W + tx + 1;
     cb = col * (uint32_t)sizeof(S);
     cs = col;
@@ -535,32 +540,32 @@ struct Tile {
       uint32_t need = 0;  // fields those faces (and the tile's faces towards it) read
       if (h < TX) {  // bottom row: +y (and +x+y) faces
         hi = bx * TX + h;
-        hj = by * TY - 1;
+        hj = jb - 1;
         l = h + 1;
         role = kPY | (R10 ? kNE : 0u);
         need = (K3 ? kNeedKy : kNeedK) | kNeedSeal | kNeedTy | kNeedTn | kNeedW;
       } else if (h < 2 * TX) {  // top row: +x-y faces
         hi = bx * TX + h - TX;
-        hj = by * TY + TY;
+        hj = jb + TY;
         l = (TY + 1) * W + h - TX + 1;
         role = R10 ? kSE : 0u;
         need = (K3 ? kNeedKy : kNeedK) | kNeedTs | kNeedW;
       } else if (h < 2 * TX + TY) {  // left column: +x (and both diagonal) faces
         hi = bx * TX - 1;
-        hj = by * TY + h - 2 * TX;
+        hj = jb + h - 2 * TX;
         l = (h - 2 * TX + 1) * W;
         role = kPX | (R10 ? kNE | kSE : 0u);
         need = kNeedK | kNeedSeal | kNeedTx | kNeedTn | kNeedTs | kNeedW;
       } else if (h < 2 * TX + 2 * TY) {  // right column: none (the tile's lower cells)
         hi = bx * TX + TX;
-        hj = by * TY + h - 2 * TX - TY;
+        hj = jb + h - 2 * TX - TY;
         l = (h - 2 * TX - TY + 1) * W + TX + 1;
         need = kNeedK | kNeedW;
       } else if (h < NH) {  // corners (10-flux stencil)
         const int c = h - 2 * TX - 2 * TY;
         const int cx = c & 1, cy = c >> 1;
         hi = cx ? bx * TX + TX : bx * TX - 1;
-        hj = cy ? by * TY + TY : by * TY - 1;
+        hj = cy ? jb + TY : jb - 1;
         l = (cy ? TY + 1 : 0) * W + (cx ? TX + 1 : 0);
         role = c == 0 ? kNE : c == 2 ? kSE : 0u;
         need = c == 0 ? kNeedTn : c == 2 ? kNeedTs : 0u;
@@ -609,7 +614,7 @@ struct Tile {
   // A halo cell's tne / tse serve only faces towards tile cells, so the halo
   // cell's own presence decides; the own cell checks its (i+1, j+-1) partner.
   __device__ __forceinline__ void load(Cell<S> &c, int k) const {
-    load_at(c, k, own, cb, cs);
+    load_at(c, k, inside, cb, cs);
     if (TIN) {
       // a face with a cell outside the domain does not exist
       c.tx = txv ? c.tx : S(0);

@@ -94,6 +94,10 @@ def case(name, code, **mut):
     case("tile-unknown", L.TPFA_ERR_TILE, launch=(99, 0, 0)),
     case("tile-below", L.TPFA_ERR_TILE, launch=(-2, 0, 0)),
     case("kz-negative", L.TPFA_ERR_TILE, launch=(0, -1, 0)),
+    case("rows-begin-negative", L.TPFA_ERR_PARAM, launch=(-1, 0, 0, -1, 4)),
+    case("rows-past-ny", L.TPFA_ERR_PARAM, launch=(-1, 0, 0, 0, 9)),
+    case("rows-empty", L.TPFA_ERR_PARAM, launch=(-1, 0, 0, 4, 4)),
+    case("rows-end-missing", L.TPFA_ERR_PARAM, launch=(-1, 0, 0, 3, 0)),
 ])
 def test_residual_validation(lib, mut, code):
     g, f, rk, st = good()
