@@ -19,6 +19,9 @@ The same run also times, as extra fields of the JSON line:
              operator of a Newton-Krylov step) on 512 x 512 x 256, FP64 and FP32
   aniso    - residual + Jacobian with per-direction permeability arrays (kx, ky,
              kz) on 512 x 512 x 256, FP64 and FP32
+  slab     - one GPU's share of an 8-GPU y-slab decomposition of the same grid:
+             a 512 x 66 x 256 local grid (64 owned rows + one halo row per side),
+             FP64 residual + Jacobian of the owned rows (row-range launch)
   paper10  - the paper's own workload (Sec. 7): 1000 applications of the FP32
              10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
   cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
@@ -117,7 +120,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections",
-                    default="fp64,fp32,res,newton,aniso,batched,adjoint,paper10,cpu")
+                    default="fp64,fp32,res,newton,aniso,slab,batched,adjoint,paper10,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -327,6 +330,36 @@ def main():
         out["aniso"] = res
         log(f"aniso: {res}")
         del r, J, k3_32, dp32
+        torch.cuda.empty_cache()
+
+    # ------------- one GPU's share of an 8-GPU y-slab decomposition (FP64 r + J)
+    if "slab" in sections:
+        n_gpu, owned = 8, g.ny // 8
+        lo, hi = 3 * owned - 1, 4 * owned + 1  # an interior slab: one halo row per side
+        gl = geomodel.Grid(g.nx, hi - lo, g.nz, dx=g.dx, dy=g.dy, dz=g.dz, gk=g.gk)
+        pl = (pref[:, None, None] + noise[0][:, lo:hi, :]).contiguous()
+        kl = kx64[:, lo:hi, :].contiguous()
+        sl = seal[:, lo:hi, :].contiguous()
+        r = torch.empty(gl.shape, dtype=torch.float64, device=dev)
+        J = torch.empty((7,) + gl.shape, dtype=torch.float64, device=dev)
+        kw = dict(seal=sl, ry=geo.ry, rz=geo.rz, r_out=r, J_out=J, rows=(1, 1 + owned))
+        for _ in range(W):
+            tp.jacobian(gl, fl, kl, pl, **kw)
+        with Timer(torch) as tm:
+            for _ in range(KA):
+                tp.jacobian(gl, fl, kl, pl, **kw)
+        ms = tm.ms / KA
+        cells = g.nx * owned * g.nz
+        halo_bytes = g.nx * g.nz * (8 + 8 + 1)  # p, kx, seal of one halo row
+        out["slab"] = {"workload": f"{g.nx}x{hi - lo}x{g.nz} local grid, rows 1..{owned} owned "
+                                   f"(one GPU of {n_gpu}), FP64 residual + Jacobian",
+                       "owned_cells": cells, "ms_per_step": ms,
+                       "cells_per_s": cells / (ms / 1e3),
+                       "algorithmic_GBps": BYTES_FP64_RJ * cells / (ms / 1e3) / 1e9,
+                       "halo_bytes_per_side": halo_bytes,
+                       "halo_exchange_us_one_xgmi_link": halo_bytes / 153e9 * 1e6}
+        log(f"slab: {out['slab']}")
+        del r, J, pl, kl, sl
         torch.cuda.empty_cache()
 
     # streaming-copy ceiling of this machine (torch copy kernel, context only)
