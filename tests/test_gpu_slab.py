@@ -51,6 +51,8 @@ def run_all(gpu, geo, g, f, pref, be, rows=None, tile=None):
               pref=None if pref is None else dev(pref))
     acc = dict(phi=d["phi"], p_prev=d["p_prev"], dt=be["dt"], cr=be["cr"])
     out = {}
+    out["res"] = gpu.residual(g, geo.fluid, d["kx"], d["p"], **kw)  # shared faces in FP64
+    out["resbe"] = gpu.residual_be(g, geo.fluid, d["kx"], d["p"], acc, **kw)
     out["r"], out["J"] = gpu.jacobian(g, geo.fluid, d["kx"], d["p"], **kw)
     out["gp"], out["gm"] = gpu.residual_vjp(g, geo.fluid, d["kx"], d["p"], d["v"], **kw)
     out["r10"] = gpu.residual10(g, geo.fluid, d["kx"], d["p"], d["tne"], d["tse"], **kw)
