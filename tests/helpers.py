@@ -317,3 +317,19 @@ def compare_res10(orc, grid, fluid, kx, p, tne, tse, r_gpu, *, tol, tau, ry, rz,
         rep["n_tie_cells"] = int(bad.sum())
         rep["max_err"] = float(np.where(bad, 0.0, err).max())
     return rep
+
+
+def crop_mask(shape, lo, hi, full):
+    """Cells of a crop whose ten neighbours in the full grid are all inside the
+    crop (or outside the domain on both): crop faces on the domain boundary
+    are exact, the others lose their outer layer."""
+    m = np.ones(shape, bool)
+    for ax, (a, b, n) in enumerate(zip(lo, hi, full)):
+        sl = [slice(None)] * 3
+        if a > 0:
+            sl[2 - ax] = 0
+            m[tuple(sl)] = False
+        if b < n:
+            sl[2 - ax] = -1
+            m[tuple(sl)] = False
+    return m

@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import geomodel
-from helpers import apply_J, rel_err
+from helpers import apply_J, crop_mask, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,54 @@ def test_flux_jvp_without_accumulation(gpu, orc, prec):
     ref = orc.evaluate_be(geo.grid, geo.fluid, k_w, p_w, zero, p_w, 1.0, 0.0, ry=geo.ry,
                           rz=geo.rz, seal=geo.seal, v=v_w, want=("J", "jv"))
     check_jv(host(jv), ref["J"], v_w, ref["jv"], tol)
+
+
+CROPS = [(0, 0, 0), (488, 488, 232), (0, 488, 100), (488, 0, 0), (250, 250, 120),
+         (63, 255, 232), (301, 0, 7), (0, 400, 200)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fullsize_backward_euler(gpu, orc, prec):
+    """512 x 512 x 256, the benchmark's backward-Euler inputs and default
+    launches: the full residual (and in FP64 J v) on eight 24^3 crops against
+    the oracle, on the crop cells whose faces all lie inside the crop."""
+    geo = geomodel.big512(noise_seeds=(2,))
+    g = geo.grid
+    be = geomodel.be_fields(g, 9)
+    pref = orc.hydrostatic(g, geo.fluid)
+    print(f"512x512x256 backward Euler {prec}", flush=True)
+    if prec == "fp64":
+        p = pref[:, None, None] + geo.noise[0]
+        pn = p - be["dp_step"]
+        k, phi, v, tol = geo.kx, be["phi"], be["v"], TOL64
+        kw = dict(seal=dev(geo.seal), ry=geo.ry, rz=geo.rz)
+        p_in, pn_in = p, pn
+    else:
+        dp = geo.noise[0].astype(np.float32)
+        dpn = (geo.noise[0] - be["dp_step"]).astype(np.float32)
+        k, phi, v = (geo.kx32().astype(np.float64), be["phi"].astype(np.float32),
+                     be["v"].astype(np.float32))
+        p, pn = orc.widen_fp32(dp, pref), orc.widen_fp32(dpn, pref)
+        kw = dict(seal=dev(geo.seal), pref=dev(pref), ry=geo.ry, rz=geo.rz)
+        p_in, pn_in, tol = dp, dpn, TOL32
+    k_in = k if prec == "fp64" else k.astype(np.float32)
+    acc = dict(phi=dev(phi), p_prev=dev(pn_in), dt=be["dt"], cr=be["cr"])
+    jv, r = gpu.jvp(g, geo.fluid, dev(k_in), dev(p_in), dev(v), accum=acc, want_r=True, **kw)
+    torch.cuda.synchronize()
+    r, jv = r.cpu().numpy().astype(np.float64), jv.cpu().numpy().astype(np.float64)
+    c = 24
+    for (i0, j0, k0) in CROPS:
+        sl = (slice(k0, k0 + c), slice(j0, j0 + c), slice(i0, i0 + c))
+        sub = geomodel.Grid(c, c, c, g.dx, g.dy, g.dz, g.gk)
+        mask = crop_mask(sub.shape, (i0, j0, k0), (i0 + c, j0 + c, k0 + c), (g.nx, g.ny, g.nz))
+        ref = orc.evaluate_be(sub, geo.fluid, k[sl], p[sl], np.asarray(phi[sl], np.float64),
+                              pn[sl], be["dt"], be["cr"], ry=geo.ry, rz=geo.rz,
+                              seal=geo.seal[sl], v=np.asarray(v[sl], np.float64),
+                              want=("r", "J", "scale", "jv"))
+        e = np.where(mask, rel_err(r[sl], ref["r"], ref["scale"][0]), 0.0)
+        assert e.max() <= tol, ((i0, j0, k0), float(e.max()))
+        if prec == "fp64":
+            scale = apply_J(np.abs(ref["J"]), np.abs(np.asarray(v[sl], np.float64)))
+            ej = np.where(mask, np.abs(jv[sl] - ref["jv"]) / np.maximum(scale, 1e-300), 0.0)
+            assert ej.max() <= tol, ((i0, j0, k0), float(ej.max()))

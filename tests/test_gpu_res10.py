@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import geomodel
-from helpers import compare_res10
+from helpers import compare_res10, crop_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -113,22 +113,6 @@ def test_res10_conservation(gpu, orc):
     _, scale = orc.residual10(geo.grid, geo.fluid, geo.kx, p, tne, tse, ry=geo.ry, rz=geo.rz,
                               seal=geo.seal)
     assert abs(r.sum()) <= 16 * r.size * 1.2e-16 * scale.sum()
-
-
-def crop_mask(shape, lo, hi, full):
-    """Cells of a crop whose ten neighbours in the full grid are all inside the
-    crop (or outside the domain on both): crop faces on the domain boundary
-    are exact, the others lose their outer layer."""
-    m = np.ones(shape, bool)
-    for ax, (a, b, n) in enumerate(zip(lo, hi, full)):
-        sl = [slice(None)] * 3
-        if a > 0:
-            sl[2 - ax] = 0
-            m[tuple(sl)] = False
-        if b < n:
-            sl[2 - ax] = -1
-            m[tuple(sl)] = False
-    return m
 
 
 @pytest.mark.slow

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import geomodel
-from helpers import apply_J, rel_err
+from helpers import apply_J, crop_mask, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -158,3 +158,39 @@ def test_trans_vjp(gpu, orc, shape, prec):
             first = (gp, gt)
         else:
             assert np.array_equal(gp, first[0]) and np.array_equal(gt, first[1]), tile
+
+
+@pytest.mark.slow
+def test_fullsize_paper10_given_transmissibilities(gpu, orc):
+    """750 x 994 x 246, all ten transmissibilities given (the benchmark's
+    paper10 transmissibility line, default launch): eight 24^3 crops against
+    the oracle on the cells whose ten faces lie inside the crop, and
+    conservation over the whole grid."""
+    nx, ny, nz = geomodel.PAPER10_SHAPES[-1]
+    g = geomodel.Grid(nx, ny, nz)
+    tr = geomodel.paper10_trans(nx, ny, nz)
+    dp = geomodel.paper10(nx, ny, nz).noise[0]
+    fl = geomodel.Fluid()
+    pref = orc.hydrostatic(g, fl)
+    print(f"paper10 given transmissibilities {nx}x{ny}x{nz}", flush=True)
+    r = gpu.residual10(g, fl, None, dev(dp), dev(tr["tne"]), dev(tr["tse"]), pref=dev(pref),
+                       trans=(dev(tr["tx"]), dev(tr["ty"]), dev(tr["tz"])))
+    torch.cuda.synchronize()
+    r_sum = float(r.double().sum().item())
+    r_abs = float(r.double().abs().sum().item())
+    assert abs(r_sum) <= 1e-5 * r_abs
+    r = r.cpu().numpy()
+    c = 24
+    for (i0, j0, k0) in [(0, 0, 0), (nx - c, ny - c, nz - c), (0, ny - c, 100), (nx - c, 0, 0),
+                         (370, 500, 120), (63, 255, nz - c), (511, 0, 7), (0, 700, 200)]:
+        sl = (slice(k0, k0 + c), slice(j0, j0 + c), slice(i0, i0 + c))
+        sub = geomodel.Grid(c, c, c, g.dx, g.dy, g.dz, g.gk)
+        mask = crop_mask(sub.shape, (i0, j0, k0), (i0 + c, j0 + c, k0 + c), (nx, ny, nz))
+        w = {key: tr[key][sl].astype(np.float64) for key in tr}
+        # a crop's last layer along each axis has faces leaving the crop: the
+        # oracle closes them (the crop boundary), and the mask drops those cells
+        ref = orc.evaluate_general(sub, fl, orc.widen_fp32(dp[sl], pref[k0:k0 + c]),
+                                   trans=(w["tx"], w["ty"], w["tz"]), diag=(w["tne"], w["tse"]),
+                                   want=("r", "scale"))
+        e = np.where(mask, rel_err(r[sl], ref["r"], ref["scale"][0]), 0.0)
+        assert e.max() <= 1e-5, ((i0, j0, k0), float(e.max()))
