@@ -20,8 +20,13 @@
  * accumulation term of the backward-Euler residual, Eq. (2), is not included.
  *
  * Conventions for every entry point:
- *  - Arrays are contiguous structure-of-arrays with x fastest:
- *    idx = i + nx * (j + ny * k).
+ *  - Arrays are structure-of-arrays with x fastest:
+ *    idx = i + ldx * (j + ny * k), where ldx = grid.ldx (the row pitch) or nx
+ *    when grid.ldx is 0 (contiguous arrays). Every per-cell array of one call
+ *    (inputs and outputs, each plane of J and of the gradients) uses the same
+ *    pitch; an array of P planes holds plane q at offset q * ldx * ny * nz.
+ *    Cells with nx <= i < ldx are padding: never read as cells and never
+ *    written.
  *  - Array pointers are DEVICE pointers (hipMalloc'ed or torch CUDA tensors)
  *    owned by the caller, unless stated otherwise. Structs are read on the host
  *    during the call and may be freed when it returns.
@@ -49,7 +54,7 @@ extern "C" {
 
 #define TPFA_OK 0
 #define TPFA_ERR_NULL (-1)        /* a required pointer is NULL */
-#define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, nx*ny*nz overflows, or one x-y plane of an array holds 2^32 bytes or more */
+#define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, 0 < ldx < nx, ldx*ny*nz overflows, or one x-y plane of an array holds 2^32 bytes or more */
 #define TPFA_ERR_PARAM (-3)       /* mu <= 0, cell size <= 0, negative ratio, non-finite constant */
 #define TPFA_ERR_UNSUPPORTED (-4) /* unsupported combination (see each call) */
 #define TPFA_ERR_HIP (-5)         /* HIP runtime error, detail in tpfa_last_error() */
@@ -57,11 +62,17 @@ extern "C" {
 
 typedef enum { TPFA_FP64 = 0, TPFA_FP32 = 1 } tpfa_precision_t;
 
-/* Grid: cell counts, cell sizes (m), gravity component along +k (m/s^2). */
+/* Grid: cell counts, cell sizes (m), gravity component along +k (m/s^2),
+   and the row pitch of the arrays in cells (0 = nx; otherwise ldx >= nx, else
+   TPFA_ERR_SHAPE). Rows that start on 128-byte lines (ldx * element size a
+   multiple of 128 and 128-byte aligned base pointers) let each tile write
+   whole lines; on MI355X, outputs whose rows straddle lines at tile edges
+   cost up to a quarter more time. */
 typedef struct {
   int64_t nx, ny, nz;
   double dx, dy, dz;
   double gk;
+  int64_t ldx;
 } tpfa_grid_t;
 
 /* Fluid, Eq. (5) and constant viscosity (SI): rho0 (kg/m^3), cf (1/Pa),
@@ -227,7 +238,8 @@ int tpfa_residual10(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
 int tpfa_hydrostatic(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, double p_top,
                      double *pref, void *stream);
 
-/* Precision-form state from an FP64 pressure: dp[idx] = (float)(p[idx] - pref[k]). */
+/* Precision-form state from an FP64 pressure: dp[idx] = (float)(p[idx] - pref[k])
+   for every cell (padding is not touched). */
 int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double *pref,
                          float *dp, void *stream);
 

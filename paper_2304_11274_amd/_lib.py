@@ -31,7 +31,7 @@ TPFA_SCHEDULE_GROUPED = 1
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("gk", C.c_double)]
+                ("gk", C.c_double), ("ldx", C.c_int64)]
 
 
 class Fluid(C.Structure):

@@ -34,6 +34,9 @@ int ok() {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+// Row pitch of the arrays in cells: grid.ldx, or nx when it is 0.
+int64_t pitch(const tpfa_grid_t &g) { return g.ldx ? g.ldx : g.nx; }
+
 int check_grid(const tpfa_grid_t *g) {
   if (!g) return fail(TPFA_ERR_NULL, "grid is NULL");
   if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0)
@@ -41,9 +44,12 @@ int check_grid(const tpfa_grid_t *g) {
   const int64_t lim = std::numeric_limits<int32_t>::max();
   if (g->nx > lim || g->ny > lim || g->nz > lim)
     return fail(TPFA_ERR_SHAPE, "each grid dimension must fit in 32 bits");
-  if (g->nx > std::numeric_limits<int64_t>::max() / g->ny ||
-      g->nx * g->ny > std::numeric_limits<int64_t>::max() / 8 / 7 / g->nz)
-    return fail(TPFA_ERR_SHAPE, "nx*ny*nz overflows");
+  if (g->ldx != 0 && (g->ldx < g->nx || g->ldx > lim))
+    return fail(TPFA_ERR_SHAPE, "the row pitch ldx must be 0 or at least nx (and fit in 32 bits)");
+  const int64_t ld = pitch(*g);
+  if (ld > std::numeric_limits<int64_t>::max() / g->ny ||
+      ld * g->ny > std::numeric_limits<int64_t>::max() / 8 / 7 / g->nz)
+    return fail(TPFA_ERR_SHAPE, "ldx*ny*nz overflows");
   if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !is_finite(g->dx) || !is_finite(g->dy) ||
       !is_finite(g->dz))
     return fail(TPFA_ERR_PARAM, "cell sizes must be positive and finite");
@@ -70,7 +76,7 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
     return fail(TPFA_ERR_PARAM, "unknown precision");
   // the kernels address a cell within its x-y plane with a 32-bit byte offset
   const int64_t elem = prec == TPFA_FP64 ? 8 : 4;
-  if (g->nx * g->ny > (int64_t)(std::numeric_limits<uint32_t>::max() / elem))
+  if (pitch(*g) * g->ny > (int64_t)(std::numeric_limits<uint32_t>::max() / elem))
     return fail(TPFA_ERR_SHAPE, "an x-y plane of one array must hold fewer than 2^32 bytes");
   if (rk->tx || rk->ty || rk->tz) {
     if (!rk->tx || !rk->ty || !rk->tz)
@@ -116,7 +122,7 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
   if (b == tpfa::MODE_VJP || b == tpfa::MODE_JVP) return 0;
   if (b == tpfa::MODE_RESIDUAL && prec == TPFA_FP64) return 0;
   if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && form == tpfa::MODE_K3) return 0;
-  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && (g.nx * 8) % 128 != 0) {
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && (pitch(g) * 8) % 128 != 0) {
     // rows off 128-byte lines: 128-wide tiles halve the partial lines at tile
     // edges (10-15% faster on 500- and 750-wide grids) where they waste no
     // more lanes than 64-wide ones
@@ -158,7 +164,8 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
   a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : 0;
   a.tile = tile;
-  a.plane = g.nx * g.ny;
+  a.ldx = (int32_t)pitch(g);
+  a.plane = pitch(g) * g.ny;
   a.nblocks = (int64_t)a.ntx * a.nty * a.nzc;
   // face area over centre distance, per direction
   a.ax = g.dy * g.dz / g.dx;
@@ -256,10 +263,10 @@ int rock_form(const tpfa_rock_t &rk) {
 }
 
 // Output store kind: the FP32 kernels write with ordinary stores unless every
-// output row starts on a 128-byte line (row length and output base pointers);
+// output row starts on a 128-byte line (row pitch and output base pointers);
 // the FP64 kernels always write non-temporal (measured faster either way).
 void set_store_kind(tpfa::Args &a, tpfa_precision_t prec) {
-  bool lines = ((int64_t)a.nx * 4) % 128 == 0;
+  bool lines = ((int64_t)a.ldx * 4) % 128 == 0;
   for (const void *q : {a.r, a.J, a.gp, a.gm, a.jv})
     if (q && reinterpret_cast<uintptr_t>(q) % 128 != 0) lines = false;
   a.plain = prec == TPFA_FP32 && !lines ? 1 : 0;

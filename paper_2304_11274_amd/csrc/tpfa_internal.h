@@ -67,7 +67,9 @@ struct Args {
   int32_t tile;       // index into kTiles
   int32_t plain;      // 1: ordinary output stores (FP32 rows off 128-byte lines)
   int32_t y0, y1;     // rows computed and written: [y0, y1) (others are read only)
-  int64_t plane;      // nx * ny
+  int32_t ldx;        // row pitch of every array, in cells (>= nx)
+  int32_t pad0_;
+  int64_t plane;      // ldx * ny
   int64_t nblocks;    // ntx * nty * nzc
   // transmissibility geometric factors a_d and directional ratios (y, z)
   double ax, ay, az, ry, rz;

@@ -172,11 +172,16 @@ __global__ void hydrostatic_kernel(int nz, double G, double rho0, double cf, dou
   }
 }
 
-__global__ void offset_kernel(int64_t plane, int64_t n, const double *__restrict__ p,
-                              const double *__restrict__ pref, float *__restrict__ dp) {
+// One thread per cell c = i + nx * row (row = j + ny * k), stored at
+// i + ldx * row; padding cells are not touched.
+__global__ void offset_kernel(int64_t nx, int64_t ldx, int64_t ny, int64_t n,
+                              const double *__restrict__ p, const double *__restrict__ pref,
+                              float *__restrict__ dp) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride)
-    dp[idx] = (float)(p[idx] - pref[idx / plane]);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+    const int64_t row = c / nx, idx = c - row * nx + row * ldx;
+    dp[idx] = (float)(p[idx] - pref[row / ny]);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -279,7 +284,7 @@ hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pr
   const int64_t n = g.nx * g.ny * g.nz;
   const int64_t blocks = (n + 255) / 256;
   const unsigned int grid = (unsigned int)(blocks < 65536 ? blocks : 65536);
-  offset_kernel<<<grid, 256, 0, st>>>(g.nx * g.ny, n, p, pref, dp);
+  offset_kernel<<<grid, 256, 0, st>>>(g.nx, g.ldx ? g.ldx : g.nx, g.ny, n, p, pref, dp);
   return hipGetLastError();
 }
 

@@ -511,6 +511,7 @@ struct Tile {
     s_fne = s_fy + 2 * HW;
     s_fse = s_fne + (R10 ? 2 * HW : 0);
     const int nx = a.nx, ny = a.ny;
+    const uint32_t ldx = (uint32_t)a.ldx;  // row pitch of the arrays (>= nx)
     nz = a.nz;
     kb = kb_;
     ke = min(kb + a.kz_chunk, nz);
@@ -527,7 +528,7 @@ struct Tile {
     txv = inside && i + 1 < nx;
     tyv = inside && j + 1 < ny;
     tsv = inside && i + 1 < nx && j >= 1;
-    const uint32_t col = inside ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
+    const uint32_t col = inside ? (uint32_t)j * ldx + (uint32_t)i : 0u;
     ol = (ty + 1) * W + tx + 1;
     cb = col * (uint32_t)sizeof(S);
     cs = col;
@@ -574,7 +575,7 @@ struct Tile {
       hn[q] = need;
       hl[q] = l;
       hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
-      const uint32_t hcol = hv[q] ? (uint32_t)hj * (uint32_t)nx + (uint32_t)hi : 0u;
+      const uint32_t hcol = hv[q] ? (uint32_t)hj * ldx + (uint32_t)hi : 0u;
       hb[q] = hcol * (uint32_t)sizeof(S);
       hs[q] = hcol;
     }

@@ -76,6 +76,11 @@ def case(name, code, **mut):
     case("nz-negative", L.TPFA_ERR_SHAPE, nz=-3),
     case("nx-over-int32", L.TPFA_ERR_SHAPE, nx=2**31),
     case("ncell-overflow", L.TPFA_ERR_SHAPE, nx=2**31 - 1, ny=2**31 - 1, nz=2**31 - 1),
+    case("ldx-below-nx", L.TPFA_ERR_SHAPE, ldx=7),
+    case("ldx-negative", L.TPFA_ERR_SHAPE, ldx=-8),
+    case("ldx-over-int32", L.TPFA_ERR_SHAPE, ldx=2**31),
+    case("pitched-overflow", L.TPFA_ERR_SHAPE, ldx=2**31 - 1, ny=2**31 - 1, nz=2**31 - 1),
+    case("pitched-r-null", L.TPFA_ERR_NULL, ldx=40, r=None),
     case("dx-zero", L.TPFA_ERR_PARAM, dx=0.0),
     case("dz-nan", L.TPFA_ERR_PARAM, dz=math.nan),
     case("gk-inf", L.TPFA_ERR_PARAM, gk=math.inf),
@@ -111,7 +116,7 @@ def test_residual_validation(lib, mut, code):
             rk = v
         elif k == "state":
             st = v
-        elif k in ("nx", "ny", "nz", "dx", "dy", "dz", "gk"):
+        elif k in ("nx", "ny", "nz", "dx", "dy", "dz", "gk", "ldx"):
             setattr(g, k, v)
         elif k in ("mu", "cf", "rho0", "p0"):
             setattr(f, k, v)
@@ -284,6 +289,12 @@ def test_plane_size_limit(lib):
     assert lib.tpfa_residual(*args, L.TPFA_FP32, None, None, None) == L.TPFA_ERR_NULL
     g.ny = 2 ** 15  # 2^30 cells: 2^32 bytes in FP32
     assert lib.tpfa_residual(*args, L.TPFA_FP32, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+    # the limit applies to the padded plane: 8 x 2^14 cells with a row pitch of 2^15
+    g.nx, g.ny, g.ldx = 8, 2 ** 14, 2 ** 15
+    assert lib.tpfa_residual(*args, L.TPFA_FP64, DUMMY, None, None) == L.TPFA_ERR_SHAPE
+    assert lib.tpfa_residual(*args, L.TPFA_FP32, None, None, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_offset_pressure(C.byref(L.Grid(8, 8, 8, 1.0, 1.0, 1.0, 0.0, 4)), DUMMY,
+                                    DUMMY, DUMMY, None) == L.TPFA_ERR_SHAPE
 
 
 def test_vjp_trans_validation(lib):

@@ -1,0 +1,65 @@
+"""Host-side checks of the row-pitched layout in the Python binding: the row
+pitch of an array is read from its strides (a contiguous array has pitch nx;
+a view buf[..., :nx] of a (..., nz, ny, ldx) buffer has pitch ldx), every other
+layout is refused, and outputs are allocated in the layout of p. No GPU is
+used: these functions only read tensor metadata."""
+import pytest
+import torch
+
+import geomodel
+from paper_2304_11274_amd import api
+
+
+G = geomodel.Grid(5, 4, 3)
+
+
+def padded(lead=(), ldx=8, dtype=torch.float64):
+    return torch.zeros(tuple(lead) + (G.nz, G.ny, ldx), dtype=dtype)[..., :G.nx]
+
+
+def test_contiguous_arrays_have_pitch_nx():
+    assert api._pitch(torch.zeros(G.nz, G.ny, G.nx), "a", G) == G.nx
+    assert api._pitch(torch.zeros(G.nz * G.ny * G.nx), "a", G) == G.nx
+    assert api._pitch(torch.zeros(7, G.nz, G.ny, G.nx), "a", G) == G.nx
+
+
+@pytest.mark.parametrize("ldx", [6, 8, 32])
+def test_padded_views_give_their_pitch(ldx):
+    assert api._pitch(padded(ldx=ldx), "a", G) == ldx
+    assert api._pitch(padded((7,), ldx=ldx), "J", G) == ldx
+    assert api._pitch(padded((3,), ldx=ldx)[1], "t", G) == ldx
+    # a view that starts at a later column of a wider buffer has the same pitch
+    wide = torch.zeros(G.nz, G.ny, ldx + 3)[..., 2:2 + G.nx]
+    assert api._pitch(wide, "a", G) == ldx + 3
+
+
+def test_degenerate_dimensions():
+    g = geomodel.Grid(5, 1, 3)
+    t = torch.zeros(3, 1, 8)[..., :5]
+    assert api._pitch(t, "a", g) == 8
+    g = geomodel.Grid(5, 4, 1)
+    t = torch.zeros(1, 4, 8)[..., :5]
+    assert api._pitch(t, "a", g) == 8
+
+
+@pytest.mark.parametrize("make", [
+    lambda: torch.zeros(G.nz, 6, G.nx)[:, 1:5, :],          # a y slice: planes too far apart
+    lambda: torch.zeros(G.nz, G.nx, G.ny).transpose(1, 2),  # x not fastest
+    lambda: torch.zeros(G.nz, G.ny, 2 * G.nx)[..., ::2],    # x strided
+    lambda: torch.zeros(7, G.nz, G.ny, 8)[:, :, :, :G.nx][::2],  # planes skipped
+])
+def test_other_layouts_are_refused(make):
+    with pytest.raises(ValueError):
+        api._pitch(make(), "a", G)
+
+
+def test_outputs_follow_the_layout_of_p():
+    p = padded(ldx=16)
+    r = api._empty(p, G, 16)
+    J = api._empty(p, G, 16, (7,))
+    assert tuple(r.shape) == (G.nz, G.ny, G.nx) and api._pitch(r, "r", G) == 16
+    assert tuple(J.shape) == (7, G.nz, G.ny, G.nx) and api._pitch(J, "J", G) == 16
+    q = torch.zeros(G.nz * G.ny * G.nx)
+    assert api._empty(q, G, G.nx).shape == q.shape
+    assert api._empty(q, G, G.nx, dtype=torch.float32).dtype == torch.float32
+
