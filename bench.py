@@ -22,13 +22,15 @@ The same run also times, as extra fields of the JSON line:
   slab     - one GPU's share of an 8-GPU y-slab decomposition of the same grid:
              a 512 x 66 x 256 local grid (64 owned rows + one halo row per side),
              FP64 residual + Jacobian of the owned rows (row-range launch)
+  pitched  - residual + Jacobian on 500 x 500 x 256, whose rows are off 128-byte
+             lines, with contiguous arrays vs arrays of row pitch 512 (FP64, FP32)
   paper10  - the paper's own workload (Sec. 7): 1000 applications of the FP32
              10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
   cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
 The roofline object is for the dominant kernel, the FP64 Jacobian kernel.
 
-    python bench.py [--steps K] [--warmup W] [--sections fp64,fp32,res,newton,aniso,batched,
-                                                           adjoint,paper10,cpu]
+    python bench.py [--steps K] [--warmup W] [--sections fp64,fp32,res,newton,aniso,slab,
+                                                           pitched,batched,adjoint,paper10,cpu]
 """
 import argparse
 import hashlib
@@ -120,7 +122,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections",
-                    default="fp64,fp32,res,newton,aniso,slab,batched,adjoint,paper10,cpu")
+                    default="fp64,fp32,res,newton,aniso,slab,pitched,batched,adjoint,paper10,"
+                            "cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -362,6 +365,55 @@ def main():
         del r, J, pl, kl, sl
         torch.cuda.empty_cache()
 
+    # -------- rows off 128-byte lines: contiguous vs row-pitched arrays (r + J)
+    if "pitched" in sections:
+        nxp, nyp, ldp = 500, 500, 512
+        gp_ = geomodel.Grid(nxp, nyp, g.nz, dx=g.dx, dy=g.dy, dz=g.dz, gk=g.gk)
+        cells = nxp * nyp * g.nz
+
+        def layout(a, ld):
+            """Crop of a 512 x 512 array to 500 x 500, contiguous or with row pitch ld."""
+            c = a[..., :nyp, :nxp]
+            if ld == nxp:
+                return c.contiguous()
+            buf = torch.zeros(tuple(c.shape[:-1]) + (ld,), dtype=c.dtype, device=dev)
+            buf[..., :nxp].copy_(c)
+            return buf[..., :nxp]
+
+        res = {"workload": f"{nxp}x{nyp}x{g.nz} (rows of 4000 / 2000 bytes, off 128-byte "
+                           f"lines), residual + Jacobian, contiguous vs row pitch {ldp}"}
+        for prec in ("fp64", "fp32"):
+            for ld in (nxp, ldp):
+                sp = layout(seal, ld)
+                if prec == "fp64":
+                    kp = layout(kx64, ld)
+                    pp = [layout(pref[:, None, None] + nz_[:, :nyp, :nxp], ld)
+                          for nz_ in noise[:2]]
+                    kw = dict(seal=sp, ry=geo.ry, rz=geo.rz)
+                    bpc = BYTES_FP64_RJ
+                else:
+                    kp = layout(kx64[:, :nyp, :nxp].float(), ld)
+                    pp = [layout(nz_[:, :nyp, :nxp].float(), ld) for nz_ in noise[:2]]
+                    kw = dict(seal=sp, pref=pref, ry=geo.ry, rz=geo.rz)
+                    bpc = BYTES_FP32_RJ
+                r_, J_ = tp.jacobian(gp_, fl, kp, pp[0], **kw)
+                kw.update(r_out=r_, J_out=J_)
+                for s_ in range(W):
+                    tp.jacobian(gp_, fl, kp, pp[s_ % 2], **kw)
+                with Timer(torch) as tm:
+                    for s_ in range(KA):
+                        tp.jacobian(gp_, fl, kp, pp[s_ % 2], **kw)
+                ms = tm.ms / KA
+                res.setdefault(prec, {})["pitch_%d" % ld] = {
+                    "ms_per_step": ms, "cells_per_s": cells / (ms / 1e3),
+                    "algorithmic_GBps": bpc * cells / (ms / 1e3) / 1e9}
+                del kp, sp, pp, r_, J_, kw
+                torch.cuda.empty_cache()
+            res[prec]["speedup_pitched"] = (res[prec]["pitch_%d" % nxp]["ms_per_step"]
+                                            / res[prec]["pitch_%d" % ldp]["ms_per_step"])
+        out["pitched"] = res
+        log(f"pitched: {res}")
+
     # streaming-copy ceiling of this box (torch copy kernel, context only)
     src = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -413,6 +465,7 @@ def main():
                                                        dtype=torch.float32, device=dev))
                 for m in members]
         ens_tiles = sorted({(m["tile"], m["kz_chunk"]) for m in members})
+        ens_tiles_of = [(m["tile"], m["kz_chunk"]) for m in members]
         for m, (t_, z_) in zip(members, solo):
             m["tile"], m["kz_chunk"] = t_, z_
 
@@ -439,9 +492,33 @@ def main():
         out["batched"]["hbm_frac"] = out["batched"]["algorithmic_GBps"] / HBM_PEAK_GBS
         if out["value"]:
             out["batched"]["cells_per_s_vs_fp64"] = out["batched"]["cells_per_s"] / out["value"]
+        ens.close()
+        del ens, outs
+        torch.cuda.empty_cache()
+        # the same models with every array's rows padded to 128-byte lines
+        # (32 floats): the same launch, whole-line stores at every tile edge
+        for m, (t_, z_) in zip(members, ens_tiles_of):
+            m["tile"], m["kz_chunk"] = t_, z_
+            nx_ = m["grid"].nx
+            ld = (nx_ + 31) // 32 * 32
+            for key in ("kx", "p", "seal"):
+                buf = torch.zeros(tuple(m[key].shape[:-1]) + (ld,), dtype=m[key].dtype,
+                                  device=dev)
+                buf[..., :nx_].copy_(m[key])
+                m[key] = buf[..., :nx_]
+        ens = tp.Ensemble(members)
+        ens.set_schedule(ens_best[2])
+        for _ in range(W):
+            ens.run()
+        with Timer(torch) as tm:
+            for _ in range(KA):
+                ens.run()
+        t_pad = tm.ms / KA
+        out["batched"]["padded_rows_ms"] = t_pad
+        out["batched"]["padded_rows_cells_per_s"] = cells / (t_pad / 1e3)
         log(f"batched: {out['batched']}")
         ens.close()
-        del ens, members, outs
+        del ens, members
         torch.cuda.empty_cache()
 
     # ---------------------------------------------------- adjoint fwd + VJP
