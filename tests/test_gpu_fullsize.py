@@ -7,6 +7,9 @@ benchmark times (library defaults; autotuned tiles for the ensemble):
   over the whole grid (the columns of J sum to zero);
 * the same grid with per-direction permeability arrays (the benchmark's
   k_y, k_z recipe), FP64 and FP32, sampled cells against the oracle;
+* its 500 x 500 x 256 crop (rows off 128-byte lines) in arrays of row pitch
+  512, FP64 and FP32: bitwise equal to the contiguous launch, sampled cells
+  against the oracle, the column-sum invariant;
 * 256 x 256 x 128 FP32 residual and vector-Jacobian product against the full
   oracle evaluation;
 * the 64-model uneven ensemble in one persistent launch: every model bitwise
@@ -130,6 +133,52 @@ def test_fullsize_per_direction_jacobian(gpu, orc, big, prec):
     rep = compare_rows(orc, geo.grid, geo.fluid, kw3[0], p, cells, r_s, J_s, tol=tol, tau=tau,
                        ry=1.0, rz=1.0, seal=geo.seal, ky=kw3[1], kz=kw3[2])
     print(f"{prec} per-direction full size:", rep)
+    assert rep["max_err"] <= tol
+
+
+def _pitched(a, ld):
+    """Device copy of a (..., nz, ny, nx) array as a view of a buffer with row pitch ld."""
+    t = dev(a)
+    buf = torch.zeros(tuple(t.shape[:-1]) + (ld,), dtype=t.dtype, device=t.device)
+    buf[..., :t.shape[-1]].copy_(t)
+    return buf[..., :t.shape[-1]]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fullsize_pitched_jacobian(gpu, orc, big, prec):
+    geo, pref = big
+    nxp, nyp, ld = 500, 500, 512
+    g = geomodel.Grid(nxp, nyp, geo.grid.nz, dx=geo.grid.dx, dy=geo.grid.dy, dz=geo.grid.dz,
+                      gk=geo.grid.gk)
+    print(f"500x500x256 {prec} jacobian, row pitch 512", flush=True)
+    crop = lambda a: np.ascontiguousarray(a[:, :nyp, :nxp])  # noqa: E731
+    seal = crop(geo.seal)
+    if prec == "fp64":
+        kx, p = crop(geo.kx), crop(pref[:, None, None] + geo.noise[0])
+        p_dev, kw, tol, tau, pw, kwide = p, {}, TOL64, 1e-9 * np.abs(p).max(), p, kx
+    else:
+        kx, dp = crop(geo.kx32()), crop(geo.dp32(0))
+        p_dev, kw, tol, tau = dp, dict(pref=dev(pref)), TOL32, TAU32
+        pw, kwide = orc.widen_fp32(dp, pref), kx.astype(np.float64)
+    r, J = gpu.jacobian(g, geo.fluid, _pitched(kx, ld), _pitched(p_dev, ld),
+                        seal=_pitched(seal, ld), ry=geo.ry, rz=geo.rz, **kw)
+    rc, Jc = gpu.jacobian(g, geo.fluid, dev(kx), dev(p_dev), seal=dev(seal), ry=geo.ry,
+                          rz=geo.rz, **kw)
+    torch.cuda.synchronize()
+    assert r.stride(-2) == ld and J.stride(-2) == ld
+    assert torch.equal(r, rc) and torch.equal(J, Jc)
+    del rc, Jc
+    colsum_check(J.double(), 1e-14 if prec == "fp64" else 1e-6)
+    cells = sample_cells(g, 20000, 15 if prec == "fp64" else 16)
+    kk, rem = np.divmod(cells, nxp * nyp)
+    jj, ii = np.divmod(rem, nxp)
+    ix = [torch.from_numpy(a).cuda() for a in (kk, jj, ii)]
+    r_s = r[ix[0], ix[1], ix[2]].double().cpu().numpy()
+    J_s = J[:, ix[0], ix[1], ix[2]].double().cpu().numpy()
+    del r, J
+    rep = compare_rows(orc, g, geo.fluid, kwide, pw, cells, r_s, J_s, tol=tol, tau=tau,
+                       ry=geo.ry, rz=geo.rz, seal=seal)
+    print(f"{prec} pitched full size:", rep)
     assert rep["max_err"] <= tol
 
 
