@@ -210,10 +210,18 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
 namespace {
 
 // The XCD band order is part of the library's default launch where it measured
-// faster on MI355X (FP32 Jacobian and residual, FP32 10-flux stencil with
-// permeability input); a caller that picks the tile also picks the flags.
-int default_flags(tpfa::Mode mode, tpfa_precision_t prec, int form) {
-  if (prec != TPFA_FP32 || form == tpfa::MODE_TRANS) return 0;
+// faster on MI355X: on launches of at most kSmallCells computed cells in every
+// mode of the permeability forms (256x256x128: the FP64 Jacobian 9%, the FP64
+// residual 14%, the FP32 VJP and J v 8% faster), and on larger ones for the
+// FP32 Jacobian and residual and the FP32 10-flux stencil with permeability
+// input (the FP64 Jacobians ran 2-7% slower with it on 384x384x192 and
+// 512x512x256). A caller that picks the tile also picks the flags.
+constexpr int64_t kSmallCells = int64_t(1) << 24;
+
+int default_flags(tpfa::Mode mode, tpfa_precision_t prec, int form, int64_t cells) {
+  if (form == tpfa::MODE_TRANS) return 0;
+  if (cells <= kSmallCells) return TPFA_LAUNCH_XCD_REMAP;
+  if (prec != TPFA_FP32) return 0;
   const int b = tpfa::base_mode(mode);
   return b == tpfa::MODE_JACOBIAN || b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10
              ? TPFA_LAUNCH_XCD_REMAP
@@ -253,7 +261,7 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   else
     kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec)) : default_kz(mode, prec);
   flags = launch ? launch->flags : 0;
-  if (dflt) flags |= default_flags(mode, prec, form);
+  if (dflt) flags |= default_flags(mode, prec, form, g.nx * (y1 - y0) * g.nz);
   return TPFA_OK;
 }
 
