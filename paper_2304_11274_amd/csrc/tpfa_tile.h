@@ -22,8 +22,9 @@
 //    threads the density of their own cell, so each exp is evaluated once per
 //    cell per workgroup;
 //  * loads and stores are x-fastest and coalesced (a 64-lane wave covers
-//    64 consecutive x cells when TX = 64); outputs are written once with
-//    non-temporal stores;
+//    64 consecutive x cells when TX = 64; rows are ldx >= nx cells apart);
+//    outputs are written once, with non-temporal stores, or ordinary ones in
+//    the FP32 kernels where rows are off 128-byte lines;
 //  * optionally, the tiles of each z chunk are split into one band of tile
 //    rows per XCD, so that halo lines are shared within one L2.
 // One tile body, specialised per mode at compile time, serves every entry

@@ -215,3 +215,29 @@ def test_mixed_pitches_are_refused(gpu):
     with pytest.raises(ValueError, match="row pitch"):
         gpu.residual(g, geo.fluid, pad(geo.kx, 32), p, out=torch.empty(g.shape, device="cuda",
                                                                        dtype=torch.float64))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_row_range_on_pitched_arrays(gpu, prec):
+    """A y-slab launch on row-pitched arrays writes exactly the owned rows of
+    the real columns (equal to the full contiguous launch there) and leaves
+    every other row and all padding untouched."""
+    geo, f, pref, be = case(prec, seed=13)
+    g = geo.grid
+    ldx = 80
+    pref_d = None if pref is None else dev(pref)
+    kw = dict(ry=geo.ry, rz=geo.rz, pref=pref_d)
+    rc, Jc = gpu.jacobian(g, geo.fluid, dev(f["kx"]), dev(f["p"]), seal=dev(f["seal"]), **kw)
+    d = {k: pad(f[k], ldx) for k in ("kx", "p", "seal", "v")}
+    for y0, y1 in ((0, 7), (7, 8), (8, 23)):
+        print(f"row range {y0}:{y1} on pitch {ldx}, {prec}", flush=True)
+        rb, r = out_like(d["p"], (), ldx)
+        Jb, J = out_like(d["p"], (7,), ldx)
+        gpu.jacobian(g, geo.fluid, d["kx"], d["p"], seal=d["seal"], rows=(y0, y1), r_out=r,
+                     J_out=J, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(r[:, y0:y1], rc[:, y0:y1]) and torch.equal(J[:, :, y0:y1],
+                                                                      Jc[:, :, y0:y1])
+        for b in (rb, Jb):
+            assert torch.isnan(b[..., :y0, :]).all() and torch.isnan(b[..., y1:, :]).all()
+            assert padding_untouched(b, 0, g.nx)
