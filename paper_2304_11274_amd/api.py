@@ -429,7 +429,9 @@ class TPFAResidual(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, p, logk, grid, fluid, seal=None, pref=None, ry=1.0, rz=1.0):
-        kx = torch.exp(logk)
+        # one layout for every array of the calls (exp and the cotangents are contiguous)
+        p, seal = p.contiguous(), None if seal is None else seal.contiguous()
+        kx = torch.exp(logk).contiguous()
         r = residual(grid, fluid, kx, p, seal=seal, pref=pref, ry=ry, rz=rz)
         ctx.save_for_backward(p, kx)
         ctx.save_for_forward(p, kx)
@@ -471,7 +473,8 @@ class TPFATransResidual(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, p, logt, grid, fluid, pref=None):
-        t = torch.exp(logt)
+        p = p.contiguous()
+        t = torch.exp(logt).contiguous()
         trans = (t[0], t[1], t[2])
         r = residual(grid, fluid, None, p, pref=pref, trans=trans)
         ctx.save_for_backward(p, t)
@@ -513,7 +516,8 @@ class TPFAAnisoResidual(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, p, logk3, grid, fluid, seal=None, pref=None):
-        k = torch.exp(logk3)
+        p, seal = p.contiguous(), None if seal is None else seal.contiguous()
+        k = torch.exp(logk3).contiguous()
         r = residual(grid, fluid, k[0], p, seal=seal, pref=pref, ky=k[1], kz=k[2])
         ctx.save_for_backward(p, k)
         ctx.save_for_forward(p, k)

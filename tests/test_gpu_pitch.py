@@ -241,3 +241,23 @@ def test_row_range_on_pitched_arrays(gpu, prec):
         for b in (rb, Jb):
             assert torch.isnan(b[..., :y0, :]).all() and torch.isnan(b[..., y1:, :]).all()
             assert padding_untouched(b, 0, g.nx)
+
+
+def test_autograd_functions_accept_pitched_inputs(gpu):
+    """The autograd Functions take row-pitched p / ln k (they work on
+    contiguous copies): values and gradients equal the contiguous case."""
+    geo, f, pref, be = case("fp64", seed=17)
+    g = geo.grid
+    w = dev(f["v"])
+    res = []
+    for put in (dev, lambda a: pad(a, 96)):
+        p = put(f["p"]).requires_grad_(True)
+        logk = put(np.log(f["kx"])).requires_grad_(True)
+        logk3 = put(np.log(np.stack([f["kx"], f["ky"], f["kz"]]))).requires_grad_(True)
+        r = gpu.TPFAResidual.apply(p, logk, g, geo.fluid, put(f["seal"]), None, geo.ry, geo.rz)
+        ra = gpu.TPFAAnisoResidual.apply(p, logk3, g, geo.fluid, put(f["seal"]), None)
+        gp, gk, gk3 = torch.autograd.grad((r * w).sum() + (ra * w).sum(), (p, logk, logk3))
+        res.append((r.detach(), ra.detach(), gp, gk, gk3))
+    torch.cuda.synchronize()
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
