@@ -86,6 +86,33 @@ def _empty(p, grid, ld, lead=(), dtype=None):
     return buf[..., :int(grid.nx)]
 
 
+def pitch_for(grid) -> int:
+    """Row pitch for a grid's arrays: nx rounded up to a multiple of 32 cells,
+    so that rows of float and double arrays start on 128-byte lines (with
+    128-byte aligned buffers). One pitch serves every array of a call, the
+    seal bytes included."""
+    return (int(grid.nx) + 31) // 32 * 32
+
+
+def empty_pitched(grid, dtype, device=None, lead=(), ldx: Optional[int] = None) -> torch.Tensor:
+    """Uninitialised (lead..., nz, ny, nx) array with row pitch ``ldx``
+    (default pitch_for(grid)): the view [..., :nx] of a (lead..., nz, ny, ldx)
+    buffer. Outputs written into such arrays take whole lines at every tile
+    edge."""
+    ld = pitch_for(grid) if ldx is None else int(ldx)
+    if ld < int(grid.nx):
+        raise ValueError(f"row pitch {ld} is below nx = {grid.nx}")
+    buf = torch.empty(tuple(lead) + (int(grid.nz), int(grid.ny), ld), dtype=dtype, device=device)
+    return buf[..., :int(grid.nx)]
+
+
+def to_pitched(t: torch.Tensor, grid, ldx: Optional[int] = None) -> torch.Tensor:
+    """Copy of a (lead..., nz, ny, nx) array in the layout of empty_pitched."""
+    out = empty_pitched(grid, t.dtype, t.device, tuple(t.shape[:-3]), ldx)
+    out.copy_(t)
+    return out
+
+
 def _need(t, name, dtype, n, device, grid=None, ld=None):
     """Checks a tensor argument; returns its row pitch for a per-cell array
     (``grid`` given; ``ld``: the pitch it must have) or None."""

@@ -261,3 +261,19 @@ def test_autograd_functions_accept_pitched_inputs(gpu):
     torch.cuda.synchronize()
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+def test_pitched_helpers(gpu):
+    """Inputs copied with to_pitched and outputs from empty_pitched (rows on
+    128-byte lines): the same results as the contiguous launch."""
+    geo, f, pref, be = case("fp32", seed=19, shape=(45, 20, 7))
+    g = geo.grid
+    kw = dict(ry=geo.ry, rz=geo.rz, pref=dev(pref))
+    rc, Jc = gpu.jacobian(g, geo.fluid, dev(f["kx"]), dev(f["p"]), seal=dev(f["seal"]), **kw)
+    k, p, s = (gpu.to_pitched(dev(f[n]), g) for n in ("kx", "p", "seal"))
+    r = gpu.empty_pitched(g, torch.float32, "cuda")
+    J = gpu.empty_pitched(g, torch.float32, "cuda", (7,))
+    gpu.jacobian(g, geo.fluid, k, p, seal=s, r_out=r, J_out=J, **kw)
+    torch.cuda.synchronize()
+    assert p.stride(-2) == 64 and s.stride(-2) == 64 and J.stride(-2) == 64
+    assert torch.equal(r, rc) and torch.equal(J, Jc)

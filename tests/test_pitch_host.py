@@ -63,3 +63,24 @@ def test_outputs_follow_the_layout_of_p():
     assert api._empty(q, G, G.nx).shape == q.shape
     assert api._empty(q, G, G.nx, dtype=torch.float32).dtype == torch.float32
 
+
+
+@pytest.mark.parametrize("nx,want", [(500, 512), (512, 512), (17, 32), (33, 64), (750, 768)])
+def test_pitch_for_rounds_rows_to_lines(nx, want):
+    g = geomodel.Grid(nx, 3, 2)
+    assert api.pitch_for(g) == want
+    for dtype in (torch.float32, torch.float64, torch.uint8):
+        t = api.empty_pitched(g, dtype, "cpu", (7,))
+        assert tuple(t.shape) == (7, 2, 3, nx) and api._pitch(t, "t", g) == want
+        if dtype != torch.uint8:
+            assert (want * t.element_size()) % 128 == 0
+    with pytest.raises(ValueError):
+        api.empty_pitched(g, torch.float32, "cpu", ldx=nx - 1)
+
+
+def test_to_pitched_copies_values():
+    src = torch.arange(G.nz * G.ny * G.nx, dtype=torch.float64).reshape(G.nz, G.ny, G.nx)
+    t = api.to_pitched(src, G)
+    assert torch.equal(t, src) and api._pitch(t, "t", G) == 32
+    t3 = api.to_pitched(torch.stack([src, -src, 2 * src]), G, ldx=8)
+    assert torch.equal(t3[1], -src) and api._pitch(t3, "t3", G) == 8
