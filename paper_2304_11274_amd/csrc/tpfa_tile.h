@@ -957,20 +957,24 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
 // together, as in the plain order) are split into 8 contiguous bands of
 // tile rows and each band goes to one XCD, so a tile's x and y neighbours
 // mostly run on the same XCD and its halo lines are shared in that L2.
-__device__ __forceinline__ void decode_tile(const Args &a, int64_t b, int &bx, int &by, int &kb) {
-  int64_t t = b;
+// Block ids and tile counts fit in 32 bits (the host refuses launches of 2^32
+// or more workgroups), so the decoding runs in unsigned 32-bit arithmetic: two
+// or three divisions by a runtime value and shifts for the 8 bands, instead of
+// the emulated 64-bit divisions that made most of the workgroup prologue.
+__device__ __forceinline__ void decode_tile(const Args &a, uint32_t b, int &bx, int &by, int &kb) {
+  const uint32_t ntx = (uint32_t)a.ntx, nty = (uint32_t)a.nty;
+  uint32_t t = b;
   if (a.remap) {
-    const int64_t C = (int64_t)a.ntx * a.nty;  // tiles per z chunk
-    const int64_t kc = b / C, u = b % C;
-    const int64_t q = C / 8, rem = C % 8;
-    const int64_t x = u % 8, l = u / 8;  // band x (one XCD), position l in it
+    const uint32_t C = ntx * nty;  // tiles per z chunk
+    const uint32_t kc = b / C, u = b - kc * C;
+    const uint32_t q = C >> 3, rem = C & 7u;
+    const uint32_t x = u & 7u, l = u >> 3;  // band x (one XCD), position l in it
     t = kc * C + (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + l;
   }
-  bx = (int)(t % a.ntx);
-  t /= a.ntx;
-  by = (int)(t % a.nty);
-  t /= a.nty;
-  kb = (int)t * a.kz_chunk;
+  const uint32_t r1 = t / ntx, r2 = r1 / nty;
+  bx = (int)(t - r1 * ntx);
+  by = (int)(r1 - r2 * nty);
+  kb = (int)r2 * a.kz_chunk;
 }
 
 template <class S, int MODE, int TX, int TY>
