@@ -52,6 +52,11 @@
 extern "C" {
 #endif
 
+/* Library version: major * 10000 + minor * 100 + patch (tpfa_version() returns
+   the built library's). The major number changes with the layout of the ABI
+   structs: version 2 added tpfa_grid_t.ldx (row-pitched arrays). */
+#define TPFA_VERSION 20000
+
 #define TPFA_OK 0
 #define TPFA_ERR_NULL (-1)        /* a required pointer is NULL */
 #define TPFA_ERR_SHAPE (-2)       /* a dimension <= 0, 0 < ldx < nx, ldx*ny*nz overflows, or one x-y plane of an array holds 2^32 bytes or more */
@@ -305,7 +310,7 @@ int tpfa_tile_shape(int id, int *tx, int *ty, int *threads);
 
 const char *tpfa_strerror(int code);
 const char *tpfa_last_error(void);
-int tpfa_version(void);
+int tpfa_version(void); /* TPFA_VERSION of the library's build */
 
 #ifdef __cplusplus
 }

@@ -102,6 +102,10 @@ SIGNATURES = {
 _lib = None
 
 
+# major version of the struct layouts below (TPFA_VERSION / 10000 in include/tpfa.h)
+ABI_MAJOR = 2
+
+
 def load():
     """Load libtpfa.so from the package directory (raises if absent)."""
     global _lib
@@ -115,6 +119,11 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        if lib.tpfa_version() // 10000 != ABI_MAJOR:
+            raise RuntimeError(
+                f"{LIB_PATH} has version {lib.tpfa_version()}, this binding's structs are "
+                f"those of major version {ABI_MAJOR}: rebuild it with "
+                "`python -m paper_2304_11274_amd.build`")
         _lib = lib
     return _lib
 

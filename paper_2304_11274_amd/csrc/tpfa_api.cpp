@@ -733,6 +733,6 @@ const char *tpfa_strerror(int code) {
 
 const char *tpfa_last_error(void) { return g_last_error.c_str(); }
 
-int tpfa_version(void) { return 10000; }
+int tpfa_version(void) { return TPFA_VERSION; }
 
 }  // extern "C"

@@ -36,7 +36,10 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_introspection(lib):
-    assert lib.tpfa_version() >= 10000
+    assert lib.tpfa_version() // 10000 == L.ABI_MAJOR
+    # the header's version is the one the library was built with
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "tpfa.h")).read()
+    assert f"#define TPFA_VERSION {lib.tpfa_version()}" in hdr
     shapes = tp.tile_shapes()
     assert len(shapes) == lib.tpfa_num_tiles()
     for tx, ty, th in shapes:
