@@ -131,9 +131,9 @@ def main():
                     help="applications per mesh in the paper10 section (the paper uses 1000)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition of this path is described in DESIGN.md but not built.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the y-slab "
+              "decomposition across GPUs is not implemented (the per-GPU slab launch is: "
+              "see the 'slab' section).", file=sys.stderr)
         sys.exit(2)
     sections = set(args.sections.split(","))
 
