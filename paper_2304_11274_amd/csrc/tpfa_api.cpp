@@ -133,11 +133,14 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
 }
 
 // z planes per workgroup: 32 for the residual-only modes and the FP64
-// Jacobian (0.7% faster than 16 there), 16 for the other products.
-int default_kz(tpfa::Mode mode, tpfa_precision_t prec) {
+// Jacobians (0.7% faster than 16 there) and for the FP32 Jacobian of the ratio
+// form (1% faster), 16 for the other products (the FP32 backward-Euler and
+// per-direction Jacobians ran 0.6-1.3% slower with 32).
+int default_kz(tpfa::Mode mode, tpfa_precision_t prec, int form) {
   const int b = tpfa::base_mode(mode);
   if (b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10) return 32;
-  return b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 ? 32 : 16;
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64) return 32;
+  return mode == tpfa::MODE_JACOBIAN && form == 0 ? 32 : 16;
 }
 
 int hip_fail(hipError_t e, const char *what) {
@@ -259,7 +262,8 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   if (launch && launch->kz_chunk > 0)
     kz = launch->kz_chunk;
   else
-    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec)) : default_kz(mode, prec);
+    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form))
+              : default_kz(mode, prec, form);
   flags = launch ? launch->flags : 0;
   if (dflt) flags |= default_flags(mode, prec, form, g.nx * (y1 - y0) * g.nz);
   return TPFA_OK;
