@@ -303,6 +303,30 @@ void tpfa_batch_destroy(tpfa_batch_t *batch);
 
 /* ---- Introspection ---- */
 
+/* Operations of the single-grid entry points, for tpfa_resolve_launch. */
+typedef enum {
+  TPFA_OP_RESIDUAL = 0,    /* tpfa_residual */
+  TPFA_OP_JACOBIAN = 1,    /* tpfa_jacobian */
+  TPFA_OP_VJP = 2,         /* tpfa_residual_vjp, tpfa_residual_vjp_trans */
+  TPFA_OP_RESIDUAL10 = 3,  /* tpfa_residual10 */
+  TPFA_OP_RESIDUAL_BE = 4, /* tpfa_residual_be */
+  TPFA_OP_JACOBIAN_BE = 5, /* tpfa_jacobian_be */
+  TPFA_OP_JVP = 6,         /* tpfa_jvp without accum */
+  TPFA_OP_JVP_BE = 7       /* tpfa_jvp with accum */
+} tpfa_op_t;
+
+/* The launch that a call of operation `op` with this grid, precision, rock
+   form and launch argument would make, written to *resolved: tile id,
+   z planes per workgroup (as run: at most nz), flags (the XCD band order
+   included where the defaults set it) and row range [y_begin, y_end).
+   Of `rock` only which arrays are given is read (it decides the form);
+   nothing is dereferenced on the device and nothing is enqueued. Errors:
+   TPFA_ERR_NULL (grid, rock or resolved NULL), the grid and launch checks of
+   the calls, TPFA_ERR_PARAM for an unknown op or precision. */
+int tpfa_resolve_launch(const tpfa_grid_t *grid, int op, tpfa_precision_t prec,
+                        const tpfa_rock_t *rock, const tpfa_launch_t *launch,
+                        tpfa_launch_t *resolved);
+
 /* Number of compiled tile shapes; shape of tile `id`: TX x TY cells per
    workgroup plane and the workgroup size in threads. */
 int tpfa_num_tiles(void);

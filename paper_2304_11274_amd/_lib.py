@@ -21,6 +21,9 @@ TPFA_ERR_TILE = -6
 
 TPFA_FP64 = 0
 TPFA_FP32 = 1
+# tpfa_op_t
+TPFA_OP_RESIDUAL, TPFA_OP_JACOBIAN, TPFA_OP_VJP, TPFA_OP_RESIDUAL10 = 0, 1, 2, 3
+TPFA_OP_RESIDUAL_BE, TPFA_OP_JACOBIAN_BE, TPFA_OP_JVP, TPFA_OP_JVP_BE = 4, 5, 6, 7
 TPFA_BATCH_RESIDUAL = 0
 TPFA_BATCH_JACOBIAN = 1
 TPFA_LAUNCH_XCD_REMAP = 1
@@ -97,6 +100,7 @@ SIGNATURES = {
     "tpfa_strerror": (C.c_char_p, [C.c_int]),
     "tpfa_last_error": (C.c_char_p, []),
     "tpfa_version": (C.c_int, []),
+    "tpfa_resolve_launch": (C.c_int, [P(Grid), C.c_int, C.c_int, P(Rock), P(Launch), P(Launch)]),
 }
 
 _lib = None

@@ -365,6 +365,37 @@ def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torc
     return dp
 
 
+_OPS = {"residual": L.TPFA_OP_RESIDUAL, "jacobian": L.TPFA_OP_JACOBIAN, "vjp": L.TPFA_OP_VJP,
+        "residual10": L.TPFA_OP_RESIDUAL10, "residual_be": L.TPFA_OP_RESIDUAL_BE,
+        "jacobian_be": L.TPFA_OP_JACOBIAN_BE, "jvp": L.TPFA_OP_JVP, "jvp_be": L.TPFA_OP_JVP_BE}
+_GIVEN = 1  # non-null marker for an array: tpfa_resolve_launch only reads which are given
+
+
+def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=None,
+                   kz_chunk=None, xcd_remap=False, rows=None, ldx: Optional[int] = None) -> dict:
+    """The launch a call of ``op`` ('residual', 'jacobian', 'vjp', 'residual10',
+    'residual_be', 'jacobian_be', 'jvp', 'jvp_be') would make on this grid in
+    this precision, rock form ('k': kx with ratios, 'k3': kx, ky, kz arrays,
+    'trans': face transmissibilities), row pitch and launch arguments: tile
+    id and shape, z planes per workgroup, XCD band order, row range. Nothing
+    runs on the GPU."""
+    prec = {torch.float64: L.TPFA_FP64, torch.float32: L.TPFA_FP32}[dtype]
+    G = _GIVEN
+    rock = {"k": L.Rock(G, None, None, 1.0, 1.0, None),
+            "k3": L.Rock(G, G, G, 1.0, 1.0, None),
+            "trans": L.Rock(None, None, None, 1.0, 1.0, None, G, G, G)}[form]
+    ln = _launch(tile, kz_chunk, xcd_remap, rows)
+    out = L.Launch()
+    lib = L.load()
+    L.check(lib.tpfa_resolve_launch(C.byref(_grid(grid, int(grid.nx) if ldx is None else ldx)),
+                                    _OPS[op], prec, C.byref(rock),
+                                    None if ln is None else C.byref(ln), C.byref(out)), lib)
+    tx, ty, th = tile_shapes()[out.tile]
+    return {"tile": out.tile, "shape": (tx, ty), "threads": th, "kz_chunk": out.kz_chunk,
+            "xcd_remap": bool(out.flags & L.TPFA_LAUNCH_XCD_REMAP),
+            "rows": (out.y_begin, out.y_end)}
+
+
 def tile_shapes():
     """[(tx, ty, threads)] of the compiled tiles, indexed by tile id."""
     lib = L.load()

@@ -18,6 +18,17 @@
 #include "../../include/tpfa.h"
 #include "tpfa_internal.h"
 
+// the public op values are the kernel modes of the entry points
+static_assert(int(TPFA_OP_RESIDUAL) == int(tpfa::MODE_RESIDUAL) &&
+                  int(TPFA_OP_JACOBIAN) == int(tpfa::MODE_JACOBIAN) &&
+                  int(TPFA_OP_VJP) == int(tpfa::MODE_VJP) &&
+                  int(TPFA_OP_RESIDUAL10) == int(tpfa::MODE_RES10) &&
+                  int(TPFA_OP_RESIDUAL_BE) == int(tpfa::MODE_RESIDUAL_BE) &&
+                  int(TPFA_OP_JACOBIAN_BE) == int(tpfa::MODE_JACOBIAN_BE) &&
+                  int(TPFA_OP_JVP) == int(tpfa::MODE_JVP) &&
+                  int(TPFA_OP_JVP_BE) == int(tpfa::MODE_JVP_BE),
+              "tpfa_op_t and the kernel modes disagree");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -710,6 +721,42 @@ void tpfa_batch_destroy(tpfa_batch_t *batch) {
   if (!batch) return;
   (void)hipDeviceSynchronize();
   batch_free(batch);
+}
+
+int tpfa_resolve_launch(const tpfa_grid_t *grid, int op, tpfa_precision_t prec,
+                        const tpfa_rock_t *rock, const tpfa_launch_t *launch,
+                        tpfa_launch_t *resolved) {
+  try {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!rock || !resolved) return fail(TPFA_ERR_NULL, "rock and resolved are required");
+    if (op < TPFA_OP_RESIDUAL || op > TPFA_OP_JVP_BE) return fail(TPFA_ERR_PARAM, "unknown op");
+    if (prec != TPFA_FP64 && prec != TPFA_FP32)
+      return fail(TPFA_ERR_PARAM, "unknown precision");
+    if (launch) {
+      if (launch->tile < -1 || launch->tile >= tpfa::kNumTiles)
+        return fail(TPFA_ERR_TILE, "unknown tile id");
+      if (launch->kz_chunk < 0) return fail(TPFA_ERR_TILE, "kz_chunk must be >= 0");
+      if ((launch->y_begin != 0 || launch->y_end != 0) &&
+          !(launch->y_begin >= 0 && launch->y_begin < launch->y_end &&
+            launch->y_end <= grid->ny))
+        return fail(TPFA_ERR_PARAM, "row range must satisfy 0 <= y_begin < y_end <= ny");
+    }
+    const tpfa::Mode mode = static_cast<tpfa::Mode>(op);
+    int tile, kz, flags;
+    int64_t y0, y1;
+    resolve_launch(*grid, mode, prec, rock_form(*rock), launch, tile, kz, flags, y0, y1);
+    resolved->tile = tile;
+    resolved->kz_chunk = (int)std::min<int64_t>(kz, grid->nz);
+    resolved->flags = flags;
+    resolved->y_begin = y0;
+    resolved->y_end = y1;
+    return ok();
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
 }
 
 int tpfa_num_tiles(void) { return tpfa::kNumTiles; }

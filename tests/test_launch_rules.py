@@ -1,0 +1,128 @@
+"""The library's default launch rules, read through tpfa_resolve_launch on the
+host (no GPU): tile shape by mode, precision, rock form and row alignment; the
+z chunk by mode and its shortening on small grids (the launch must hold at
+least one full residency of the chip, 256 CUs x 4 SIMDs x 8 waves); the XCD
+band order by size, precision and form; row ranges; explicit launches taken as
+given; argument errors."""
+import ctypes as C
+
+import pytest
+import torch
+
+import geomodel
+from paper_2304_11274_amd import _lib as L
+from paper_2304_11274_amd import api
+
+F64, F32 = torch.float64, torch.float32
+G512 = geomodel.Grid(512, 512, 256)
+
+
+def rl(grid, op, dtype=F64, **kw):
+    return api.resolve_launch(grid, op, dtype, **kw)
+
+
+def test_benchmark_launches():
+    a = rl(G512, "jacobian")
+    assert (a["shape"], a["threads"], a["kz_chunk"], a["xcd_remap"]) == ((64, 8), 512, 32, False)
+    assert a["rows"] == (0, 512)
+    b = rl(G512, "jacobian", F32)
+    assert (b["shape"], b["kz_chunk"], b["xcd_remap"]) == ((64, 8), 32, True)
+    assert rl(G512, "jacobian_be", F32)["kz_chunk"] == 16
+    assert rl(G512, "residual")["shape"] == (64, 4)   # shared faces, more LDS
+    assert rl(G512, "residual", F32)["shape"] == (64, 8)
+    for op in ("vjp", "jvp", "jvp_be"):
+        r = rl(G512, op)
+        assert (r["shape"], r["kz_chunk"], r["xcd_remap"]) == ((64, 4), 16, False), op
+    k3 = rl(G512, "jacobian", form="k3")
+    assert (k3["shape"], k3["kz_chunk"]) == ((64, 4), 32)   # 142 VGPRs: smaller workgroups
+    assert rl(G512, "jacobian", F32, form="k3")["kz_chunk"] == 16
+
+
+def test_rows_off_lines_and_row_pitch():
+    g = geomodel.Grid(500, 500, 256)
+    assert rl(g, "jacobian")["shape"] == (128, 4)          # halves the partial lines
+    assert rl(g, "jacobian", ldx=512)["shape"] == (64, 8)  # pitched rows are on lines
+    assert rl(g, "jacobian", F32)["shape"] == (64, 8)
+    # 128-wide tiles would idle more lanes than 64-wide ones on 300-wide rows
+    assert rl(geomodel.Grid(300, 700, 256), "jacobian")["shape"] == (64, 8)
+
+
+def test_narrow_grids_and_the_10_flux_stencil():
+    assert rl(geomodel.Grid(16, 40, 30), "jacobian")["shape"] == (16, 16)
+    assert rl(geomodel.Grid(30, 40, 30), "jacobian")["shape"] == (32, 8)
+    p10 = rl(geomodel.Grid(750, 994, 246), "residual10", F32)
+    assert (p10["shape"], p10["kz_chunk"], p10["xcd_remap"]) == ((128, 4), 32, True)
+    assert rl(geomodel.Grid(750, 994, 246), "residual10", F32, form="trans")["xcd_remap"] is False
+    assert rl(geomodel.Grid(100, 100, 50), "residual10", F32)["shape"] == (64, 4)
+
+
+def full_residency_waves(r, grid, rows):
+    tx, ty = r["shape"]
+    tiles = -(-grid.nx // tx) * -(-rows // ty)
+    return tiles * -(-grid.nz // r["kz_chunk"]) * (r["threads"] // 64)
+
+
+@pytest.mark.parametrize("shape,op,dtype,default,kz", [
+    ((256, 256, 128), "jacobian", F64, 32, 16),
+    ((256, 256, 128), "vjp", F32, 16, 16),
+    ((128, 128, 64), "residual", F32, 32, 4),
+    ((128, 128, 64), "jacobian", F64, 32, 4),
+    ((512, 512, 256), "jacobian", F64, 32, 32),
+])
+def test_small_grids_get_shorter_chunks(shape, op, dtype, default, kz):
+    """The default chunk is halved, down to 4 planes, until the launch holds a
+    full residency; a chunk shorter than the default is the longest that does."""
+    g = geomodel.Grid(*shape)
+    r = rl(g, op, dtype)
+    assert r["kz_chunk"] == kz
+    assert full_residency_waves(r, g, g.ny) >= 8192 or kz == 4
+    if kz < default:
+        assert full_residency_waves(dict(r, kz_chunk=2 * kz), g, g.ny) < 8192
+
+
+def test_band_order_by_size_precision_and_form():
+    small = geomodel.Grid(256, 256, 128)        # 2^23 cells
+    for op in ("residual", "jacobian", "vjp", "jvp", "residual_be", "jacobian_be"):
+        for dt in (F64, F32):
+            assert rl(small, op, dt)["xcd_remap"], (op, dt)
+            assert rl(small, op, dt, form="k3")["xcd_remap"], (op, dt)
+    assert not rl(small, "jacobian", form="trans")["xcd_remap"]
+    big = geomodel.Grid(512, 512, 256)          # 2^26 cells
+    assert not rl(big, "jacobian")["xcd_remap"] and not rl(big, "vjp", F32)["xcd_remap"]
+    assert rl(big, "residual", F32)["xcd_remap"]
+    # the rule counts the computed cells: one slab of 64 rows of the big grid is small
+    slab = rl(geomodel.Grid(512, 66, 256), "jacobian", rows=(1, 65))
+    assert slab["xcd_remap"] and slab["rows"] == (1, 65) and slab["kz_chunk"] == 16
+    assert rl(geomodel.Grid(512, 4097, 16), "jacobian")["xcd_remap"] is False  # 2^25 cells
+
+
+def test_explicit_launches_are_taken_as_given():
+    r = rl(G512, "jacobian", F32, tile=0, kz_chunk=7)
+    assert (r["tile"], r["kz_chunk"], r["xcd_remap"]) == (0, 7, False)
+    r = rl(G512, "jacobian", tile=5, xcd_remap=True)
+    assert (r["shape"], r["xcd_remap"], r["kz_chunk"]) == ((32, 16), True, 32)
+    assert rl(geomodel.Grid(64, 64, 5), "jacobian", kz_chunk=64)["kz_chunk"] == 5  # at most nz
+
+
+def test_errors():
+    lib = L.load()
+    g = api._grid(G512)
+    rock = L.Rock(1, None, None, 1.0, 1.0, None)
+    out = L.Launch()
+    assert lib.tpfa_resolve_launch(C.byref(g), 8, L.TPFA_FP64, C.byref(rock), None,
+                                   C.byref(out)) == L.TPFA_ERR_PARAM
+    assert lib.tpfa_resolve_launch(C.byref(g), 1, 5, C.byref(rock), None,
+                                   C.byref(out)) == L.TPFA_ERR_PARAM
+    assert lib.tpfa_resolve_launch(C.byref(g), 1, L.TPFA_FP64, None, None,
+                                   C.byref(out)) == L.TPFA_ERR_NULL
+    assert lib.tpfa_resolve_launch(None, 1, L.TPFA_FP64, C.byref(rock), None,
+                                   C.byref(out)) == L.TPFA_ERR_NULL
+    bad_rows = L.Launch(-1, 0, 0, 3, 600)
+    assert lib.tpfa_resolve_launch(C.byref(g), 1, L.TPFA_FP64, C.byref(rock), C.byref(bad_rows),
+                                   C.byref(out)) == L.TPFA_ERR_PARAM
+    bad_tile = L.Launch(10, 0, 0, 0, 0)
+    assert lib.tpfa_resolve_launch(C.byref(g), 1, L.TPFA_FP64, C.byref(rock), C.byref(bad_tile),
+                                   C.byref(out)) == L.TPFA_ERR_TILE
+    g.ldx = 100
+    assert lib.tpfa_resolve_launch(C.byref(g), 1, L.TPFA_FP64, C.byref(rock), None,
+                                   C.byref(out)) == L.TPFA_ERR_SHAPE
