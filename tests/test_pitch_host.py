@@ -84,3 +84,49 @@ def test_to_pitched_copies_values():
     assert torch.equal(t, src) and api._pitch(t, "t", G) == 32
     t3 = api.to_pitched(torch.stack([src, -src, 2 * src]), G, ldx=8)
     assert torch.equal(t3[1], -src) and api._pitch(t3, "t3", G) == 8
+
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@st.composite
+def strided_views(draw):
+    """A view of a buffer with strides near those of a row-padded layout:
+    each stride is the padded one or, with some probability, another value."""
+    nx, ny, nz = draw(st.integers(1, 9)), draw(st.integers(1, 5)), draw(st.integers(1, 4))
+    lead = draw(st.sampled_from([0, 1, 3]))
+    ld = draw(st.integers(nx, nx + 6))
+    exact = (1, ld, ld * ny, ld * ny * nz)
+    strides = [e if draw(st.booleans()) or draw(st.booleans()) else draw(st.integers(1, 300))
+               for e in exact]
+    off = draw(st.integers(0, 5))
+    return nx, ny, nz, lead, strides, off
+
+
+@settings(max_examples=400, deadline=None)
+@given(v=strided_views())
+def test_accepted_views_have_the_kernel_layout(v):
+    """Whatever strides a tensor has, if the binding accepts it with pitch ld,
+    element (q, k, j, i) lies at storage offset q*ld*ny*nz + i + ld*(j + ny*k)
+    from its first element: the addressing the kernels use."""
+    nx, ny, nz, lead, (sx, sy, sz, sp), off = v
+    g = geomodel.Grid(nx, ny, nz)
+    shape = ((lead,) if lead else ()) + (nz, ny, nx)
+    strides = ((sp,) if lead else ()) + (sz, sy, sx)
+    need = off + sum((n - 1) * s for n, s in zip(shape, strides)) + 1
+    t = torch.arange(need, dtype=torch.float64).as_strided(shape, strides, off)
+    try:
+        ld = api._pitch(t, "t", g)
+    except ValueError:
+        return
+    assert ld >= nx
+    t4 = t if lead else t.unsqueeze(0)
+    q, k, j, i = torch.meshgrid(*(torch.arange(n) for n in t4.shape), indexing="ij")
+    want = off + q * ld * ny * nz + i + ld * (j + ny * k)
+    assert torch.equal(t4.to(torch.int64), want.to(torch.int64))
+
+
+def test_layout_property_sees_accepted_padded_views():
+    """The generator above reaches accepted padded layouts (pitch > nx)."""
+    t = torch.arange(2 * 3 * 4 * 10, dtype=torch.float64).as_strided((2, 3, 4, 7), (120, 40, 10, 1))
+    assert api._pitch(t, "t", geomodel.Grid(7, 4, 3)) == 10
