@@ -55,31 +55,60 @@ def _prec(p: torch.Tensor) -> int:
     raise TypeError(f"p must be float64 or float32, got {p.dtype}")
 
 
-def _pitch(t, name, grid) -> int:
+def _pitch(t, name, grid) -> Optional[int]:
     """Row pitch of a per-cell array of shape (nz, ny, nx) or (P, nz, ny, nx):
     nx when it is contiguous, ldx when it is a view ``buf[..., :nx]`` of a
-    row-padded buffer (..., nz, ny, ldx)."""
+    row-padded buffer (..., nz, ny, ldx); None when the array holds a single
+    row, which every pitch addresses alike."""
     nx, ny, nz = int(grid.nx), int(grid.ny), int(grid.nz)
-    if t.is_contiguous():
-        return nx
-    if t.dim() not in (3, 4) or tuple(t.shape[-3:]) != (nz, ny, nx) or t.stride(-1) != 1:
+    if t.dim() in (3, 4) and tuple(t.shape[-3:]) == (nz, ny, nx):
+        if nx > 1 and t.stride(-1) != 1:
+            raise ValueError(f"{name} must be contiguous along x")
+        # stride of each dimension in units of the pitch (dimensions of size 1 carry none)
+        per = {-2: 1, -3: ny}
+        if t.dim() == 4:
+            per[0] = ny * nz
+        fixed = [(d, f) for d, f in per.items() if t.shape[d] > 1]
+        if not fixed:
+            return None
+        ld = t.stride(fixed[0][0]) // fixed[0][1]
+        if ld < nx or any(t.stride(d) != f * ld for d, f in fixed):
+            raise ValueError(f"{name}: strides {t.stride()} are not those of a row-padded "
+                             f"(..., nz, ny, ldx) buffer")
+        return ld
+    if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous or a view [..., :nx] of a row-padded "
                          f"(..., nz, ny, ldx) buffer")
-    # stride of each dimension in units of the pitch (dimensions of size 1 carry none)
-    per = {-2: 1, -3: ny}
-    if t.dim() == 4:
-        per[0] = ny * nz
-    ld = next((t.stride(d) // f for d, f in per.items() if t.shape[d] > 1), nx)
-    if ld < nx or any(t.shape[d] > 1 and t.stride(d) != f * ld for d, f in per.items()):
-        raise ValueError(f"{name}: strides {t.stride()} are not those of a row-padded "
-                         f"(..., nz, ny, ldx) buffer")
-    return ld
+    return nx if t.numel() > nx else None
 
 
-def _empty(p, grid, ld, lead=(), dtype=None):
-    """Output array in the layout of ``p``: p's shape when contiguous, else a
-    view [..., :nx] of a new buffer with row pitch ld."""
+class _Layout:
+    """The one row pitch of a call's per-cell arrays: set by the first array
+    that fixes it (arrays of a single row fit any pitch), nx if none does."""
+
+    def __init__(self, grid):
+        self.grid = grid
+        self.ld = None
+
+    def take(self, t, name):
+        got = _pitch(t, name, self.grid)
+        if got is None:
+            return
+        if self.ld is None:
+            self.ld = got
+        elif got != self.ld:
+            raise ValueError(f"{name} has row pitch {got}, the call's other arrays {self.ld}")
+
+    @property
+    def pitch(self) -> int:
+        return int(self.grid.nx) if self.ld is None else self.ld
+
+
+def _empty(p, lay, lead=(), dtype=None):
+    """Output array in the call's layout: p's shape when the pitch is nx, else
+    a view [..., :nx] of a new buffer with the call's row pitch."""
     dt = p.dtype if dtype is None else dtype
+    grid, ld = lay.grid, lay.pitch
     if ld == int(grid.nx):
         return torch.empty(tuple(lead) + tuple(p.shape), dtype=dt, device=p.device)
     buf = torch.empty(tuple(lead) + (int(grid.nz), int(grid.ny), ld), dtype=dt, device=p.device)
@@ -113,11 +142,11 @@ def to_pitched(t: torch.Tensor, grid, ldx: Optional[int] = None) -> torch.Tensor
     return out
 
 
-def _need(t, name, dtype, n, device, grid=None, ld=None):
-    """Checks a tensor argument; returns its row pitch for a per-cell array
-    (``grid`` given; ``ld``: the pitch it must have) or None."""
+def _need(t, name, dtype, n, device, lay=None):
+    """Checks a tensor argument; a per-cell array (``lay`` given) must fit the
+    call's row pitch."""
     if t is None:
-        return None
+        return
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.device.type != "cuda":
@@ -128,14 +157,11 @@ def _need(t, name, dtype, n, device, grid=None, ld=None):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
-    if grid is None:
+    if lay is None:
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
-        return None
-    got = _pitch(t, name, grid)
-    if ld is not None and got != ld:
-        raise ValueError(f"{name} has row pitch {got}, the call's other arrays {ld}")
-    return got
+        return
+    lay.take(t, name)
 
 
 def _kyz(ky, kz):
@@ -149,28 +175,29 @@ def _inputs(grid, kx, p, seal, pref, trans=None, kyz=None):
     prec = _prec(p)
     dt = p.dtype
     dev = p.device
-    ld = _need(p, "p", dt, n, None, grid)
+    lay = _Layout(grid)
+    _need(p, "p", dt, n, None, lay)
     if kyz is not None:
         if trans is not None:
             raise ValueError("give either permeabilities (kx, ky, kz) or trans, not both")
-        _need(kyz[0], "ky", dt, n, dev, grid, ld)
-        _need(kyz[1], "kz", dt, n, dev, grid, ld)
+        _need(kyz[0], "ky", dt, n, dev, lay)
+        _need(kyz[1], "kz", dt, n, dev, lay)
     if trans is not None:
         if kx is not None or seal is not None:
             raise ValueError("give either kx (and seal) or trans=(tx, ty, tz), not both")
         for name, t in zip(("tx", "ty", "tz"), trans):
             if t is None:
                 raise ValueError(f"trans needs {name}")
-            _need(t, name, dt, n, dev, grid, ld)
+            _need(t, name, dt, n, dev, lay)
     elif kx is None:
         raise ValueError("kx is required (or trans=(tx, ty, tz))")
-    _need(kx, "kx", dt, n, dev, grid, ld)
-    _need(seal, "seal", torch.uint8, n, dev, grid, ld)
+    _need(kx, "kx", dt, n, dev, lay)
+    _need(seal, "seal", torch.uint8, n, dev, lay)
     if prec == L.TPFA_FP32:
         if pref is None:
             raise ValueError("the FP32 precision form needs pref (float64[nz])")
         _need(pref, "pref", torch.float64, int(grid.nz), dev)
-    return n, prec, dt, dev, ld
+    return n, prec, dt, dev, lay
 
 
 def _rock(kx, seal, ry, rz, trans=None, ky=None, kz=None) -> L.Rock:
@@ -183,11 +210,11 @@ def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
              out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
              rows=None) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    r = out if out is not None else _empty(p, grid, ld)
-    _need(r, "out", dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    r = out if out is not None else _empty(p, lay)
+    _need(r, "out", dt, n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_residual(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_residual(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
                               _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
@@ -204,15 +231,15 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
              xcd_remap=False, rows=None):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = None
     if want_r:
-        r = r_out if r_out is not None else _empty(p, grid, ld)
-        _need(r, "r_out", dt, n, dev, grid, ld)
-    J = J_out if J_out is not None else _empty(p, grid, ld, (7,))
-    _need(J, "J_out", dt, 7 * n, dev, grid, ld)
+        r = r_out if r_out is not None else _empty(p, lay)
+        _need(r, "r_out", dt, n, dev, lay)
+    J = J_out if J_out is not None else _empty(p, lay, (7,))
+    _need(J, "J_out", dt, 7 * n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_jacobian(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_jacobian(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
                               _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
@@ -226,32 +253,32 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     ``trans`` = (tx, ty, tz) the second output is grad_logt [3, nz, ny, nx]:
     d(w.r)/d ln T of each cell's +x, +y, +z face. With per-direction arrays
     ``ky``, ``kz`` it is [3, nz, ny, nx]: d(w.r)/d ln kx, ln ky, ln kz."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    _need(w, "w", dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    _need(w, "w", dt, n, dev, lay)
     planes = 3 if trans is not None or ky is not None else 1
     gp = gm = None
     if want_p:
-        gp = gp_out if gp_out is not None else _empty(p, grid, ld)
-        _need(gp, "gp_out", dt, n, dev, grid, ld)
+        gp = gp_out if gp_out is not None else _empty(p, lay)
+        _need(gp, "gp_out", dt, n, dev, lay)
     if want_logk:
-        gm = gm_out if gm_out is not None else _empty(p, grid, ld, (3,) if planes == 3 else ())
-        _need(gm, "gm_out", dt, planes * n, dev, grid, ld)
+        gm = gm_out if gm_out is not None else _empty(p, lay, (3,) if planes == 3 else ())
+        _need(gm, "gm_out", dt, planes * n, dev, lay)
     lib = L.load()
     fn = lib.tpfa_residual_vjp_trans if trans is not None else lib.tpfa_residual_vjp
-    L.check(fn(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(fn(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w), _ptr(gp), _ptr(gm),
                _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
     return gp, gm
 
 
-def _accum(accum, dt_, n, dev, grid, ld):
+def _accum(accum, dt_, n, dev, lay):
     """``accum`` = dict(phi=..., p_prev=..., dt=..., cr=...) -> L.Accum."""
     if accum is None:
         return None
     phi, p_prev = accum["phi"], accum["p_prev"]
-    _need(phi, "phi", dt_, n, dev, grid, ld)
-    _need(p_prev, "p_prev", dt_, n, dev, grid, ld)
+    _need(phi, "phi", dt_, n, dev, lay)
+    _need(p_prev, "p_prev", dt_, n, dev, lay)
     return L.Accum(_ptr(phi), _ptr(p_prev), float(accum["dt"]), float(accum.get("cr", 0.0)))
 
 
@@ -260,14 +287,14 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
                 rows=None) -> torch.Tensor:
     """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
     the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    acc = _accum(accum, dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    acc = _accum(accum, dt, n, dev, lay)
     if acc is None:
         raise ValueError("residual_be needs accum")
-    r = out if out is not None else _empty(p, grid, ld)
-    _need(r, "out", dt, n, dev, grid, ld)
+    r = out if out is not None else _empty(p, lay)
+    _need(r, "out", dt, n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_residual_be(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_residual_be(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
@@ -279,18 +306,18 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
                 kz=None, want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
                 xcd_remap=False, rows=None):
     """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    acc = _accum(accum, dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    acc = _accum(accum, dt, n, dev, lay)
     if acc is None:
         raise ValueError("jacobian_be needs accum")
     r = None
     if want_r:
-        r = r_out if r_out is not None else _empty(p, grid, ld)
-        _need(r, "r_out", dt, n, dev, grid, ld)
-    J = J_out if J_out is not None else _empty(p, grid, ld, (7,))
-    _need(J, "J_out", dt, 7 * n, dev, grid, ld)
+        r = r_out if r_out is not None else _empty(p, lay)
+        _need(r, "r_out", dt, n, dev, lay)
+    J = J_out if J_out is not None else _empty(p, lay, (7,))
+    _need(J, "J_out", dt, 7 * n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap, rows),
@@ -303,17 +330,17 @@ def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1
         xcd_remap=False, rows=None):
     """Matrix-free J v of the flux residual, or of the backward-Euler residual
     when ``accum`` is given; returns (jv, r or None)."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    _need(v, "v", dt, n, dev, grid, ld)
-    acc = _accum(accum, dt, n, dev, grid, ld)
-    jv = out if out is not None else _empty(p, grid, ld)
-    _need(jv, "out", dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    _need(v, "v", dt, n, dev, lay)
+    acc = _accum(accum, dt, n, dev, lay)
+    jv = out if out is not None else _empty(p, lay)
+    _need(jv, "out", dt, n, dev, lay)
     r = None
     if want_r:
-        r = r_out if r_out is not None else _empty(p, grid, ld)
-        _need(r, "r_out", dt, n, dev, grid, ld)
+        r = r_out if r_out is not None else _empty(p, lay)
+        _need(r, "r_out", dt, n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_jvp(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_jvp(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                          C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                          C.byref(L.State(_ptr(p), _ptr(pref))),
                          None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
@@ -326,13 +353,13 @@ def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz
                rows=None) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
     faces with caller-supplied transmissibilities tne, tse)."""
-    n, prec, dt, dev, ld = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
-    _need(tne, "tne", dt, n, dev, grid, ld)
-    _need(tse, "tse", dt, n, dev, grid, ld)
-    r = out if out is not None else _empty(p, grid, ld)
-    _need(r, "out", dt, n, dev, grid, ld)
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
+    _need(tne, "tne", dt, n, dev, lay)
+    _need(tse, "tse", dt, n, dev, lay)
+    r = out if out is not None else _empty(p, lay)
+    _need(r, "out", dt, n, dev, lay)
     lib = L.load()
-    L.check(lib.tpfa_residual10(C.byref(_grid(grid, ld)), C.byref(_fluid(fluid)),
+    L.check(lib.tpfa_residual10(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                 C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                 C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
                                 _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
@@ -355,13 +382,15 @@ def hydrostatic(grid, fluid, p_top: Optional[float] = None, device=None) -> torc
 def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torch.Tensor:
     """FP32 offsets dp = (float)(p - pref[k]) of an FP64 pressure field."""
     n = int(grid.nx) * int(grid.ny) * int(grid.nz)
-    ld = _need(p, "p", torch.float64, n, None, grid)
+    lay = _Layout(grid)
+    _need(p, "p", torch.float64, n, None, lay)
     _need(pref, "pref", torch.float64, int(grid.nz), p.device)
-    dp = out if out is not None else _empty(p, grid, ld, dtype=torch.float32)
-    _need(dp, "out", torch.float32, n, p.device, grid, ld)
+    if out is not None:
+        _need(out, "out", torch.float32, n, p.device, lay)
+    dp = out if out is not None else _empty(p, lay, dtype=torch.float32)
     lib = L.load()
-    L.check(lib.tpfa_offset_pressure(C.byref(_grid(grid, ld)), _ptr(p), _ptr(pref), _ptr(dp),
-                                     _stream(p.device)), lib)
+    L.check(lib.tpfa_offset_pressure(C.byref(_grid(grid, lay.pitch)), _ptr(p), _ptr(pref),
+                                     _ptr(dp), _stream(p.device)), lib)
     return dp
 
 
@@ -424,18 +453,18 @@ class Ensemble:
         prec = None
         for m, d in enumerate(self.members):
             g, p = d["grid"], d["p"]
-            n, pr, dt, dev, ld = _inputs(g, d["kx"], p, d.get("seal"), d.get("pref"))
+            n, pr, dt, dev, lay = _inputs(g, d["kx"], p, d.get("seal"), d.get("pref"))
             if prec is None:
                 prec, self.device = pr, dev
             elif pr != prec or dev != self.device:
                 raise ValueError("all ensemble members need the same precision and device")
-            r = _empty(p, g, ld) if (
+            r = _empty(p, lay) if (
                 want_r or self.mode == L.TPFA_BATCH_RESIDUAL) else None
-            J = _empty(p, g, ld, (7,)) if (
+            J = _empty(p, lay, (7,)) if (
                 self.mode == L.TPFA_BATCH_JACOBIAN) else None
             self.r.append(r)
             self.J.append(J)
-            arr[m] = L.Model(_grid(g, ld), _fluid(d["fluid"]),
+            arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
                              _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                              L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
                              _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"))

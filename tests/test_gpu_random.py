@@ -1,0 +1,78 @@
+"""Randomised parity (hypothesis, derandomised so every run draws the same
+cases): small grids of any shape, seal density, precision, tile shape, z chunk,
+XCD band order and row pitch. The full-grid Jacobian launch meets the oracle
+bound (R16 metric, either one-sided derivative at upwind ties); a launch over a
+random row range on NaN-filled outputs equals it bitwise on the owned rows and
+leaves every other row and all padding untouched."""
+import numpy as np
+import pytest
+import torch
+from hypothesis import given, settings, strategies as st
+
+import geomodel
+from helpers import compare_full
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32, TAU32 = 1e-12, 1e-5, 0.05
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def pad(a, ldx):
+    t = dev(a)
+    fill = 255 if t.dtype == torch.uint8 else float("nan")
+    buf = torch.full(tuple(t.shape[:-1]) + (ldx,), fill, dtype=t.dtype, device=t.device)
+    buf[..., :t.shape[-1]].copy_(t)
+    return buf[..., :t.shape[-1]]
+
+
+@st.composite
+def cases(draw):
+    nx, ny, nz = draw(st.integers(1, 70)), draw(st.integers(1, 20)), draw(st.integers(1, 12))
+    y0 = draw(st.integers(0, ny - 1))
+    y1 = draw(st.integers(y0 + 1, ny))
+    return dict(shape=(nx, ny, nz), seed=draw(st.integers(0, 10 ** 6)),
+                seal=draw(st.sampled_from([0.0, 0.05, 0.3])),
+                prec=draw(st.sampled_from(["fp64", "fp32"])),
+                tile=draw(st.sampled_from([None] + list(range(10)))),
+                kz=draw(st.sampled_from([None, 1, 3, 8])), remap=draw(st.booleans()),
+                extra=draw(st.sampled_from([0, 1, 13])), rows=(y0, y1))
+
+
+@settings(derandomize=True, max_examples=60, deadline=None)
+@given(c=cases())
+def test_random_launches_against_oracle(gpu, orc, c):
+    print("case", c, flush=True)
+    geo = geomodel.random_small(c["seed"] % 9973, *c["shape"], sigma=1.5, seal_prob=c["seal"])
+    g = geo.grid
+    ldx = g.nx + c["extra"]
+    launch = dict(tile=c["tile"], kz_chunk=c["kz"], xcd_remap=c["remap"])
+    if c["prec"] == "fp64":
+        p = orc.pressure(geo)
+        k, pin, kw, tol, tau = geo.kx, p, {}, TOL64, 1e-9 * float(np.abs(p).max())
+        pw, kwide = p, geo.kx
+    else:
+        pref = orc.hydrostatic(g, geo.fluid, geo.p_top)
+        k, pin = geo.kx32(), geo.dp32()
+        kw, tol, tau = dict(pref=dev(pref)), TOL32, TAU32
+        pw, kwide = orc.widen_fp32(pin, pref), k.astype(np.float64)
+    kp, pp, sp = pad(k, ldx), pad(pin, ldx), pad(geo.seal, ldx)
+    r, J = gpu.jacobian(g, geo.fluid, kp, pp, seal=sp, ry=geo.ry, rz=geo.rz, **launch, **kw)
+    rb = torch.full(g.shape[:2] + (ldx,), float("nan"), dtype=r.dtype, device="cuda")
+    Jb = torch.full((7,) + g.shape[:2] + (ldx,), float("nan"), dtype=r.dtype, device="cuda")
+    y0, y1 = c["rows"]
+    gpu.jacobian(g, geo.fluid, kp, pp, seal=sp, ry=geo.ry, rz=geo.rz, rows=(y0, y1),
+                 r_out=rb[..., :g.nx], J_out=Jb[..., :g.nx], **launch, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(rb[:, y0:y1, :g.nx], r[:, y0:y1]) and torch.equal(Jb[..., y0:y1, :g.nx],
+                                                                     J[..., y0:y1, :])
+    assert torch.isnan(rb[:, :y0]).all() and torch.isnan(rb[:, y1:]).all()
+    assert torch.isnan(Jb[..., :y0, :]).all() and torch.isnan(Jb[..., y1:, :]).all()
+    assert torch.isnan(rb[..., g.nx:]).all() and torch.isnan(Jb[..., g.nx:]).all()
+    rep = compare_full(orc, g, geo.fluid, kwide, pw, r.double().cpu().numpy(),
+                       J.double().cpu().numpy(), tol=tol, tau=tau, ry=geo.ry, rz=geo.rz,
+                       seal=geo.seal)
+    assert rep["max_err"] <= tol, (c, rep)

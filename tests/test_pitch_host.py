@@ -55,13 +55,35 @@ def test_other_layouts_are_refused(make):
 
 def test_outputs_follow_the_layout_of_p():
     p = padded(ldx=16)
-    r = api._empty(p, G, 16)
-    J = api._empty(p, G, 16, (7,))
+    lay = api._Layout(G)
+    lay.take(p, "p")
+    r = api._empty(p, lay)
+    J = api._empty(p, lay, (7,))
     assert tuple(r.shape) == (G.nz, G.ny, G.nx) and api._pitch(r, "r", G) == 16
     assert tuple(J.shape) == (7, G.nz, G.ny, G.nx) and api._pitch(J, "J", G) == 16
     q = torch.zeros(G.nz * G.ny * G.nx)
-    assert api._empty(q, G, G.nx).shape == q.shape
-    assert api._empty(q, G, G.nx, dtype=torch.float32).dtype == torch.float32
+    lay = api._Layout(G)
+    lay.take(q, "q")
+    assert lay.pitch == G.nx and api._empty(q, lay).shape == q.shape
+    assert api._empty(q, lay, dtype=torch.float32).dtype == torch.float32
+
+
+def test_single_rows_fit_any_pitch():
+    """A one-row grid's arrays fix no pitch: the call takes it from the
+    arrays that do (here J's planes), or nx when none does."""
+    g = geomodel.Grid(5, 1, 1)
+    p = torch.zeros(1, 1, 8)[..., :5]
+    J = torch.zeros(7, 1, 1, 8)[..., :5]
+    assert api._pitch(p, "p", g) is None and api._pitch(J, "J", g) == 8
+    lay = api._Layout(g)
+    lay.take(p, "p")
+    assert lay.pitch == 5
+    lay.take(J, "J")
+    lay.take(torch.zeros(1, 1, 5), "r")
+    assert lay.pitch == 8
+    with pytest.raises(ValueError, match="row pitch"):
+        lay.take(torch.zeros(3, 1, 1, 6)[..., :5], "gm")
+    assert api._empty(p, lay, (7,)).stride()[0] == 8
 
 
 
@@ -119,9 +141,12 @@ def test_accepted_views_have_the_kernel_layout(v):
         ld = api._pitch(t, "t", g)
     except ValueError:
         return
-    assert ld >= nx
     t4 = t if lead else t.unsqueeze(0)
     q, k, j, i = torch.meshgrid(*(torch.arange(n) for n in t4.shape), indexing="ij")
+    if ld is None:  # a single row: every pitch addresses it as off + i
+        assert t4.shape[0] * nz * ny == 1 or t.numel() <= nx
+        ld = nx
+    assert ld >= nx
     want = off + q * ld * ny * nz + i + ld * (j + ny * k)
     assert torch.equal(t4.to(torch.int64), want.to(torch.int64))
 
