@@ -76,3 +76,44 @@ def test_random_launches_against_oracle(gpu, orc, c):
                        J.double().cpu().numpy(), tol=tol, tau=tau, ry=geo.ry, rz=geo.rz,
                        seal=geo.seal)
     assert rep["max_err"] <= tol, (c, rep)
+
+
+@settings(derandomize=True, max_examples=40, deadline=None)
+@given(c=cases(), op=st.sampled_from(["vjp", "residual10"]))
+def test_random_vjp_and_10_flux_against_oracle(gpu, orc, c, op):
+    """The vector-Jacobian product (grad p, grad ln k) and the 10-flux residual
+    under random launches and row pitches, against the oracle."""
+    from helpers import compare_res10, compare_vjp
+    print("case", op, c, flush=True)
+    geo = geomodel.random_small(c["seed"] % 9973, *c["shape"], sigma=1.5, seal_prob=c["seal"])
+    g = geo.grid
+    ldx = g.nx + c["extra"]
+    launch = dict(tile=c["tile"], kz_chunk=c["kz"], xcd_remap=c["remap"])
+    rng = np.random.default_rng(c["seed"])
+    w = rng.standard_normal(g.shape)
+    tne, tse = geomodel.diagonal_t(g, c["seed"] % 9973 + 1)
+    if c["prec"] == "fp64":
+        p = orc.pressure(geo)
+        k, pin, kw, tol, tau = geo.kx, p, {}, TOL64, 1e-9 * float(np.abs(p).max())
+        pw, kwide, wq, tq = p, geo.kx, w, (tne, tse)
+    else:
+        pref = orc.hydrostatic(g, geo.fluid, geo.p_top)
+        k, pin = geo.kx32(), geo.dp32()
+        kw, tol, tau = dict(pref=dev(pref)), TOL32, TAU32
+        pw, kwide = orc.widen_fp32(pin, pref), k.astype(np.float64)
+        wq, tq = w.astype(np.float32), (tne.astype(np.float32), tse.astype(np.float32))
+    args = (g, geo.fluid, pad(k, ldx), pad(pin, ldx))
+    kw.update(seal=pad(geo.seal, ldx), ry=geo.ry, rz=geo.rz, **launch)
+    if op == "vjp":
+        gp, gm = gpu.residual_vjp(*args, pad(wq, ldx), **kw)
+        torch.cuda.synchronize()
+        rep = compare_vjp(orc, g, geo.fluid, kwide, pw, np.asarray(wq, np.float64),
+                          gp.double().cpu().numpy(), gm.double().cpu().numpy(), tol=tol, tau=tau,
+                          ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    else:
+        r = gpu.residual10(*args, pad(tq[0], ldx), pad(tq[1], ldx), **kw)
+        torch.cuda.synchronize()
+        rep = compare_res10(orc, g, geo.fluid, kwide, pw, tq[0].astype(np.float64),
+                            tq[1].astype(np.float64), r.double().cpu().numpy(), tol=tol, tau=tau,
+                            ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    assert rep["max_err"] <= tol, (op, c, rep)
