@@ -117,3 +117,75 @@ def test_random_vjp_and_10_flux_against_oracle(gpu, orc, c, op):
                             tq[1].astype(np.float64), r.double().cpu().numpy(), tol=tol, tau=tau,
                             ry=geo.ry, rz=geo.rz, seal=geo.seal)
     assert rep["max_err"] <= tol, (op, c, rep)
+
+
+def _check_rJ(r, J, ref, tol):
+    from helpers import rel_err
+    assert rel_err(r, ref["r"], ref["scale"][0]).max() <= tol
+    assert rel_err(J[0], ref["J"][0], ref["scale"][1]).max() <= tol
+    for n in range(1, 7):
+        assert rel_err(J[n], ref["J"][n], np.abs(ref["J"][n])).max() <= tol, n
+
+
+@settings(derandomize=True, max_examples=40, deadline=None)
+@given(c=cases(), op=st.sampled_from(["k3", "trans", "be"]))
+def test_random_other_forms_against_oracle(gpu, orc, c, op):
+    """Per-direction permeability and face-transmissibility Jacobians, and the
+    backward-Euler Jacobian with J v, under random launches and row pitches."""
+    from helpers import apply_J, compare_full
+    print("case", op, c, flush=True)
+    s = c["seed"] % 9973
+    geo = geomodel.random_small(s, *c["shape"], sigma=1.5, seal_prob=c["seal"])
+    g = geo.grid
+    ldx = g.nx + c["extra"]
+    launch = dict(tile=c["tile"], kz_chunk=c["kz"], xcd_remap=c["remap"])
+    fp64 = c["prec"] == "fp64"
+    cast = (lambda a: a) if fp64 else (lambda a: np.asarray(a, np.float32))  # noqa: E731
+    wide = lambda a: np.asarray(a, np.float64)  # noqa: E731
+    if fp64:
+        p = orc.pressure(geo)
+        pin, pw, kw, tol, tau = p, p, {}, TOL64, 1e-9 * float(np.abs(p).max())
+    else:
+        pref = orc.hydrostatic(g, geo.fluid, geo.p_top)
+        pin = geo.dp32()
+        pw, kw, tol, tau = orc.widen_fp32(pin, pref), dict(pref=dev(pref)), TOL32, TAU32
+    kw.update(launch)
+    P = lambda a: pad(a, ldx)  # noqa: E731
+    if op == "k3":
+        k3 = [cast(a) for a in geomodel.k3_fields(geo.kx, s + 1)]
+        r, J = gpu.jacobian(g, geo.fluid, P(k3[0]), P(pin), seal=P(geo.seal), ky=P(k3[1]),
+                            kz=P(k3[2]), **kw)
+        torch.cuda.synchronize()
+        rep = compare_full(orc, g, geo.fluid, wide(k3[0]), pw, r.double().cpu().numpy(),
+                           J.double().cpu().numpy(), tol=tol, tau=tau, ry=1.0, rz=1.0,
+                           seal=geo.seal, ky=wide(k3[1]), kz=wide(k3[2]))
+        assert rep["max_err"] <= tol, (op, c, rep)
+    elif op == "trans":
+        t = geomodel.diagonal_t(g, s + 2, zero_prob=0.05) + geomodel.diagonal_t(g, s + 3)[:1]
+        tq = [cast(a) for a in t]
+        r, J = gpu.jacobian(g, geo.fluid, None, P(pin), trans=tuple(P(a) for a in tq), **kw)
+        torch.cuda.synchronize()
+        ref = orc.evaluate_general(g, geo.fluid, pw, trans=tuple(wide(a) for a in tq),
+                                   want=("r", "J", "scale"))
+        _check_rJ(r.double().cpu().numpy(), J.double().cpu().numpy(), ref, tol)
+    else:
+        be = geomodel.be_fields(g, s + 4)
+        if fp64:
+            pn, pnw = p - be["dp_step"], p - be["dp_step"]
+        else:
+            pn = (geo.noise[0] - be["dp_step"]).astype(np.float32)
+            pnw = orc.widen_fp32(pn, pref)
+        phi, v = cast(be["phi"]), cast(be["v"])
+        acc = dict(phi=P(phi), p_prev=P(pn), dt=be["dt"], cr=be["cr"])
+        kx = cast(geo.kx)
+        args = (g, geo.fluid, P(kx), P(pin))
+        r, J = gpu.jacobian_be(*args, acc, seal=P(geo.seal), ry=geo.ry, rz=geo.rz, **kw)
+        jv, _ = gpu.jvp(*args, P(v), accum=acc, seal=P(geo.seal), ry=geo.ry, rz=geo.rz, **kw)
+        torch.cuda.synchronize()
+        ref = orc.evaluate_be(g, geo.fluid, wide(kx), pw, wide(phi), pnw, be["dt"], be["cr"],
+                              ry=geo.ry, rz=geo.rz, seal=geo.seal, v=wide(v),
+                              want=("r", "J", "scale", "jv"))
+        _check_rJ(r.double().cpu().numpy(), J.double().cpu().numpy(), ref, tol)
+        scale = apply_J(np.abs(ref["J"]), np.abs(wide(v)))
+        err = np.abs(jv.double().cpu().numpy() - ref["jv"])
+        assert np.all(err <= tol * scale + 1e-300), (op, c)
