@@ -3,7 +3,11 @@ cases): small grids of any shape, seal density, precision, tile shape, z chunk,
 XCD band order and row pitch. The full-grid Jacobian launch meets the oracle
 bound (R16 metric, either one-sided derivative at upwind ties); a launch over a
 random row range on NaN-filled outputs equals it bitwise on the owned rows and
-leaves every other row and all padding untouched."""
+leaves every other row and all padding untouched. The same random launches
+drive the VJP, the 10-flux residual, the per-direction and transmissibility
+forms and the backward-Euler J and J v against the oracle, and random uneven
+ensembles (either schedule, graph or direct launch) against the members'
+single-grid launches, bitwise."""
 import numpy as np
 import pytest
 import torch
@@ -189,3 +193,61 @@ def test_random_other_forms_against_oracle(gpu, orc, c, op):
         scale = apply_J(np.abs(ref["J"]), np.abs(wide(v)))
         err = np.abs(jv.double().cpu().numpy() - ref["jv"])
         assert np.all(err <= tol * scale + 1e-300), (op, c)
+
+
+@st.composite
+def ensembles(draw):
+    n = draw(st.integers(1, 12))
+    members = []
+    for _ in range(n):
+        members.append(dict(shape=(draw(st.integers(1, 80)), draw(st.integers(1, 24)),
+                                   draw(st.integers(1, 20))),
+                            seed=draw(st.integers(0, 9999)), tile=draw(st.sampled_from([0, 1, 2])),
+                            kz=draw(st.sampled_from([1, 4, 16, 64])), extra=draw(st.sampled_from([0, 5]))))
+    return dict(members=members, prec=draw(st.sampled_from(["fp64", "fp32"])),
+                mode=draw(st.sampled_from(["jacobian", "residual"])),
+                schedule=draw(st.sampled_from(["persistent", "grouped"])),
+                graph=draw(st.booleans()))
+
+
+@settings(derandomize=True, max_examples=25, deadline=None)
+@given(e=ensembles())
+def test_random_ensembles_equal_single_launches(gpu, orc, e):
+    """Uneven ensembles of 1..12 members (tile, z chunk and row pitch per
+    member), either schedule, graph replay or direct launch, repeated: every
+    member's outputs bitwise equal to its own single-grid launch."""
+    print("ensemble", e, flush=True)
+    members, singles = [], []
+    for m in e["members"]:
+        geo = geomodel.random_small(m["seed"], *m["shape"], sigma=1.2, seal_prob=0.05)
+        g = geo.grid
+        ldx = g.nx + m["extra"]
+        if e["prec"] == "fp64":
+            k, pin, kw = geo.kx, orc.pressure(geo), {}
+        else:
+            k, pin = geo.kx32(), geo.dp32()
+            kw = dict(pref=dev(orc.hydrostatic(g, geo.fluid, geo.p_top)))
+        d = dict(grid=g, fluid=geo.fluid, kx=pad(k, ldx), p=pad(pin, ldx), seal=pad(geo.seal, ldx),
+                 ry=geo.ry, rz=geo.rz, tile=m["tile"], kz_chunk=m["kz"], **kw)
+        members.append(d)
+        launch = dict(seal=dev(geo.seal), ry=geo.ry, rz=geo.rz, tile=m["tile"], kz_chunk=m["kz"], **kw)
+        if e["mode"] == "jacobian":
+            singles.append(gpu.jacobian(g, geo.fluid, dev(k), dev(pin), **launch))
+        else:
+            singles.append((gpu.residual(g, geo.fluid, dev(k), dev(pin), **launch), None))
+    ens = gpu.Ensemble(members, mode=e["mode"])
+    ens.set_schedule(e["schedule"])
+    try:
+        for rep in range(2):
+            for q in range(len(members)):
+                ens.r[q].fill_(float("nan"))
+                if ens.J[q] is not None:
+                    ens.J[q].fill_(float("nan"))
+            ens.run(graph=e["graph"])
+            torch.cuda.synchronize()
+            for q, (r, J) in enumerate(singles):
+                assert torch.equal(ens.r[q], r), (rep, q)
+                if J is not None:
+                    assert torch.equal(ens.J[q], J), (rep, q)
+    finally:
+        ens.close()
