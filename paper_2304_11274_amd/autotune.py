@@ -114,21 +114,35 @@ def ensemble_tile(nx: int, ny: int, tiles: Sequence[int] = (0, 1)) -> int:
     return best[0]
 
 
+def balanced_kz(nz: int, most: int) -> int:
+    """z chunk of a column of nz planes cut into the fewest chunks of at most
+    ``most`` planes, of near-equal length (34 planes with most = 32: two
+    chunks of 17 instead of 32 + 2; with most = 48: one of 34)."""
+    chunks = -(-nz // most)
+    return -(-nz // chunks)
+
+
 def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64),
                   tiles: Sequence[int] = TILE_IDS_256,
                   schedules: Sequence[str] = ("persistent", "grouped"), reps: int = 5,
-                  mode: str = "jacobian") -> Tuple[Tuple[str, int, str], Dict[str, float]]:
+                  mode: str = "jacobian") -> Tuple[Tuple[str, int | str, str], Dict[str, float]]:
     """Chooses the launch shape of one ensemble launch by timing it: every
     uniform tile and a mixed assignment (per-model tile by lane utilisation),
-    each with every z-chunk and every schedule. Sets ``tile`` and ``kz_chunk``
-    on every member; returns ((assignment, kz, schedule), {label: ms})."""
+    each with every uniform z chunk, per-model balanced chunks ('bal32',
+    'bal48': see balanced_kz) and every schedule. Sets ``tile`` and
+    ``kz_chunk`` on every member; returns ((assignment, kz, schedule),
+    {label: ms})."""
     mixed = [ensemble_tile(m["grid"].nx, m["grid"].ny) for m in members]
     cands = [(f"tile{t}", [t] * len(members)) for t in tiles] + [("mixed", mixed)]
+    # z chunks: uniform lengths, and per model balanced chunks of at most 32 or 48 planes
+    zs = list(kz) + ["bal32", "bal48"]
     times, best = {}, None
     for label, assign in cands:
-        for z in kz:
+        for z in zs:
             for m, t in zip(members, assign):
-                m["tile"], m["kz_chunk"] = t, z
+                m["tile"] = t
+                m["kz_chunk"] = (balanced_kz(m["grid"].nz, int(z[3:])) if isinstance(z, str)
+                                 else z)
             ens = api.Ensemble(members, mode=mode)
             for sch in schedules:
                 ens.set_schedule(sch)
@@ -140,5 +154,6 @@ def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64),
             del ens
     _, label, assign, z, sch = best
     for m, t in zip(members, assign):
-        m["tile"], m["kz_chunk"] = t, z
+        m["tile"] = t
+        m["kz_chunk"] = balanced_kz(m["grid"].nz, int(z[3:])) if isinstance(z, str) else z
     return (label, z, sch), times

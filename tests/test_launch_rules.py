@@ -126,3 +126,15 @@ def test_errors():
     g.ldx = 100
     assert lib.tpfa_resolve_launch(C.byref(g), 1, L.TPFA_FP64, C.byref(rock), None,
                                    C.byref(out)) == L.TPFA_ERR_SHAPE
+
+
+@pytest.mark.parametrize("nz,most,want", [(34, 32, 17), (34, 48, 34), (128, 48, 43), (64, 32, 32),
+                                          (1, 32, 1), (65, 32, 22), (96, 48, 48)])
+def test_balanced_z_chunks(nz, most, want):
+    """Per-model z chunks of the ensemble autotuner: the fewest chunks of at
+    most `most` planes, of near-equal length, covering the column."""
+    from paper_2304_11274_amd import autotune
+    kz = autotune.balanced_kz(nz, most)
+    assert kz == want and kz <= most
+    chunks = -(-nz // kz)
+    assert chunks == -(-nz // most) and (chunks - 1) * kz < nz <= chunks * kz
