@@ -75,7 +75,7 @@ def _load():
         lib.oracle_hydrostatic.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid),
                                            C.c_double, vp]
         lib.oracle_residual10.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp, C.c_double,
-                                          C.c_double, vp, vp, vp, vp, vp, vp]
+                                          C.c_double, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_residual10_cs.argtypes = [C.POINTER(_Grid), C.POINTER(_Fluid), vp,
                                              C.c_double, C.c_double, vp, vp, vp, vp, vp,
                                              C.c_double, vp]
@@ -231,18 +231,22 @@ def evaluate_cs(grid, fluid, kx, p, *, ry=1.0, rz=1.0, seal=None, vp=None, vm=No
     return re, im / h
 
 
-def residual10(grid, fluid, kx, p, tne, tse, *, ry=1.0, rz=1.0, seal=None):
+def residual10(grid, fluid, kx, p, tne, tse, *, ry=1.0, rz=1.0, seal=None, force=None):
     """Residual of the 10-flux stencil (six TPFA faces plus the four in-plane
-    diagonal faces with given transmissibilities) and its flux scale sum |F|."""
+    diagonal faces with given transmissibilities) and its flux scale sum |F|.
+    ``force`` is an int8 [5, ...] upwind override per face (+1 lower cell, -1
+    upper cell, 0 rule): x, y, z faces by their lower cell, then the faces
+    (i,j)-(i+1,j+1) and (i,j)-(i+1,j-1) by their (i, j) end."""
     shape = (grid.nz, grid.ny, grid.nx)
     kx, p = _arr(kx, np.float64, shape), _arr(p, np.float64, shape)
     tne, tse = _arr(tne, np.float64, shape), _arr(tse, np.float64, shape)
     seal = _arr(seal, np.uint8, shape)
+    force = _arr(force, np.int8, (5,) + shape)
     r = np.empty(shape)
     scale = np.empty((2,) + shape)
     rc = _load().oracle_residual10(C.byref(_g(grid)), C.byref(_f(fluid)), _ptr(kx), float(ry),
-                                   float(rz), _ptr(seal), _ptr(tne), _ptr(tse), _ptr(p), _ptr(r),
-                                   _ptr(scale))
+                                   float(rz), _ptr(seal), _ptr(tne), _ptr(tse), _ptr(p),
+                                   _ptr(force), _ptr(r), _ptr(scale))
     if rc != 0:
         raise ValueError("oracle_residual10 rejected its arguments")
     return r, scale[0]

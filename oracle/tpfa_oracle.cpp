@@ -92,6 +92,9 @@ struct Problem {
   double ry, rz;
   const uint8_t* seal;         // NULL or bit a set: face towards +a neighbour closed
   const int8_t* force;         // NULL or [3][N]: +1 / -1 forces the lower / upper cell upwind
+  const int8_t* force_diag = nullptr;  // NULL or [2][N]: the same for the in-plane diagonal
+                                       //   faces (i,j)-(i+1,j+1) and (i,j)-(i+1,j-1), indexed
+                                       //   by the face's left (i) end
   const S* tne = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j+1) of each cell
   const S* tse = nullptr;      // NULL or the transmissibility of the face (i,j)-(i+1,j-1) of each cell
   const S* tx = nullptr;       // NULL, or the transmissibilities of the faces towards +x, +y, +z
@@ -214,7 +217,13 @@ FluxKL<S> flux(const Problem<S>& pb, int64_t K, int64_t L, int axis, int side) {
 
   // single-point upwinding (Eq. 4); a tie goes to the lower index
   bool upK;
-  const int8_t forced = (pb.force && axis < 3) ? pb.force[(int64_t)force_axis * pb.ncell() + lo] : 0;
+  int8_t forced = (pb.force && axis < 3) ? pb.force[(int64_t)force_axis * pb.ncell() + lo] : 0;
+  if (axis == 3 && pb.force_diag) {
+    const int64_t left = side > 0 ? K : L;
+    const int64_t right = side > 0 ? L : K;
+    const int d = (right - left == 1 + g.nx) ? 0 : 1;
+    forced = pb.force_diag[(int64_t)d * pb.ncell() + left];
+  }
   if (forced != 0) {
     upK = (forced > 0) == (K == lo);
   } else {
@@ -649,12 +658,17 @@ int oracle_eval_be_cs(const oracle_grid* g, const oracle_fluid* f, const double*
 // Residual of the 10-flux stencil: the six TPFA faces plus the four in-plane
 // diagonal faces, whose transmissibilities are given per cell (tne: face with
 // (i+1, j+1), tse: face with (i+1, j-1); entries without that neighbour are
-// ignored). Optionally the flux scale sum |F| per cell.
+// ignored). Optionally the flux scale sum |F| per cell. `force` (NULL or
+// [5][N]) overrides the upwind choice of a face (+1 lower, -1 upper cell,
+// 0 the rule): planes 0-2 the x, y, z faces by their lower cell, planes 3-4
+// the diagonal faces (i,j)-(i+1,j+1) and (i,j)-(i+1,j-1) by their left end.
 int oracle_residual10(const oracle_grid* g, const oracle_fluid* f, const double* kx,
                       double ry, double rz, const uint8_t* seal, const double* tne,
-                      const double* tse, const double* p, double* r, double* scale) {
+                      const double* tse, const double* p, const int8_t* force, double* r,
+                      double* scale) {
   if (!valid(g, f, p, kx) || !tne || !tse || !r) return -1;
-  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, nullptr};
+  Problem<double> pb{g, f, p, kx, nullptr, nullptr, ry, rz, seal, force};
+  if (force) pb.force_diag = force + 3 * pb.ncell();
   pb.tne = tne;
   pb.tse = tse;
   Outputs o;

@@ -29,8 +29,8 @@ int oracle_eval_cs(const oracle_grid*, const oracle_fluid*, const double*, doubl
                    double*);
 int oracle_hydrostatic(const oracle_grid*, const oracle_fluid*, double, double*);
 int oracle_residual10(const oracle_grid*, const oracle_fluid*, const double*, double, double,
-                      const uint8_t*, const double*, const double*, const double*, double*,
-                      double*);
+                      const uint8_t*, const double*, const double*, const double*,
+                      const int8_t*, double*, double*);
 int oracle_eval_be(const oracle_grid*, const oracle_fluid*, const double*, double, double,
                    const uint8_t*, const double*, const double*, const double*, double, double,
                    const double*, double*, double*, double*, double*);
@@ -98,7 +98,13 @@ int main() {
                             nullptr, 1e-20, r.data(), ri.data()) != 0;
     fails += oracle_hydrostatic(&g, &fl, 1e7, pref.data()) != 0;
     fails += oracle_residual10(&g, &fl, k.data(), 1.0, 0.1, seal.data(), t.data(),
-                               t.data() + N, p.data(), r.data(), sc.data()) != 0;
+                               t.data() + N, p.data(), nullptr, r.data(), sc.data()) != 0;
+    {
+      std::vector<int8_t> f5(5 * N);
+      for (int64_t c = 0; c < 5 * N; ++c) f5[c] = (int8_t)(c % 3 - 1);
+      fails += oracle_residual10(&g, &fl, k.data(), 1.0, 0.1, seal.data(), t.data(),
+                                 t.data() + N, p.data(), f5.data(), r.data(), sc.data()) != 0;
+    }
     fails += oracle_eval_be(&g, &fl, k.data(), 1.0, 0.1, seal.data(), p.data(), phi.data(),
                             pn.data(), 3600.0, 5e-10, v.data(), r.data(), J.data(), jv.data(),
                             sc.data()) != 0;
