@@ -111,8 +111,13 @@ typedef struct {
 } tpfa_rock_t;
 
 /* State: TPFA_FP64 -> p is absolute pressure (double, Pa), pref ignored.
-   TPFA_FP32 -> p is the float offset dp and pref (double[nz], device) is
-   required. */
+   TPFA_FP32 -> p is the float offset dp and pref (double[nz], device, finite)
+   is required; the pressure of a cell in plane k is pref[k] + dp. The kernels
+   split each density into its plane's reference density
+   rho0 exp(cf (pref[k] - p0)), evaluated in FP64, and a float deviation, so
+   the potential difference of a z face carries no float rounding of rho g dz
+   whatever pref is (Sec. 3, Eqs. 3b and 5); a hydrostatic pref
+   (tpfa_hydrostatic) keeps the offsets, and their rounding, small. */
 typedef struct {
   const void *p;
   const double *pref;
@@ -121,7 +126,9 @@ typedef struct {
 /* Optional launch shape (pass NULL for the defaults): tile = id from
    tpfa_tile_shape(), or -1 for the library's default launch; kz_chunk = z
    planes marched by one workgroup (0 = default, which a single-grid call
-   shortens on small grids until the launch fills the GPU); flags bit 0 selects the
+   shortens on small grids until the launch fills the GPU; in TPFA_FP32 at most
+   128, larger values run as 128, since those kernels keep two constants per
+   plane of their chunk on chip); flags bit 0 selects the
    XCD-aware workgroup order (the tiles of each z chunk are split into 8
    contiguous bands of tile rows, one per XCD). With tile = -1 (or NULL) the
    library also sets that bit where it measured faster; with an explicit tile
@@ -248,12 +255,28 @@ int tpfa_hydrostatic(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid, double 
 int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double *pref,
                          float *dp, void *stream);
 
+/* ---- Bandwidth probe ---- */
+
+/* The memory traffic of the Jacobian entry points without their arithmetic,
+   to measure the ceiling the device reaches on that access pattern (the
+   streaming-copy measurement beside the roofline, Sec. 7's Roofline
+   analysis): for c < n, out[q * n + c] = p[c] + (q + seal[c]) * k[c],
+   q = 0..7, with p, k and out of the precision's type (double or float;
+   8 + 8 + 1 bytes read and 64 written per cell in FP64, 4 + 4 + 1 and 32 in
+   FP32), coalesced, non-temporal stores. Device pointers owned by the caller;
+   out holds 8 n elements. Errors: TPFA_ERR_SHAPE (n <= 0 or 8 n overflows),
+   TPFA_ERR_PARAM (precision), TPFA_ERR_NULL, TPFA_ERR_HIP. */
+int tpfa_stream_probe(int64_t n, tpfa_precision_t prec, const void *p, const void *k,
+                      const uint8_t *seal, void *out, void *stream);
+
 /* ---- Batched ensemble: many independent grids in one persistent launch ---- */
 
 /* One member of an ensemble. All pointers are device pointers that must stay
    valid while the batch is used; r may be NULL; J is required for
-   TPFA_BATCH_JACOBIAN and ignored for TPFA_BATCH_RESIDUAL. launch.tile must be
-   one of the 256-thread tiles (tpfa_tile_shape reports the thread count). */
+   TPFA_BATCH_JACOBIAN and ignored for TPFA_BATCH_RESIDUAL. launch.tile is -1
+   (default: the single-grid default tile, or 64x4 where that default is a
+   512-thread tile) or one of the tiles the ensemble kernels hold: 0, 1, 2
+   (64x4, 32x8, 16x16); any other tile gives TPFA_ERR_TILE. */
 typedef struct {
   tpfa_grid_t grid;
   tpfa_fluid_t fluid;
@@ -277,7 +300,11 @@ typedef struct tpfa_batch tpfa_batch_t; /* opaque */
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
                       tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream);
 
-/* Replays the captured graph on `stream`: all models, one persistent launch. */
+/* Replays the captured graph on `stream`: all models, one persistent launch.
+   Runs of one batch share its work counters (the launch's last workgroup
+   resets them for the next run), so they must not overlap: never run one
+   batch on two streams at once without ordering the runs (e.g. with an
+   event). Different batches are independent. */
 int tpfa_batch_run(tpfa_batch_t *batch, void *stream);
 
 /* The same persistent kernel launched directly, without the graph. */
@@ -297,8 +324,9 @@ int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule);
 /* Number of work items and of persistent workgroups of a batch. */
 int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgroups);
 
-/* Frees the batch's device buffers and graph (synchronises its work first).
-   NULL is accepted. */
+/* Frees the batch's device buffers and graph after waiting for the batch's
+   last run (an event recorded by every run; other work on the device is not
+   waited for). NULL is accepted. */
 void tpfa_batch_destroy(tpfa_batch_t *batch);
 
 /* ---- Introspection ---- */

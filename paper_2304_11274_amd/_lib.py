@@ -101,6 +101,7 @@ SIGNATURES = {
     "tpfa_last_error": (C.c_char_p, []),
     "tpfa_version": (C.c_int, []),
     "tpfa_resolve_launch": (C.c_int, [P(Grid), C.c_int, C.c_int, P(Rock), P(Launch), P(Launch)]),
+    "tpfa_stream_probe": (C.c_int, [C.c_int64, C.c_int, vp, vp, vp, vp, vp]),
 }
 
 _lib = None

@@ -394,6 +394,29 @@ def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torc
     return dp
 
 
+def stream_probe(p: torch.Tensor, k: torch.Tensor, seal: torch.Tensor, out=None) -> torch.Tensor:
+    """Bandwidth probe with the Jacobian kernels' access pattern (tpfa_stream_probe):
+    out[q] = p + (q + seal) * k for q = 0..7, from contiguous p, k (float64 or
+    float32) and uint8 seal of equal size; returns out of shape (8,) + p.shape."""
+    for t, name in ((p, "p"), (k, "k"), (seal, "seal")):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous CUDA tensor")
+    if k.dtype != p.dtype or p.dtype not in (torch.float64, torch.float32):
+        raise ValueError("p and k must both be float64 or both float32")
+    if seal.dtype != torch.uint8 or not (p.numel() == k.numel() == seal.numel()):
+        raise ValueError("seal must be uint8 and p, k, seal of equal size")
+    n = p.numel()
+    if out is None:
+        out = torch.empty((8,) + tuple(p.shape), dtype=p.dtype, device=p.device)
+    elif not (out.is_contiguous() and out.dtype == p.dtype and out.numel() == 8 * n):
+        raise ValueError("out must be contiguous, of p's dtype, with 8 * p.numel() elements")
+    prec = L.TPFA_FP64 if p.dtype == torch.float64 else L.TPFA_FP32
+    lib = L.load()
+    L.check(lib.tpfa_stream_probe(n, prec, _ptr(p), _ptr(k), _ptr(seal), _ptr(out),
+                                  _stream(p.device)), lib)
+    return out
+
+
 _OPS = {"residual": L.TPFA_OP_RESIDUAL, "jacobian": L.TPFA_OP_JACOBIAN, "vjp": L.TPFA_OP_VJP,
         "residual10": L.TPFA_OP_RESIDUAL10, "residual_be": L.TPFA_OP_RESIDUAL_BE,
         "jacobian_be": L.TPFA_OP_JACOBIAN_BE, "jvp": L.TPFA_OP_JVP, "jvp_be": L.TPFA_OP_JVP_BE}

@@ -153,7 +153,16 @@ def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64),
             ens.close()
             del ens
     _, label, assign, z, sch = best
-    for m, t in zip(members, assign):
-        m["tile"] = t
-        m["kz_chunk"] = balanced_kz(m["grid"].nz, int(z[3:])) if isinstance(z, str) else z
+    apply_ensemble_launch(members, (label, z, sch))
     return (label, z, sch), times
+
+
+def apply_ensemble_launch(members: Sequence[dict], launch) -> None:
+    """Sets ``tile`` and ``kz_chunk`` of every member from a launch returned by
+    tune_ensemble: (assignment 'tile<t>' or 'mixed', z chunk or 'bal<n>',
+    schedule)."""
+    label, z = launch[0], launch[1]
+    for m in members:
+        nx, ny, nz = m["grid"].nx, m["grid"].ny, m["grid"].nz
+        m["tile"] = ensemble_tile(nx, ny) if label == "mixed" else int(label[4:])
+        m["kz_chunk"] = balanced_kz(nz, int(z[3:])) if isinstance(z, str) else int(z)

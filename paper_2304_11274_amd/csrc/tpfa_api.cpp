@@ -208,6 +208,7 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.cff = (float)f.cf;
   a.inv_muf = (float)a.inv_mu;
   a.hcf = (float)a.hc;
+  a.hgf = (float)(0.5 * a.G);
   a.p = st.p;
   a.pref = st.pref;
   a.kx = rk.kx;
@@ -275,6 +276,8 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   else
     kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form))
               : default_kz(mode, prec, form);
+  // the FP32 kernels hold per-plane constants of their chunk in LDS
+  if (prec == TPFA_FP32) kz = std::min(kz, tpfa::kMaxChunk32);
   flags = launch ? launch->flags : 0;
   if (dflt) flags |= default_flags(mode, prec, form, g.nx * (y1 - y0) * g.nz);
   return TPFA_OK;
@@ -536,6 +539,19 @@ int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double 
   return ok();
 }
 
+int tpfa_stream_probe(int64_t n, tpfa_precision_t prec, const void *p, const void *k,
+                      const uint8_t *seal, void *out, void *stream) {
+  if (n <= 0) return fail(TPFA_ERR_SHAPE, "n must be positive");
+  if (prec != TPFA_FP64 && prec != TPFA_FP32) return fail(TPFA_ERR_PARAM, "unknown precision");
+  if (!p || !k || !seal || !out) return fail(TPFA_ERR_NULL, "p, k, seal and out are required");
+  if (n > std::numeric_limits<int64_t>::max() / 8 / 8)
+    return fail(TPFA_ERR_SHAPE, "8 * n elements overflow");
+  const hipError_t e =
+      tpfa::launch_stream_probe(prec, n, p, k, seal, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "probe launch");
+  return ok();
+}
+
 // ---------------------------------------------------------------------------
 // Batched ensemble
 // ---------------------------------------------------------------------------
@@ -552,6 +568,8 @@ struct tpfa_batch {
   int schedule = TPFA_SCHEDULE_PERSISTENT;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every run: destroy waits for the last one
+  bool ran = false;
 };
 
 static void batch_free(tpfa_batch *b) {
@@ -561,6 +579,7 @@ static void batch_free(tpfa_batch *b) {
   if (b->d_models) (void)hipFree(b->d_models);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->done) (void)hipEventDestroy(b->done);
   delete b;
 }
 
@@ -592,6 +611,38 @@ static hipError_t batch_capture(tpfa_batch *b) {
   return e;
 }
 
+// Kernel arguments of ensemble member m (every check of an ensemble member;
+// no allocation unless an error message is built).
+static int batch_model(const tpfa_model_t &md, int m, tpfa_precision_t prec,
+                       tpfa_batch_mode_t mode, tpfa::Args &a) {
+  int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
+  if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
+  if (md.rock.tx || md.rock.ky)
+    return fail(TPFA_ERR_UNSUPPORTED, "model " + std::to_string(m) +
+                                          ": the batch needs the permeability form with "
+                                          "ry, rz ratios");
+  if (mode == TPFA_BATCH_JACOBIAN && !md.J)
+    return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": J is NULL");
+  if (mode == TPFA_BATCH_RESIDUAL && !md.r)
+    return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": r is NULL");
+  int tile, kz, flags;
+  int64_t y0, y1;
+  resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
+                                                      : tpfa::MODE_RESIDUAL,
+                 prec, 0, &md.launch, tile, kz, flags, y0, y1, false);
+  // the ensemble kernels hold the tile bodies 0, 1, 2 (64x4, 32x8, 16x16);
+  // a default tile outside them (64x8 or 128x4) becomes 64x4
+  if (md.launch.tile < 0 && tile > 2) tile = 0;
+  if (tile > 2)
+    return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
+                                   ": batched tiles must be tile 0, 1 or 2 (64x4, 32x8, "
+                                   "16x16)");
+  tpfa::make_args(a, md.grid, md.fluid, md.rock, md.state, tile, kz, flags, y0, y1);
+  a.r = md.r;
+  a.J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
+  return TPFA_OK;
+}
+
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
                       tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream) {
   try {
@@ -604,29 +655,8 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     std::vector<tpfa::Args> args(n_models);
     std::vector<tpfa::WorkItem> wl;
     for (int m = 0; m < n_models; ++m) {
-      const tpfa_model_t &md = models[m];
-      int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
-      if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
-      if (md.rock.tx || md.rock.ky)
-        return fail(TPFA_ERR_UNSUPPORTED, "model " + std::to_string(m) +
-                                              ": the batch needs the permeability form with "
-                                              "ry, rz ratios");
-      if (mode == TPFA_BATCH_JACOBIAN && !md.J)
-        return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": J is NULL");
-      if (mode == TPFA_BATCH_RESIDUAL && !md.r)
-        return fail(TPFA_ERR_NULL, "model " + std::to_string(m) + ": r is NULL");
-      int tile, kz, flags;
-      int64_t y0, y1;
-      resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
-                                                          : tpfa::MODE_RESIDUAL,
-                     prec, 0, &md.launch, tile, kz, flags, y0, y1, false);
-      if (md.launch.tile < 0) tile = tile == 3 ? 0 : tile;  // the 256-thread counterpart
-      if (tpfa::kTiles[tile].threads != 256)
-        return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
-                                       ": batched tiles must be 256-thread tiles");
-      tpfa::make_args(args[m], md.grid, md.fluid, md.rock, md.state, tile, kz, flags, y0, y1);
-      args[m].r = md.r;
-      args[m].J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
+      int rc = batch_model(models[m], m, prec, mode, args[m]);
+      if (rc) return rc;
       // natural order: a tile's x neighbours follow it, so they run together
       // and share their halo cells and the output lines at their common edge
       // in L2
@@ -653,6 +683,11 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
     b->n_wg = (int)std::min<int64_t>(wg, b->n_items);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
+    if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
+      b->done = nullptr;
+      batch_free(b);
+      return hip_fail(e, "batch event");
+    }
     if ((e = hipMalloc(&b->d_models, sizeof(tpfa::Args) * args.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_items, sizeof(tpfa::WorkItem) * wl.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_counter, tpfa::kCounterWords * sizeof(unsigned int))) != hipSuccess) {
@@ -683,18 +718,28 @@ int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t
   }
 }
 
+// Marks the end of a run on `st`, for tpfa_batch_destroy.
+static int batch_mark(tpfa_batch *b, hipStream_t st) {
+  const hipError_t e = hipEventRecord(b->done, st);
+  if (e != hipSuccess) return hip_fail(e, "event record");
+  b->ran = true;
+  return ok();
+}
+
 int tpfa_batch_run(tpfa_batch_t *batch, void *stream) {
   if (!batch || !batch->exec) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
-  const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = hipGraphLaunch(batch->exec, st);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
-  return ok();
+  return batch_mark(batch, st);
 }
 
 int tpfa_batch_run_eager(tpfa_batch_t *batch, void *stream) {
   if (!batch || !batch->d_items) return fail(TPFA_ERR_NULL, "batch is NULL or empty");
-  const hipError_t e = batch_launch(batch, static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = batch_launch(batch, st);
   if (e != hipSuccess) return hip_fail(e, "ensemble launch");
-  return ok();
+  return batch_mark(batch, st);
 }
 
 int tpfa_batch_set_schedule(tpfa_batch_t *batch, int schedule) {
@@ -719,7 +764,9 @@ int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgrou
 
 void tpfa_batch_destroy(tpfa_batch_t *batch) {
   if (!batch) return;
-  (void)hipDeviceSynchronize();
+  // runs of one batch are ordered (never concurrent), so the last one's end
+  // is the end of all of them
+  if (batch->ran) (void)hipEventSynchronize(batch->done);
   batch_free(batch);
 }
 

@@ -52,6 +52,10 @@ constexpr bool has_accumulation(int m) {
 struct TileShape {
   int tx, ty, threads;
 };
+// FP32 kernels keep two per-plane constants of their z chunk in LDS (the
+// plane's reference density and the hydrostatic part of its z-face potential
+// difference), so their chunk is at most this many planes.
+constexpr int kMaxChunk32 = 128;
 constexpr int kNumTiles = 10;
 constexpr TileShape kTiles[kNumTiles] = {
     {64, 4, 256},  {32, 8, 256},  {16, 16, 256}, {64, 8, 512},  {128, 4, 512},
@@ -82,7 +86,8 @@ struct Args {
   double hc;             // 0.5 * cf * G
   // FP32 precision form
   float a2xf, a2yf, a2zf;
-  float rho0f, cff, inv_muf, hcf, pad2_;
+  float rho0f, cff, inv_muf, hcf;
+  float hgf;             // 0.5 * G, for the density deviations of a z face
   // accumulation term of the backward-Euler residual: V / dt and the rock
   // compressibility (FP64 and FP32 copies)
   double vdt, cr;
@@ -121,6 +126,8 @@ hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, doubl
                               double *pref, hipStream_t stream);
 hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
                          hipStream_t stream);
+hipError_t launch_stream_probe(tpfa_precision_t prec, int64_t n, const void *p, const void *k,
+                               const uint8_t *seal, void *out, hipStream_t stream);
 
 // Batched ensemble kernels (persistent and grouped schedules). The work list
 // is cut into one band per XCD; the persistent schedule keeps one claim

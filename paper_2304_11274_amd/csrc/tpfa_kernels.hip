@@ -2,6 +2,8 @@
 // hydrostatic reference column and the FP32 offsets, and the dispatch of
 // single-grid launches to the per-precision translation units. The tile
 // body they all share, and its design, is in tpfa_tile.h.
+#include <algorithm>
+
 #include "tpfa_tile.h"
 
 namespace tpfa {
@@ -182,6 +184,56 @@ __global__ void offset_kernel(int64_t nx, int64_t ldx, int64_t ny, int64_t n,
     const int64_t row = c / nx, idx = c - row * nx + row * ldx;
     dp[idx] = (float)(p[idx] - pref[row / ny]);
   }
+}
+
+// ----------------------------------------------------------------------------
+// Bandwidth probe: the memory traffic of the Jacobian kernels without their
+// arithmetic. Per cell it reads p and k (one element each) and the seal byte
+// and writes eight planes, out[q][c] = p[c] + (q + seal[c]) k[c] (so that
+// no load is dead), with coalesced non-temporal stores. Each workgroup takes
+// runs of kProbeRun consecutive cells (one per lane, kProbeRun / 256 per
+// lane), so every plane is written in long contiguous runs, as a tile row of
+// the march kernels writes them; the grid strides over the runs.
+// ----------------------------------------------------------------------------
+constexpr int kProbeThreads = 256;
+constexpr int kProbeRun = 1024;
+
+template <class S>
+__global__ void __launch_bounds__(kProbeThreads)
+    stream_probe_kernel(int64_t n, const S *__restrict__ p, const S *__restrict__ k,
+                        const uint8_t *__restrict__ seal, S *__restrict__ out) {
+  for (int64_t base = (int64_t)blockIdx.x * kProbeRun; base < n;
+       base += (int64_t)gridDim.x * kProbeRun) {
+#pragma unroll
+    for (int u = 0; u < kProbeRun / kProbeThreads; ++u) {
+      const int64_t c = base + u * kProbeThreads + threadIdx.x;
+      if (c < n) {
+        const S pc = p[c], kc = k[c];
+        const int sc = seal[c];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          __builtin_nontemporal_store(pc + S(q + sc) * kc, (gptr<S>)(out + q * n + c));
+      }
+    }
+  }
+}
+
+hipError_t launch_stream_probe(tpfa_precision_t prec, int64_t n, const void *p, const void *k,
+                               const uint8_t *seal, void *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  // 256 CUs x 8 workgroups of 256 threads fill the chip; at most one pass of
+  // runs when the array is smaller
+  const int64_t runs = (n + kProbeRun - 1) / kProbeRun;
+  const unsigned grid = (unsigned)std::min<int64_t>(runs, 256 * 8 * 4);
+  if (prec == TPFA_FP64)
+    stream_probe_kernel<double><<<grid, kProbeThreads, 0, st>>>(
+        n, static_cast<const double *>(p), static_cast<const double *>(k), seal,
+        static_cast<double *>(out));
+  else
+    stream_probe_kernel<float><<<grid, kProbeThreads, 0, st>>>(
+        n, static_cast<const float *>(p), static_cast<const float *>(k), seal,
+        static_cast<float *>(out));
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------

@@ -35,11 +35,17 @@
 // Precision. FP64: every quantity in double; the flux of each face is formed
 // as (Ups * lambda) * dPhi with Ups = (2 a k_Lo) * (k_Up * (1 / (k_Lo + k_Up)))
 // and a reciprocal accurate to about one ulp, so every result agrees with the
-// definition's evaluation order to about 1e-16 relative. FP32 precision form: the z-face
-// potential difference is formed in FP64 from pref[k] - pref[k+1] and the
-// stored offsets dp, and decides the upwind cell in FP64; x-y faces subtract
-// offsets of one plane in float (whose sign is exact, so the upwind choice is
-// the FP64 one); transmissibility, density (single-precision exp), mobility,
+// definition's evaluation order to about 1e-16 relative. FP32 precision form:
+// a cell's density is split into the reference density of its plane,
+// rho_k = rho0 exp(cf (pref[k] - p0)) (FP64, once per plane and workgroup),
+// and a float deviation d = rho_k (exp(cf dp) - 1) from a series that has no
+// cancellation. The z-face potential difference is then
+//   [(pref[k] - pref[k+1]) + (rho_k + rho_k+1) G / 2]  (FP64 per-plane constant)
+//   + (dp_Lo - dp_Up) + (d_Lo + d_Up) G / 2,
+// whose large terms cancel inside the FP64 constant, so its error is
+// relative to the deviations, not to rho G dz; it decides the upwind cell in
+// FP64. x-y faces subtract offsets of one plane in float (whose sign is exact,
+// so the upwind choice is the FP64 one); transmissibility, density, mobility,
 // the flux/derivative products and the Jacobian diagonal are FP32; the
 // residual, the gradients and J v are accumulated in FP64 and rounded once on
 // store.
@@ -75,20 +81,40 @@ template <class S>
 struct Props {
   S rho;  // density, Eq. (5)
   S lam;  // mobility rho / mu
+  S dv;   // FP32 form: rho minus the plane's reference density (0 in FP64)
 };
 
-// Eq. (5). FP64: rho0 exp(cf (p - p0)). FP32 form: the exponent is formed from
-// the plane's reference offset x_k = pref[k] - p0 (in float) plus dp; its
-// rounding (< 1 Pa) shifts the exponent by < 1e-9.
+// exp(x) - 1 in float without the cancellation of exp(x) - 1 near 0: for
+// |x| < 1/8 its Taylor series through x^6 / 720 (truncation below 1e-9
+// relative), otherwise the hardware exponential (relative error then a few
+// 1e-7, as for the density itself).
+__device__ __forceinline__ float expm1_series(float x) {
+  float c = fmaf(x, 1.0f / 720.0f, 1.0f / 120.0f);
+  c = fmaf(x, c, 1.0f / 24.0f);
+  c = fmaf(x, c, 1.0f / 6.0f);
+  c = fmaf(x, c, 0.5f);
+  c = fmaf(x, c, 1.0f);
+  float m = x * c;
+  if (!(fabsf(x) < 0.125f)) m = __expf(x) - 1.0f;
+  return m;
+}
+
+// Eq. (5). FP64: rho0 exp(cf (p - p0)). FP32 form: rho = rho_k (1 + m) with the
+// plane's reference density rho_k (rounded to float; FP64 where z faces need
+// it) and m = exp(cf dp) - 1, so the deviation d = rho_k m carries no rounding
+// of rho itself.
 __device__ __forceinline__ Props<double> props(double p, double, const Args &a) {
   Props<double> q;
   q.rho = a.rho0 * exp(a.cf * (p - a.p0));
   q.lam = q.rho * a.inv_mu;
+  q.dv = 0.0;
   return q;
 }
-__device__ __forceinline__ Props<float> props(float dp, float xk, const Args &a) {
+__device__ __forceinline__ Props<float> props(float dp, float rk, const Args &a) {
   Props<float> q;
-  q.rho = a.rho0f * __expf(a.cff * (xk + dp));
+  const float m = expm1_series(a.cff * dp);
+  q.dv = rk * m;
+  q.rho = fmaf(rk, m, rk);
   q.lam = q.rho * a.inv_muf;
   return q;
 }
@@ -203,18 +229,23 @@ __device__ __forceinline__ Face<S> face_ht(const Args &a, S T, S pLo, S pUp, S l
 }
 
 // z face between planes k (Lo) and k+1 (Up): dPhi = (p_Lo - p_Up) + rho_avg G.
-// For FP32 `dpref` = pref[k] - pref[k+1] and the potential is formed in FP64.
-__device__ __forceinline__ double zpot(double pLo, double pUp, double, double ra, const Args &a) {
+// FP32 form: `hk` = (pref[k] - pref[k+1]) + (rho_k + rho_k+1) G / 2 in FP64
+// (zero up to rounding for a hydrostatic pref), plus the offsets' difference
+// and the density deviations' share of rho_avg G, all summed in FP64.
+__device__ __forceinline__ double zpot(double pLo, double pUp, double, const Props<double> &Lo,
+                                       const Props<double> &Up, const Args &a) {
+  const double ra = 0.5 * (Lo.rho + Up.rho);
   return fma(ra, a.G, pLo - pUp);
 }
-__device__ __forceinline__ double zpot(float pLo, float pUp, double dpref, float ra,
-                                       const Args &a) {
-  return fma((double)ra, a.G, dpref + ((double)pLo - (double)pUp));
+__device__ __forceinline__ double zpot(float pLo, float pUp, double hk, const Props<float> &Lo,
+                                       const Props<float> &Up, const Args &a) {
+  const float dg = (Lo.dv + Up.dv) * a.hgf;
+  return (hk + ((double)pLo - (double)pUp)) + (double)dg;
 }
 
 template <bool DERIV, bool VJP, class S>
 __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open, S pLo, S pUp,
-                                          double dpref, Props<S> Lo, Props<S> Up,
+                                          double hk, Props<S> Lo, Props<S> Up,
                                           bool tin = false, S Tin = S(0)) {
   Face<S> f;
   S T;
@@ -224,8 +255,7 @@ __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open
     T = trans64<VJP>(a.a2z, kLo, kUp, open, f);
   else
     T = trans32<VJP>(a.a2zf, kLo, kUp, open, f);
-  const S ra = S(0.5) * (Lo.rho + Up.rho);
-  const double dphi = zpot(pLo, pUp, dpref, ra, a);
+  const double dphi = zpot(pLo, pUp, hk, Lo, Up, a);
   const S hc = sizeof(S) == 8 ? S(a.hc) : S(a.hcf);
   const S cf = sizeof(S) == 8 ? S(a.cf) : S(a.cff);
   upwind<S, DERIV, true>(f, T, (S)dphi, dphi >= 0.0, Lo.lam, Up.lam, cf, fma(hc, Lo.rho, S(1)),
@@ -273,10 +303,20 @@ constexpr bool tile_shares() {
          !has_k3(MODE) && share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
 
+// FP32 form: per-plane constants of the chunk (planes kb-1 .. kb+chunk), at
+// the start of the tile's LDS: the hydrostatic part of each z face's potential
+// difference (FP64) and each plane's reference density (float).
+constexpr int kPlaneSlots = kMaxChunk32 + 2;
+template <class S>
+constexpr int plane_lds_bytes() {
+  return sizeof(S) == 4 ? (kPlaneSlots * 12 + 15) / 16 * 16 : 0;
+}
+
 // Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
 // p, k (or t_x), mobility, seal, plus w / v for the product modes, t_ne and
 // t_se for the 10-flux stencil, t_y for the transmissibility form and k_y for
-// the per-direction form; or the shared-face layout.
+// the per-direction form; or the shared-face layout; after the FP32 form's
+// per-plane constants.
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = (TX + 2) * (TY + 2);
@@ -284,8 +324,9 @@ constexpr int tile_lds_bytes() {
   constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) +
                          (mode_kind(MODE) == MODE_RES10 ? 2 : 0) +
                          (has_trans(MODE) || has_k3(MODE) ? 1 : 0);
-  return tile_shares<S, MODE, TX, TY>() ? share_lds_bytes<S, MODE, TX, TY>()
-                                        : 2 * HW * ((int)sizeof(S) * arrays + 1);
+  return plane_lds_bytes<S>() + (tile_shares<S, MODE, TX, TY>()
+                                     ? share_lds_bytes<S, MODE, TX, TY>()
+                                     : 2 * HW * ((int)sizeof(S) * arrays + 1));
 }
 
 // Lower-cell faces a halo cell evaluates for the tile in the shared-face form.
@@ -308,11 +349,12 @@ struct Pending {
 // Accumulation term of the backward-Euler residual of one cell and its
 // pressure derivative: V/dt (phi(p) rho(p) - phi(pn) rho(pn)) with
 // phi(p) = phi_ref (1 + c_r (p - p0)), and V/dt (phi_ref c_r rho + phi c_f rho).
-// FP32 form: p - p0 = x_k + dp with the plane offset x_k; the two masses are
-// FP32 products and their difference is taken in FP64.
+// FP32 form: p - p0 = x_k + dp with the plane offset x_k, the previous level's
+// density from the plane's reference density rho_k as for the current one; the
+// two masses are FP32 products and their difference is taken in FP64.
 __device__ __forceinline__ void accumulation(const Args &a, const Cell<double> &c,
-                                             const Props<double> &d, double, double &term,
-                                             double &diag) {
+                                             const Props<double> &d, double, double,
+                                             double &term, double &diag) {
   const double phi1 = c.phi * (1.0 + a.cr * (c.p - a.p0));
   const double phi0 = c.phi * (1.0 + a.cr * (c.pn - a.p0));
   const double rho0 = a.rho0 * exp(a.cf * (c.pn - a.p0));
@@ -321,11 +363,11 @@ __device__ __forceinline__ void accumulation(const Args &a, const Cell<double> &
   diag = a.vdt * ((c.phi * a.cr) * d.rho + phi1 * (a.cf * d.rho));
 }
 __device__ __forceinline__ void accumulation(const Args &a, const Cell<float> &c,
-                                             const Props<float> &d, float xk, double &term,
-                                             float &diag) {
+                                             const Props<float> &d, float xk, float rk,
+                                             double &term, float &diag) {
   const float phi1 = c.phi * (1.0f + a.crf * (xk + c.p));
   const float phi0 = c.phi * (1.0f + a.crf * (xk + c.pn));
-  const float rho0 = a.rho0f * __expf(a.cff * (xk + c.pn));
+  const float rho0 = props(c.pn, rk, a).rho;
   const float m1 = phi1 * d.rho, m0 = phi0 * rho0;
   term = a.vdt * ((double)m1 - (double)m0);
   diag = a.vdtf * ((c.phi * a.crf) * d.rho + phi1 * (a.cff * d.rho));
@@ -354,7 +396,7 @@ __device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
 // In the backward-Euler modes the accumulation term comes first, as in Eq. (2).
 template <class S, int MODE>
 __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz, uint32_t cb,
-                                     const Cell<S> &c0, const Props<S> &d0, S xk,
+                                     const Cell<S> &c0, const Props<S> &d0, S xk, S rk,
                                      const Face<S> (&f)[6], const S (&wn)[6],
                                      const S (&fd)[4]) {
   constexpr int BASE = base_mode(MODE);
@@ -408,7 +450,7 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
   } else {
     double acc = 0.0;
     S dacc = S(0);
-    if constexpr (ACC) accumulation(a, c0, d0, xk, acc, dacc);
+    if constexpr (ACC) accumulation(a, c0, d0, xk, rk, acc, dacc);
     // residual in the neighbour order, accumulated in FP64
     if (BASE != MODE_JVP || a.r) {
       double r = acc;
@@ -448,6 +490,52 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
   }
 }
 
+// exp(x) in FP64 for the FP32 form's per-plane constants, with no constant
+// other than 1: x is halved j times until |x| / 2^j <= 1/16, exp of that by
+// its Taylor series through the 10th power in nested form
+// 1 + y (1 + y/2 (1 + y/3 (...))) (truncation below 1e-18 relative), then
+// squared j times (relative error about 2^j ulp; j = 0 for |x| < 1/32). The
+// loops are kept rolled: inlined into the ensemble kernels' item loop, the
+// constants of a library exponential were hoisted out of that loop and held
+// in registers across the whole tile body.
+__device__ __forceinline__ double exp_halving(double x) {
+  const int j = max(0, __builtin_amdgcn_frexp_exp(x) + 4);
+  const double y = __builtin_amdgcn_ldexp(x, -j);
+  double t = 1.0;
+#pragma unroll 1
+  for (int i = 10; i >= 1; --i) t = fma(y * t, rcp64((double)i), 1.0);
+#pragma unroll 1
+  for (int i = 0; i < j; ++i) t = t * t;
+  return t;
+}
+
+// FP32 form: the reference density rho_k = rho0 exp(cf (pref[k] - p0)) of planes
+// kb-1 .. ke (slot k - kb + 1; rounded to float) and the FP64 constant of the
+// z face (k, k+1), (pref[k] - pref[k+1]) + (rho_k + rho_k+1) G / 2. Threads
+// tid, tid + nt, ... take one plane each.
+__device__ __forceinline__ void fill_plane_constants(const Args &a, int kb, int ke, int nz,
+                                                     int tid, int nt, float *s_rk,
+                                                     double *s_hk) {
+  const int np = ke - kb + 2;
+  for (int q = tid; q < np; q += nt) {
+    const int k = kb - 1 + q;
+    float rkf = 0.0f;
+    double h = 0.0;
+    if (k >= 0 && k < nz) {
+      const double pk = *((gptr<const double>)a.pref + k);
+      const double r0 = a.rho0 * exp_halving(a.cf * (pk - a.p0));
+      rkf = (float)r0;
+      if (k + 1 < nz) {
+        const double pk1 = *((gptr<const double>)a.pref + k + 1);
+        const double r1 = a.rho0 * exp_halving(a.cf * (pk1 - a.p0));
+        h = (pk - pk1) + (0.5 * (r0 + r1)) * a.G;
+      }
+    }
+    s_rk[q] = rkf;
+    s_hk[q] = h;
+  }
+}
+
 template <class S, int MODE, int TX, int TY>
 struct Tile {
   static constexpr int W = TX + 2, H = TY + 2, HW = W * H;
@@ -482,6 +570,8 @@ struct Tile {
   S *s_yf;  // y-face field, two-sided layout only: t_y (transmissibility input; t_x is
             // staged in s_k) or k_y (per-direction form; k_x is staged in s_k)
   uint8_t *s_s;
+  double *s_hk;  // FP32 form: hydrostatic part of the z-face potential, planes kb-1 .. ke
+  float *s_rk;   // FP32 form: reference density of planes kb-1 .. ke
   size_t plane;
   int nz, kb, ke;
   bool inside;         // the thread's cell lies in the grid (staged as a real cell)
@@ -499,6 +589,9 @@ struct Tile {
 
   __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem, int tid_)
       : a(a_) {
+    s_hk = reinterpret_cast<double *>(smem);
+    s_rk = reinterpret_cast<float *>(s_hk + kPlaneSlots);
+    smem += plane_lds_bytes<S>();
     s_p = reinterpret_cast<S *>(smem);
     s_k = s_p + 2 * HW;
     s_l = s_k + 2 * HW;
@@ -584,6 +677,16 @@ struct Tile {
     A2y = FP32 ? S(a.a2yf) : S(a.a2y);
   }
 
+  // FP32 form: the per-plane constants of planes kb-1 .. ke (at most
+  // kPlaneSlots: the host limits FP32 chunks to kMaxChunk32 planes), one plane
+  // per thread, followed by a barrier.
+  __device__ __forceinline__ void plane_constants(int tid) const {
+    if constexpr (FP32) {
+      fill_plane_constants(a, kb, ke, nz, tid, NT, s_rk, s_hk);
+      __syncthreads();
+    }
+  }
+
   // A cell outside the domain reads the plane's first cell (any finite value)
   // and gets k = 0, which closes every face that touches it (T = 0).
   // Fields outside `need` keep their previous (finite) values; nothing reads them.
@@ -649,10 +752,13 @@ struct Tile {
       }
   }
 
-  // FP32 form: x_k = pref[k] - p0 for the density exponent
+  // FP32 form: pref[k]; x_k = pref[k] - p0 for the porosity law of the
+  // accumulation term; the plane's reference density rho_k and the FP64
+  // constant of the z face (k, k+1) from the chunk's per-plane constants
   __device__ __forceinline__ double pr(int k) const { return *((gptr<const double>)a.pref + k); }
   __device__ __forceinline__ S xoff(int k) const { return FP32 ? (S)(pr(k) - a.p0) : S(0); }
-  __device__ __forceinline__ double dpref(int k) const { return FP32 ? pr(k) - pr(k + 1) : 0.0; }
+  __device__ __forceinline__ S rk(int k) const { return FP32 ? (S)s_rk[k - kb + 1] : S(0); }
+  __device__ __forceinline__ double hk(int k) const { return FP32 ? s_hk[k - kb + 1] : 0.0; }
 
   // The -z face of the chunk's first plane: face (kb-1, kb), own cell is Up.
   __device__ __forceinline__ Face<S> first_zface(const Cell<S> &cur, const Props<S> &dcur) const {
@@ -660,9 +766,9 @@ struct Tile {
     if (kb > 0) {
       Cell<S> pr;
       load(pr, kb - 1);
-      const Props<S> dp = props(pr.p, xoff(kb - 1), a);
+      const Props<S> dp = props(pr.p, rk(kb - 1), a);
       f = face_z<DERIV, VJP>(a, K3 ? pr.kz : pr.k, K3 ? cur.kz : cur.k, (pr.s & 4u) == 0u,
-                             pr.p, cur.p, dpref(kb - 1), dp, dcur, TIN, pr.tz);
+                             pr.p, cur.p, hk(kb - 1), dp, dcur, TIN, pr.tz);
       f.w = pr.w;
     }
     return f;
@@ -677,7 +783,7 @@ struct Tile {
                                        Cell<S> (&h2)[HC], const Face<S> &zm, Face<S> &zp) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
-    const S xk = xoff(k);
+    const S rkk = rk(k);
     if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
     if (HALO2) {
       if (k + 2 < ke) load_halo(h2, k + 2);
@@ -700,7 +806,7 @@ struct Tile {
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
       if (hl[q] < 0) continue;
-      const Props<S> dh = props(h0[q].p, xk, a);
+      const Props<S> dh = props(h0[q].p, rkk, a);
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
       s_k[l] = TIN ? h0[q].tx : h0[q].k;
@@ -716,7 +822,7 @@ struct Tile {
     __syncthreads();
 
     // on the last plane c1 holds a stale (finite) cell and the +z face is closed
-    d1 = props(c1.p, xoff(has_pz ? k + 1 : k), a);
+    d1 = props(c1.p, rk(has_pz ? k + 1 : k), a);
 
     // the six faces, in the neighbour order -x, +x, -y, +y, -z, +z; a face
     // whose neighbour does not exist has T = 0 and contributes exact zeros
@@ -751,7 +857,7 @@ struct Tile {
     f[4] = zm;
     wn[4] = zm.w;
     zp = face_z<DERIV, VJP>(a, K3 ? c0.kz : c0.k, K3 ? c1.kz : c1.k,
-                            has_pz && (c0.s & 4u) == 0u, c0.p, c1.p, has_pz ? dpref(k) : 0.0,
+                            has_pz && (c0.s & 4u) == 0u, c0.p, c1.p, has_pz ? hk(k) : 0.0,
                             d0, d1, TIN, c0.tz);
     zp.w = c0.w;
     f[5] = zp;
@@ -777,7 +883,7 @@ struct Tile {
       }
     }
     if (!own) return;
-    emit<S, MODE>(a, k, plane, nz, cb, c0, d0, xk, f, wn, fd);
+    emit<S, MODE>(a, k, plane, nz, cb, c0, d0, ACC ? xoff(k) : S(0), rkk, f, wn, fd);
   }
 
   // ---- shared-face form (residual-only modes) ----------------------------
@@ -837,7 +943,7 @@ struct Tile {
                                              Pending<S> &pd) const {
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
-    const S xk = xoff(k);
+    const S rkk = rk(k);
     if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
     if (HALO2) {
       if (k + 2 < ke) load_halo(h2, k + 2);
@@ -852,7 +958,7 @@ struct Tile {
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
       if (hl[q] < 0) continue;
-      hlam[q] = props(h0[q].p, xk, a).lam;
+      hlam[q] = props(h0[q].p, rkk, a).lam;
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
       s_k[l] = TIN ? h0[q].tx : h0[q].k;
@@ -863,9 +969,9 @@ struct Tile {
     // plane k-1: its upper-cell fluxes were written before this barrier
     if (k > kb) finish(k - 1, HW - b, pd);
 
-    d1 = props(c1.p, xoff(has_pz ? k + 1 : k), a);
+    d1 = props(c1.p, rk(has_pz ? k + 1 : k), a);
     zp = face_z<false, false>(a, c0.k, c1.k, has_pz && (c0.s & 4u) == 0u, c0.p, c1.p,
-                              has_pz ? dpref(k) : 0.0, d0, d1, TIN, c0.tz);
+                              has_pz ? hk(k) : 0.0, d0, d1, TIN, c0.tz);
 
     const int o = b + ol;
     pd.fpx = fwd_face(kPX, o + 1, c0.p, c0.k, d0.lam, c0.s, c0.tx);
@@ -882,7 +988,7 @@ struct Tile {
     pd.fzp = zp.F;
     if constexpr (ACC) {
       S dacc;
-      accumulation(a, c0, d0, xk, pd.acc, dacc);
+      accumulation(a, c0, d0, xoff(k), rkk, pd.acc, dacc);
     }
     // faces entering the tile from the -x / -y side of the halo ring
 #pragma unroll
@@ -907,6 +1013,7 @@ template <class S, int MODE, int TX, int TY>
 __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb, char *smem,
                                            int tid = threadIdx.x) {
   const Tile<S, MODE, TX, TY> t(a, bx, by, kb, smem, tid);
+  t.plane_constants(tid);
   // own column at planes k, k+1, k+2, halo cell at k, k+1 (and k+2 with HALO2),
   // z faces (k-1,k), (k,k+1)
   using T = Tile<S, MODE, TX, TY>;
@@ -917,7 +1024,7 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
   t.load_halo(h0, kb);
   if (T::HALO2 && kb + 1 < t.ke) t.load_halo(h1, kb + 1);
   if (kb + 1 < t.nz) t.load(c1, kb + 1);
-  d0 = props(c0.p, t.xoff(kb), a);
+  d0 = props(c0.p, t.rk(kb), a);
   z0 = t.first_zface(c0, d0);
   if constexpr (T::SHARE) {
     Pending<S> pd{};

@@ -1,50 +1,139 @@
-"""The FP32 precision form's z-face potential difference is formed in FP64
-from float densities, so it carries an absolute error of about 1e-7 rho g dz
-(about 2e-3 Pa here), independent of |dPhi|. Where a cell's faces all have a
-small |dPhi| (a vertical column whose z faces carry 10-30 Pa), that error is
-no longer small against the cell's flux scale: the per-cell relative error can
-exceed 1e-5 there, while each face stays within the absolute bound. This test
-pins that bound (and records the relative error reached)."""
+"""The FP32 precision form where small potential differences dominate a cell.
+
+The z-face potential difference of the FP32 form (Sec. 3, Eqs. 3b and 5) is
+formed from an FP64 per-plane constant (pref[k] - pref[k+1]) + (rho_k + rho_k+1)
+G / 2, the offsets' difference and float density deviations from the planes'
+reference densities. Nothing of size rho g dz is rounded to float, so its
+error is far below 1e-5 of any |dPhi| these workloads carry, and the per-cell
+relative error (R16 metric) stays within 1e-5 where a cell's faces all carry
+potential differences of a few Pa. These cases failed that bound when the
+densities entered the z face as float values:
+  * a vertical column whose z faces carry 10-30 Pa;
+  * heavily sealed grids with small offsets, where cells with only z faces
+    open and small vertical potential differences are common (the structure of
+    the failures seen in random sweeps at 30% sealed faces);
+  * offsets within +-10 Pa of the hydrostatic column.
+At exact hydrostatic equilibrium (dp = 0) the FP32 fluxes meet the bound the
+FP64 path's test uses.
+"""
 import numpy as np
 import pytest
 import torch
 
 import geomodel
+from helpers import compare_full, compare_res10, compare_vjp
 
 pytestmark = pytest.mark.gpu
 
+TOL32 = 1e-5
+TAU32 = 1e-4  # Pa: upwind tie band of the FP32 form (its |dPhi| error is below 1e-6 Pa here)
 
-def test_fp32_z_faces_with_small_potential_differences(gpu, orc):
-    nz = 40
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def column(nz=40, seed=5):
     g = geomodel.Grid(1, 1, nz)
-    fl = geomodel.Fluid()
-    rng = np.random.default_rng(5)
-    pref = orc.hydrostatic(g, fl)
+    rng = np.random.default_rng(seed)
     # offsets falling by 10-30 Pa per plane: every z face carries |dPhi| of that size
     steps = rng.uniform(10.0, 30.0, nz)
     dp = (np.cumsum(steps[::-1])[::-1] - steps.sum() / 2).astype(np.float32).reshape(nz, 1, 1)
     k = np.exp(rng.normal(np.log(1e-13), 0.5, (nz, 1, 1))).astype(np.float32)
-    r = gpu.residual(g, fl, torch.from_numpy(k).cuda(), torch.from_numpy(dp).cuda(),
-                     pref=torch.from_numpy(pref).cuda(), ry=1.0, rz=1.0)
-    torch.cuda.synchronize()
+    return g, dp, k
+
+
+def test_fp32_column_with_small_z_potentials(gpu, orc):
+    g, dp, k = column()
+    fl = geomodel.Fluid()
+    pref = orc.hydrostatic(g, fl)
+    r, J = gpu.jacobian(g, fl, dev(k), dev(dp), pref=dev(pref), ry=1.0, rz=1.0)
     p_w = orc.widen_fp32(dp, pref)
-    ref = orc.evaluate(g, fl, k.astype(np.float64), p_w, ry=1.0, rz=1.0, want=("r", "J", "scale",
-                                                                               "dphi"))
+    kw = k.astype(np.float64)
+    ref = orc.evaluate(g, fl, kw, p_w, ry=1.0, rz=1.0, want=("dphi",))
     dphi = ref["dphi"][2][:-1].ravel()
     assert np.all((np.abs(dphi) > 5) & (np.abs(dphi) < 40))
-    err = np.abs(r.double().cpu().numpy() - ref["r"]).ravel()
-    # |dF/d dPhi| of each face = T lambda_up; the cell's error is at most the sum over its
-    # two z faces of T lambda_up eps, eps = 5e-3 Pa (about twice 1e-7 rho g dz), plus rounding
-    a_z = g.dx * g.dy / g.dz
-    kk = k.astype(np.float64).ravel()
-    T = a_z * 2 * kk[:-1] * kk[1:] / (kk[:-1] + kk[1:])
-    lam = fl.rho0 * np.exp(fl.cf * (p_w.ravel() - fl.p0)) / fl.mu
-    face = T * np.maximum(lam[:-1], lam[1:]) * 5e-3
-    bound = np.zeros(nz)
-    bound[:-1] += face
-    bound[1:] += face
-    scale = ref["scale"][0].ravel()
-    assert np.all(err <= bound + 1e-6 * scale), (err / np.maximum(bound, 1e-300)).max()
-    rel = float((err / scale).max())
-    print(f"largest per-cell relative error {rel:.2e} (absolute bound holds)")
-    assert rel < 1e-3
+    rep = compare_full(orc, g, fl, kw, p_w, host(r), host(J), tol=TOL32, tau=TAU32, ry=1.0,
+                       rz=1.0, seal=None)
+    print("column: largest per-cell relative error", rep, flush=True)
+    assert rep["max_err"] <= TOL32 and rep["n_tie_faces"] == 0
+    w = np.random.default_rng(9).standard_normal(g.shape).astype(np.float32)
+    gp, gm = gpu.residual_vjp(g, fl, dev(k), dev(dp), dev(w), pref=dev(pref), ry=1.0, rz=1.0)
+    rep = compare_vjp(orc, g, fl, kw, p_w, w.astype(np.float64), host(gp), host(gm), tol=TOL32,
+                      tau=TAU32, ry=1.0, rz=1.0, seal=None)
+    assert rep["max_err"] <= TOL32, rep
+
+
+@pytest.mark.parametrize("amp", [0.0, 10.0])
+def test_fp32_hydrostatic_equilibrium(gpu, orc, amp):
+    """dp = 0: the fluxes vanish up to the FP64 path's bound (the hydrostatic
+    part of each z face is an FP64 constant, the x-y faces subtract equal
+    offsets). dp ~ U(-10, 10) Pa: every face carries a few Pa, and the
+    residual, Jacobian, VJP and 10-flux residual meet 1e-5 against the oracle."""
+    geo = geomodel.random_small(11, 33, 9, 50, sigma=1.5, seal_prob=0.05, rz=0.1)
+    g, fl = geo.grid, geo.fluid
+    pref = orc.hydrostatic(g, fl, geo.p_top)
+    dp = (geo.noise[0] * (amp / 1e5)).astype(np.float32)
+    k = geo.kx32()
+    args = (g, fl, dev(k), dev(dp))
+    kw = dict(pref=dev(pref), seal=dev(geo.seal), ry=geo.ry, rz=geo.rz)
+    r, J = gpu.jacobian(*args, **kw)
+    r, J = host(r), host(J)
+    p_w = orc.widen_fp32(dp, pref)
+    kwide = k.astype(np.float64)
+    if amp == 0.0:
+        Tz = 50 * geo.rz * float(kwide.max()) * 2
+        lam = 1.1 * fl.rho0 / fl.mu
+        bound = 1e-12 * Tz * lam * float(np.abs(np.diff(pref)).max())
+        print(f"hydrostatic: max |r| {np.abs(r).max():.3e}, bound {bound:.3e}", flush=True)
+        assert np.abs(r).max() <= bound
+        ref = orc.evaluate(g, fl, kwide, p_w, ry=geo.ry, rz=geo.rz, seal=geo.seal, want=("r",))
+        assert np.abs(ref["r"]).max() <= bound
+        return
+    rep = compare_full(orc, g, fl, kwide, p_w, r, J, tol=TOL32, tau=TAU32, ry=geo.ry,
+                       rz=geo.rz, seal=geo.seal)
+    print("near equilibrium:", rep, flush=True)
+    assert rep["max_err"] <= TOL32
+    w = np.random.default_rng(3).standard_normal(g.shape).astype(np.float32)
+    gp, gm = gpu.residual_vjp(*args, dev(w), **kw)
+    rep = compare_vjp(orc, g, fl, kwide, p_w, w.astype(np.float64), host(gp), host(gm),
+                      tol=TOL32, tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    assert rep["max_err"] <= TOL32, rep
+    tne, tse = geomodel.diagonal_t(g, 5)
+    r10 = gpu.residual10(*args, dev(tne.astype(np.float32)), dev(tse.astype(np.float32)), **kw)
+    rep = compare_res10(orc, g, fl, kwide, p_w, tne.astype(np.float32).astype(np.float64),
+                        tse.astype(np.float32).astype(np.float64), host(r10), tol=TOL32,
+                        tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    assert rep["max_err"] <= TOL32, rep
+
+
+@pytest.mark.parametrize("seal_prob", [0.3, 0.6])
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_fp32_sealed_small_offsets(gpu, orc, seed, seal_prob):
+    """Regression cases: heavily sealed grids with offsets of +-300 Pa, so that
+    many cells keep only z faces with potential differences of a few Pa to a
+    few hundred Pa; Jacobian and VJP within 1e-5 of the oracle, every cell."""
+    geo = geomodel.random_small(100 + seed, 45, 13, 24, sigma=2.0, seal_prob=seal_prob, rz=0.1)
+    g, fl = geo.grid, geo.fluid
+    pref = orc.hydrostatic(g, fl, geo.p_top)
+    dp = (geo.noise[0] * 3e-3).astype(np.float32)
+    k = geo.kx32()
+    print(f"sealed case seed {seed} seals {seal_prob}", flush=True)
+    args = (g, fl, dev(k), dev(dp))
+    kw = dict(pref=dev(pref), seal=dev(geo.seal), ry=geo.ry, rz=geo.rz)
+    r, J = gpu.jacobian(*args, **kw)
+    p_w = orc.widen_fp32(dp, pref)
+    kwide = k.astype(np.float64)
+    rep = compare_full(orc, g, fl, kwide, p_w, host(r), host(J), tol=TOL32, tau=TAU32,
+                       ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    assert rep["max_err"] <= TOL32, rep
+    w = np.random.default_rng(seed).standard_normal(g.shape).astype(np.float32)
+    gp, gm = gpu.residual_vjp(*args, dev(w), **kw)
+    rep = compare_vjp(orc, g, fl, kwide, p_w, w.astype(np.float64), host(gp), host(gm),
+                      tol=TOL32, tau=TAU32, ry=geo.ry, rz=geo.rz, seal=geo.seal)
+    assert rep["max_err"] <= TOL32, rep

@@ -18,7 +18,7 @@ from helpers import compare_full
 
 pytestmark = pytest.mark.gpu
 
-TOL64, TOL32, TAU32 = 1e-12, 1e-5, 0.05
+TOL64, TOL32, TAU32 = 1e-12, 1e-5, 1e-4
 
 
 def dev(a):

@@ -138,3 +138,32 @@ def test_balanced_z_chunks(nz, most, want):
     assert kz == want and kz <= most
     chunks = -(-nz // kz)
     assert chunks == -(-nz // most) and (chunks - 1) * kz < nz <= chunks * kz
+
+
+def test_fp32_chunks_hold_at_most_128_planes():
+    """The FP32 kernels keep two constants per plane of their chunk in LDS, so
+    an FP32 chunk runs as at most 128 planes; FP64 chunks are as given."""
+    g = geomodel.Grid(64, 64, 300)
+    assert rl(g, "jacobian", F32, tile=0, kz_chunk=200)["kz_chunk"] == 128
+    assert rl(g, "vjp", F32, tile=0, kz_chunk=129)["kz_chunk"] == 128
+    assert rl(g, "residual10", F32, tile=0, kz_chunk=128)["kz_chunk"] == 128
+    assert rl(g, "jacobian", F64, tile=0, kz_chunk=200)["kz_chunk"] == 200
+    assert rl(geomodel.Grid(64, 64, 90), "jacobian", F32, tile=0, kz_chunk=500)["kz_chunk"] == 90
+
+
+@pytest.mark.parametrize("tile,want", [(6, L.TPFA_ERR_TILE), (7, L.TPFA_ERR_TILE),
+                                       (3, L.TPFA_ERR_TILE), (9, L.TPFA_ERR_TILE)])
+def test_batch_refuses_tiles_the_ensemble_kernels_do_not_hold(tile, want):
+    """The ensemble kernels hold the tile bodies 0, 1, 2 only: any other
+    explicit tile is refused on the host, before anything touches the device
+    (the pointers below are never dereferenced)."""
+    lib = L.load()
+    g = geomodel.Grid(100, 40, 20)
+    m = L.Model(api._grid(g), api._fluid(geomodel.Fluid()),
+                L.Rock(16, None, None, 1.0, 0.1, None), L.State(16, None), 16, 16,
+                L.Launch(tile, 0, 0, 0, 0))
+    arr = (L.Model * 1)(m)
+    h = C.c_void_p()
+    assert lib.tpfa_batch_create(arr, 1, L.TPFA_FP64, 1, C.byref(h), None) == want
+    assert not h.value
+    assert b"tile 0, 1 or 2" in lib.tpfa_last_error()
