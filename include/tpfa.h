@@ -329,6 +329,26 @@ int tpfa_batch_info(const tpfa_batch_t *batch, int64_t *n_items, int *n_workgrou
    waited for). NULL is accepted. */
 void tpfa_batch_destroy(tpfa_batch_t *batch);
 
+/* ---- Ensemble run that allocates nothing ---- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   ensemble of tpfa_batch_create + tpfa_batch_run in one call that allocates
+   nothing. The model table and each model's first work item are written into
+   a fixed-size device array of the library (at most 256 models, 256 * 416 +
+   257 * 8 bytes, about 108 KB; each GPU the library runs on holds its own
+   copy until the process ends) by small upload launches on `stream`, then
+   one grouped launch (one workgroup per work item, as
+   TPFA_SCHEDULE_GROUPED) runs every model: the kernels and the results are
+   those of a batch of the same models. Models are checked as by
+   tpfa_batch_create, all before anything is enqueued. Every call on a GPU
+   shares that GPU's array and leaves the last call's table in it: calls that
+   overlap on one GPU (on two streams, or from two threads without ordering)
+   race. Errors: those of tpfa_batch_create, and TPFA_ERR_SHAPE for more than
+   256 models. */
+int tpfa_ensemble_run_noalloc(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
+                              tpfa_batch_mode_t mode, void *stream);
+
 /* ---- Introspection ---- */
 
 /* Operations of the single-grid entry points, for tpfa_resolve_launch. */

@@ -459,6 +459,39 @@ def tile_shapes():
     return out
 
 
+def ensemble_run_noalloc(members: Sequence[dict], outputs: Sequence[tuple], *,
+                         mode: str = "jacobian"):
+    """One ensemble launch that allocates nothing (tpfa_ensemble_run_noalloc):
+    ``members`` as for Ensemble, ``outputs`` one (r, J) pair per member,
+    allocated by the caller in the layout of the member's p (r may be None in
+    the Jacobian mode, J is ignored in the residual mode). The model table is
+    written into the library's fixed-size device array: at most 256 members,
+    and calls that overlap on one GPU race."""
+    if not members or len(outputs) != len(members):
+        raise ValueError("one (r, J) pair per member, at least one member")
+    bm = {"jacobian": L.TPFA_BATCH_JACOBIAN, "residual": L.TPFA_BATCH_RESIDUAL}[mode]
+    arr = (L.Model * len(members))()
+    prec = device = None
+    for m, (d, (r, J)) in enumerate(zip(members, outputs)):
+        g, p = d["grid"], d["p"]
+        n, pr, dt, dev, lay = _inputs(g, d["kx"], p, d.get("seal"), d.get("pref"))
+        if prec is None:
+            prec, device = pr, dev
+        elif pr != prec or dev != device:
+            raise ValueError("all ensemble members need the same precision and device")
+        if bm == L.TPFA_BATCH_JACOBIAN:
+            _need(J, "J", dt, 7 * n, dev, lay)
+        if r is not None or bm == L.TPFA_BATCH_RESIDUAL:
+            _need(r, "r", dt, n, dev, lay)
+        arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
+                         _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
+                         L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
+                         _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"))
+                         or L.Launch(-1, 0, 0, 0, 0))
+    lib = L.load()
+    L.check(lib.tpfa_ensemble_run_noalloc(arr, len(members), prec, bm, _stream(device)), lib)
+
+
 class Ensemble:
     """Many independent grids run by one persistent kernel replayed from a
     HIP graph. ``members`` is a sequence of dicts with keys grid, fluid, kx,

@@ -770,6 +770,57 @@ void tpfa_batch_destroy(tpfa_batch_t *batch) {
   batch_free(batch);
 }
 
+int tpfa_ensemble_run_noalloc(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
+                              tpfa_batch_mode_t mode, void *stream) {
+  try {
+    if (!models) return fail(TPFA_ERR_NULL, "models is NULL");
+    if (n_models <= 0) return fail(TPFA_ERR_SHAPE, "n_models must be positive");
+    if (n_models > tpfa::kStaticModels)
+      return fail(TPFA_ERR_SHAPE, "an allocation-free run takes at most " +
+                                      std::to_string(tpfa::kStaticModels) + " models");
+    if (mode != TPFA_BATCH_RESIDUAL && mode != TPFA_BATCH_JACOBIAN)
+      return fail(TPFA_ERR_PARAM, "unknown batch mode");
+    // every member is checked before anything is enqueued
+    tpfa::Args a;
+    int64_t items = 0;
+    int tiles = -1;
+    for (int m = 0; m < n_models; ++m) {
+      const int rc = batch_model(models[m], m, prec, mode, a);
+      if (rc) return rc;
+      items += a.nblocks;
+      tiles = (tiles < 0 || tiles == a.tile) ? a.tile : 3;
+    }
+    if (items > (int64_t)std::numeric_limits<uint32_t>::max())
+      return fail(TPFA_ERR_SHAPE, "too many work items for one workgroup each");
+    void *scr = nullptr;
+    hipError_t e = tpfa::static_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    tpfa::UploadBlock blk{};
+    int64_t item = 0;
+    for (int m0 = 0; m0 < n_models; m0 += tpfa::kUploadModels) {
+      blk.first = m0;
+      blk.count = std::min(tpfa::kUploadModels, n_models - m0);
+      for (int q = 0; q < blk.count; ++q) {
+        (void)batch_model(models[m0 + q], m0 + q, prec, mode, blk.a[q]);
+        blk.item0[q] = item;
+        item += blk.a[q].nblocks;
+      }
+      if ((e = tpfa::launch_upload(blk, scr, st)) != hipSuccess)
+        return hip_fail(e, "model table upload");
+    }
+    const tpfa::Mode km = mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN : tpfa::MODE_RESIDUAL;
+    if ((e = tpfa::launch_static_grouped(prec, km, tiles, scr, n_models, items, st)) !=
+        hipSuccess)
+      return hip_fail(e, "ensemble launch");
+    return ok();
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
 int tpfa_resolve_launch(const tpfa_grid_t *grid, int op, tpfa_precision_t prec,
                         const tpfa_rock_t *rock, const tpfa_launch_t *launch,
                         tpfa_launch_t *resolved) {

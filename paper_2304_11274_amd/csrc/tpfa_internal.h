@@ -150,4 +150,20 @@ int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles);
 hipError_t launch_grouped(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
                           const WorkItem *d_items, int64_t n_items, hipStream_t stream);
 
+// Allocation-free ensemble run: the model table and each model's first work
+// item live in a fixed-size device array of the library (one per GPU), written
+// by upload launches whose kernel arguments carry up to kUploadModels models.
+constexpr int kStaticModels = 256;
+constexpr int kUploadModels = 8;
+struct UploadBlock {
+  int32_t first, count;            // table rows [first, first + count)
+  int64_t item0[kUploadModels];    // first work item of each of these models
+  Args a[kUploadModels];
+};
+// The device address of this GPU's array (resolved once per device).
+hipError_t static_scratch(void **ptr);
+hipError_t launch_upload(const UploadBlock &blk, void *scratch, hipStream_t stream);
+hipError_t launch_static_grouped(tpfa_precision_t prec, Mode mode, int tiles, void *scratch,
+                                 int n_models, int64_t n_items, hipStream_t stream);
+
 }  // namespace tpfa

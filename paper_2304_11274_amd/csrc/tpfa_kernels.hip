@@ -3,6 +3,7 @@
 // single-grid launches to the per-precision translation units. The tile
 // body they all share, and its design, is in tpfa_tile.h.
 #include <algorithm>
+#include <mutex>
 
 #include "tpfa_tile.h"
 
@@ -184,6 +185,115 @@ __global__ void offset_kernel(int64_t nx, int64_t ldx, int64_t ny, int64_t n,
     const int64_t row = c / nx, idx = c - row * nx + row * ldx;
     dp[idx] = (float)(p[idx] - pref[row / ny]);
   }
+}
+
+// ----------------------------------------------------------------------------
+// Allocation-free ensemble run. The model table (Args of each model) and the
+// first work item of each model live in `scratch`, a file-scope device array
+// of fixed size: each GPU the library runs on holds its own copy until the
+// process ends, and every call on that GPU shares it (calls that overlap on
+// one GPU race). Upload launches write the table from their kernel arguments
+// (so nothing is allocated, copied from host memory or set by a memset node);
+// the grouped ensemble schedule then runs one workgroup per work item, which
+// it decodes itself: the model by binary search over the first items, tile
+// and z chunk in the natural order of a batch's work list (z chunk, tile row,
+// tile), so the results are those of the batch.
+// ----------------------------------------------------------------------------
+constexpr size_t kScratchTable = (size_t)kStaticModels * sizeof(Args);
+constexpr size_t kScratchBytes = kScratchTable + (size_t)(kStaticModels + 1) * sizeof(int64_t);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static_assert(sizeof(UploadBlock) <= 4096, "the arguments of one upload launch");
+static_assert(sizeof(Args) % 8 == 0, "the table is copied in 8-byte words");
+
+__global__ void __launch_bounds__(256) upload_kernel(const UploadBlock blk, unsigned char *scr) {
+  const uint64_t *src = reinterpret_cast<const uint64_t *>(&blk.a[0]);
+  uint64_t *dst = reinterpret_cast<uint64_t *>(scr) + (size_t)blk.first * (sizeof(Args) / 8);
+  const int words = blk.count * (int)(sizeof(Args) / 8);
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  int64_t *item0 = reinterpret_cast<int64_t *>(scr + kScratchTable);
+  if (threadIdx.x < (unsigned)blk.count) item0[blk.first + threadIdx.x] = blk.item0[threadIdx.x];
+}
+
+template <class S, int MODE, int TILE>
+__global__ void __launch_bounds__(kPersistThreads)
+    static_grouped_kernel(const unsigned char *__restrict__ scr, int n_models) {
+  __shared__ __attribute__((aligned(16))) char smem[persist_lds_bytes<S, MODE, TILE>()];
+  const Args *models = reinterpret_cast<const Args *>(scr);
+  const int64_t *item0 = reinterpret_cast<const int64_t *>(scr + kScratchTable);
+  // workgroup b is item l = b / kXcds of band b % kXcds, as in grouped_kernel
+  uint32_t start, len;
+  band_range(gridDim.x, blockIdx.x % kXcds, start, len);
+  const int64_t t = (int64_t)start + blockIdx.x / kXcds;
+  // the model: the last one whose first item is at most t
+  int lo = 0, hi = n_models - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (item0[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const Args m = models[lo];
+  const uint32_t l = (uint32_t)(t - item0[lo]);
+  const uint32_t ntx = (uint32_t)m.ntx, nty = (uint32_t)m.nty;
+  const uint32_t r1 = l / ntx, bz = r1 / nty;
+  WorkItem w;
+  w.model = lo;
+  w.bx = (int)(l - r1 * ntx);
+  w.by = (int)(r1 - bz * nty);
+  w.kb = (int)bz * m.kz_chunk;
+  run_item<S, MODE, TILE>(m, w, smem, threadIdx.x);
+}
+
+// This GPU's address of `scratch`, resolved once per device with that device
+// current (each GPU holds its own copy; the array's name is not a device
+// address in host code).
+constexpr int kMaxDevices = 64;
+static void *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+hipError_t static_scratch(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+  }
+  *ptr = g_scratch[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_upload(const UploadBlock &blk, void *scr, hipStream_t st) {
+  upload_kernel<<<1, 256, 0, st>>>(blk, static_cast<unsigned char *>(scr));
+  return hipGetLastError();
+}
+
+template <class S, int MODE>
+static const void *static_fn(int tiles) {
+  switch (tiles) {
+    case 0: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 0>);
+    case 1: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 1>);
+    case 2: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 2>);
+    default: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, kMixedTiles>);
+  }
+}
+
+hipError_t launch_static_grouped(tpfa_precision_t prec, Mode mode, int tiles, void *scr,
+                                 int n_models, int64_t n_items, hipStream_t st) {
+  const void *fn;
+  if (prec == TPFA_FP64)
+    fn = mode == MODE_RESIDUAL ? static_fn<double, MODE_RESIDUAL>(tiles)
+                               : static_fn<double, MODE_JACOBIAN>(tiles);
+  else
+    fn = mode == MODE_RESIDUAL ? static_fn<float, MODE_RESIDUAL>(tiles)
+                               : static_fn<float, MODE_JACOBIAN>(tiles);
+  const unsigned char *p = static_cast<const unsigned char *>(scr);
+  void *args[] = {(void *)&p, (void *)&n_models};
+  return hipLaunchKernel(fn, dim3((unsigned)n_items), dim3(kPersistThreads), args, 0, st);
 }
 
 // ----------------------------------------------------------------------------

@@ -178,6 +178,25 @@ def test_stream_probe_validation(lib):
         tp.stream_probe(t, t, t.to(torch.uint8))   # host tensors
 
 
+def test_noalloc_run_validation(lib):
+    g, f, rk, st = good()
+    m = (L.Model * 257)()
+    for q in range(257):
+        m[q] = L.Model(g, f, rk, st, DUMMY.value, DUMMY.value, L.Launch(-1, 0, 0))
+    J = L.TPFA_BATCH_JACOBIAN
+    assert lib.tpfa_ensemble_run_noalloc(m, 257, L.TPFA_FP64, J, None) == L.TPFA_ERR_SHAPE
+    assert b"at most 256" in lib.tpfa_last_error()
+    assert lib.tpfa_ensemble_run_noalloc(None, 2, L.TPFA_FP64, J, None) == L.TPFA_ERR_NULL
+    assert lib.tpfa_ensemble_run_noalloc(m, 0, L.TPFA_FP64, J, None) == L.TPFA_ERR_SHAPE
+    assert lib.tpfa_ensemble_run_noalloc(m, 2, L.TPFA_FP64, 5, None) == L.TPFA_ERR_PARAM
+    m[1].launch = L.Launch(6, 0, 0)  # a tile the ensemble kernels do not hold
+    assert lib.tpfa_ensemble_run_noalloc(m, 2, L.TPFA_FP64, J, None) == L.TPFA_ERR_TILE
+    m[1].launch = L.Launch(-1, 0, 0)
+    m[1].J = None
+    assert lib.tpfa_ensemble_run_noalloc(m, 2, L.TPFA_FP64, J, None) == L.TPFA_ERR_NULL
+    assert b"model 1" in lib.tpfa_last_error()
+
+
 def test_batch_validation(lib):
     g, f, rk, st = good()
     out = C.c_void_p()
