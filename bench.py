@@ -26,11 +26,17 @@ The same run also times, as extra fields of the JSON line:
              lines, with contiguous arrays vs arrays of row pitch 512 (FP64, FP32)
   paper10  - the paper's own workload (Sec. 7): 1000 applications of the FP32
              10-flux residual on Nx x Ny x 246 meshes up to 750 x 994 x 246
-  cpu_baseline - the FP64 CPU oracle on a bounded slab of the same workload
+  copy_ceiling - the library's bandwidth probe: the Jacobian kernels' loads and
+             stores without their arithmetic, FP64 and FP32, on the same cell count
+  cpu_baseline, cpu_baselines, parity - the FP64 CPU oracle on each workload
+             (16^3; 512 x 512 x 256 in FP64 and on the FP32 form's widened inputs;
+             the 64-model ensemble; 256 x 256 x 128 forward + VJP), timed on the
+             host, and its outputs compared with one GPU application of each
+             (launched as timed): the per-cell relative error of every result
 The roofline object is for the dominant kernel, the FP64 Jacobian kernel.
 
     python bench.py [--steps K] [--warmup W] [--sections fp64,fp32,res,newton,aniso,slab,
-                                                           pitched,batched,adjoint,paper10,cpu]
+                                                   pitched,probe,batched,adjoint,paper10,cpu]
 """
 import argparse
 import hashlib
@@ -61,9 +67,12 @@ BYTES_FP64_RJ_K3 = BYTES_FP64_RJ + 8 + 8    # + ky, kz arrays = 97
 BYTES_FP32_RJ_K3 = BYTES_FP32_RJ + 4 + 4    # + ky, kz arrays = 49
 # the paper's wall times for 1000 applications on 750 x 994 x 246 (Sec. 7, Table 1)
 PAPER10_CONTEXT = {"cs2_s": 0.0823, "a100_raja_s": 16.8378, "a100_cuda_s": 14.6573}
+# the kernels and the host code that picks their launches: a change to either
+# invalidates the committed counter summaries
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2304_11274_amd", "csrc", f)
                for f in ("tpfa_tile.h", "tpfa_kernels.hip", "tpfa_march_f64.hip",
-                         "tpfa_march_f32.hip", "tpfa_march_f32_plain.hip")]
+                         "tpfa_march_f32.hip", "tpfa_march_f32_plain.hip", "tpfa_api.cpp",
+                         "tpfa_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tpfa_jacobian_fp64_512x512x256_traffic.txt")
 
 
@@ -116,19 +125,284 @@ class Timer:
         self.ms = self.a.elapsed_time(self.b)
 
 
+# ---------------------------------------------------------------------------
+# Per-cell relative error of a GPU result against the FP64 oracle (the metric
+# every parity test uses): r against the cell's flux scale sum |F_KL|, the
+# Jacobian diagonal against sum |dF_KL/dp_K|, an off-diagonal entry against
+# itself, grad p against sum |J_rc| |w_r|, grad ln k against 2 max|w| sum |F|;
+# an entry whose scale is 0 must be exactly 0 (else the error is infinite).
+# Faces whose potential difference lies within tau of zero may take either
+# upwind choice; the errors of cells away from such faces are reported apart.
+# ---------------------------------------------------------------------------
+
+def _rel(np, got, ref, scale):
+    d = np.abs(np.asarray(got, np.float64) - ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d == 0, 0.0, np.inf))
+    return e
+
+
+def _shift(np, v, axis, side):
+    """u[c] = v[c + side e_axis] (0 outside); axis 0/1/2 = x/y/z."""
+    u = np.zeros_like(v)
+    ax = 2 - axis
+    src = [slice(None)] * 3
+    dst = [slice(None)] * 3
+    if side > 0:
+        dst[ax], src[ax] = slice(0, -1), slice(1, None)
+    else:
+        dst[ax], src[ax] = slice(1, None), slice(0, -1)
+    u[tuple(dst)] = v[tuple(src)]
+    return u
+
+
+def _tie_cells(np, dphi, tau):
+    """Cells touching a face (indexed by its lower cell) with |dPhi| <= tau."""
+    with np.errstate(invalid="ignore"):
+        ties = np.abs(dphi) <= tau
+    touch = ties[0] | ties[1] | ties[2]
+    for a in range(3):
+        touch |= _shift(np, ties[a].astype(np.uint8), a, -1).astype(bool)
+    return ties, touch
+
+
+def _report(np, e, dphi, tau, tol, extra=None):
+    ties, touch = _tie_cells(np, dphi, tau)
+    away = e[~touch]
+    rep = {"max_rel_err": float(e.max()),
+           "max_rel_err_away_from_ties": float(away.max()) if away.size else 0.0,
+           "tie_faces": int(ties.sum()), "cells": int(e.size), "tol": tol, "tau_Pa": tau,
+           "within_tol": bool(e.max() <= tol)}
+    if extra:
+        rep.update(extra)
+    return rep
+
+
+def rj_errors(np, r, J, ref):
+    """Per-cell max of the residual and Jacobian errors."""
+    e = _rel(np, r, ref["r"], ref["scale"][0])
+    e = np.maximum(e, _rel(np, J[0], ref["J"][0], ref["scale"][1]))
+    for q in range(1, 7):
+        e = np.maximum(e, _rel(np, J[q], ref["J"][q], np.abs(ref["J"][q])))
+    return e
+
+
+def vjp_errors(np, gp, gm, w, ref):
+    """Per-cell max of the grad p and grad ln k errors."""
+    J, aw = ref["J"], np.abs(w)
+    sp_ = np.abs(J[0]) * aw
+    wmax = aw.copy()
+    for n in range(6):
+        a, side = n // 2, 1 if n % 2 else -1
+        # (J^T |w|)_c gains |J_{L,c}| |w_L| from the row of neighbour L = c + side e_a,
+        # whose plane for its neighbour c is the opposite one
+        sp_ += _shift(np, np.abs(J[1 + (n ^ 1)]) * aw, a, side)
+        wmax = np.maximum(wmax, _shift(np, aw, a, side))
+    e = _rel(np, gp, ref["grad_p"], sp_)
+    return np.maximum(e, _rel(np, gm, ref["grad_logk"], 2.0 * wmax * ref["scale"][0]))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f_:
+            return next(l.split(":", 1)[1].strip() for l in f_ if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown CPU"
+
+
+def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
+    """The FP64 oracle on the host (single-threaded, as it stands), timed on each
+    workload, and its outputs compared cell by cell with one GPU application of
+    the same inputs in the launch the timed sections use."""
+    import geomodel
+    import oracle
+    cpu = _cpu_model()
+    cores = len(os.sched_getaffinity(0))
+    want = ("r", "J", "scale", "dphi")
+    base = {"unit": "cells/s", "cores": 1, "kind": "oracle", "host_cores_available": cores}
+    out["cpu_baselines"], out["parity"] = {}, {}
+
+    def up(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    def host(t):
+        torch.cuda.synchronize()
+        return t.cpu().numpy()
+
+    def timed(fn):
+        t0 = time.time()
+        res = fn()
+        return res, time.time() - t0
+
+    # config 1: 16^3, FP64
+    t16 = geomodel.tiny16()
+    g1 = t16.grid
+    p1 = oracle.pressure(t16)
+    ref1, dt1 = timed(lambda: oracle.evaluate(g1, t16.fluid, t16.kx, p1, ry=t16.ry, rz=t16.rz,
+                                              seal=t16.seal, want=want))
+    reps = max(1, int(0.5 / max(dt1, 1e-4)))
+    _, dtr = timed(lambda: [oracle.evaluate(g1, t16.fluid, t16.kx, p1, ry=t16.ry, rz=t16.rz,
+                                            seal=t16.seal, want=("r", "J"))
+                            for _ in range(reps)])
+    k1, pd1, s1 = up(t16.kx), up(p1), up(t16.seal)
+    r1, J1 = tp.jacobian(g1, t16.fluid, k1, pd1, seal=s1, ry=t16.ry, rz=t16.rz)
+    e1 = rj_errors(np, host(r1), host(J1), ref1)
+    for _ in range(10):
+        tp.jacobian(g1, t16.fluid, k1, pd1, seal=s1, ry=t16.ry, rz=t16.rz, r_out=r1, J_out=J1)
+    with Timer(torch) as tm:
+        for _ in range(200):
+            tp.jacobian(g1, t16.fluid, k1, pd1, seal=s1, ry=t16.ry, rz=t16.rz, r_out=r1,
+                        J_out=J1)
+    out["tiny16"] = {"workload": "16x16x16 FP64 residual + Jacobian (latency-bound; no "
+                                 "roofline fraction: it fits in cache)",
+                     "cells": g1.ncell, "ms_per_step": tm.ms / 200,
+                     "cells_per_s": g1.ncell / (tm.ms / 200 / 1e3)}
+    out["cpu_baselines"]["tiny16_fp64_rj"] = dict(
+        base, value=g1.ncell * reps / dtr,
+        sample=f"16x16x16, {reps} evaluations of r + J, {dtr:.2f} s on {cpu}")
+    out["parity"]["tiny16_fp64_rj"] = _report(np, e1, ref1["dphi"], 1e-9 * np.abs(p1).max(),
+                                              1e-12)
+    log(f"oracle leg 16^3: {out['parity']['tiny16_fp64_rj']}")
+    del k1, pd1, s1, r1, J1
+
+    # config 2: 512 x 512 x 256 FP64, pressure field 0 (the p the GPU builds)
+    g, fl = geo.grid, geo.fluid
+    N = g.ncell
+    pref_h = pref.cpu().numpy()
+    p2 = pref_h[:, None, None] + geo.noise[0]
+    ref2, dt2 = timed(lambda: oracle.evaluate(g, fl, geo.kx, p2, ry=geo.ry, rz=geo.rz,
+                                              seal=geo.seal, want=want))
+    out["cpu_baseline"] = dict(
+        base, value=N / dt2,
+        sample=f"the whole 512x512x256 workload, pressure field 0: FP64 r + J with the error "
+               f"scales and face potentials, single-threaded plain oracle, {dt2:.1f} s on {cpu}")
+    kx64, sl = up(geo.kx), up(geo.seal)
+    r2, J2 = tp.jacobian(g, fl, kx64, up(p2), seal=sl, ry=geo.ry, rz=geo.rz)
+    rep2 = _report(np, rj_errors(np, host(r2), host(J2), ref2), ref2["dphi"],
+                   1e-9 * float(np.abs(p2).max()), 1e-12)
+    out["parity"]["fp64_512"] = rep2
+    del r2, J2
+    log(f"oracle leg 512^2x256 FP64: {rep2} (oracle {dt2:.1f} s)")
+
+    # config 3: the FP32 form on the same geomodel; informational error against
+    # the unquantised FP64 inputs (the config-2 oracle), then against the oracle
+    # on the widened FP32 inputs (the bound)
+    k32 = geo.kx.astype(np.float32)
+    dp32 = geo.noise[0].astype(np.float32)
+    r3, J3 = tp.jacobian(g, fl, up(k32), up(dp32), seal=sl, pref=pref, ry=geo.ry, rz=geo.rz)
+    r3, J3 = host(r3), host(J3)
+    info = float(rj_errors(np, r3, J3, ref2).max())
+    del ref2, p2
+    p3 = oracle.widen_fp32(dp32, pref_h)
+    ref3, dt3 = timed(lambda: oracle.evaluate(g, fl, k32.astype(np.float64), p3, ry=geo.ry,
+                                              rz=geo.rz, seal=geo.seal, want=want))
+    rep3 = _report(np, rj_errors(np, r3, J3, ref3), ref3["dphi"], 1e-4, 1e-5,
+                   {"max_rel_err_vs_unquantised_fp64_inputs": info})
+    out["parity"]["fp32_512"] = rep3
+    out["cpu_baselines"]["fp32_form_widened_inputs"] = dict(
+        base, value=N / dt3,
+        sample=f"512x512x256, the FP32 form's inputs widened to FP64 (k, pref[k] + dp): r + J "
+               f"with error scales, {dt3:.1f} s on {cpu}")
+    for sec, key in (("fp32", "fp32_512"),):
+        if sec in out:
+            out[sec]["max_rel_err"] = out["parity"][key]["max_rel_err"]
+    del r3, J3, ref3, p3, kx64, sl
+    torch.cuda.empty_cache()
+    log(f"oracle leg 512^2x256 FP32: {rep3} (oracle {dt3:.1f} s)")
+
+    # config 4: the 64-model ensemble (one graph-replayed launch), per model
+    if "batched" in out:
+        models = geomodel.ensemble()
+        members, refs, t_or, worst = [], [], 0.0, None
+        for geo_m in models:
+            gm_ = geo_m.grid
+            pr = tp.hydrostatic(gm_, geo_m.fluid)
+            members.append(dict(grid=gm_, fluid=geo_m.fluid, kx=up(geo_m.kx32()),
+                                p=up(geo_m.dp32()), seal=up(geo_m.seal), pref=pr,
+                                ry=geo_m.ry, rz=geo_m.rz))
+        lt = out["batched"].get("ensemble_launch")
+        if lt:
+            from paper_2304_11274_amd import autotune
+            autotune.apply_ensemble_launch(members, lt)
+        ens = tp.Ensemble(members)
+        if lt:
+            ens.set_schedule(lt[2])
+        ens.run()
+        torch.cuda.synchronize()
+        cells = 0
+        for m, geo_m in enumerate(models):
+            pw = oracle.widen_fp32(geo_m.dp32(), members[m]["pref"].cpu().numpy())
+            ref, dtm = timed(lambda: oracle.evaluate(geo_m.grid, geo_m.fluid,
+                                                     geo_m.kx32().astype(np.float64), pw,
+                                                     ry=geo_m.ry, rz=geo_m.rz, seal=geo_m.seal,
+                                                     want=want))
+            t_or += dtm
+            cells += geo_m.ncell
+            rep = _report(np, rj_errors(np, host(ens.r[m]), host(ens.J[m]), ref), ref["dphi"],
+                          1e-4, 1e-5)
+            if worst is None or rep["max_rel_err"] > worst["max_rel_err"]:
+                worst = dict(rep, model=m)
+            tie = rep["tie_faces"]
+            refs.append((rep["max_rel_err"], tie))
+        ens.close()
+        out["parity"]["ensemble"] = {
+            "max_rel_err": max(e for e, _ in refs), "tie_faces": sum(t for _, t in refs),
+            "tol": 1e-5, "cells": cells, "worst_model": worst,
+            "within_tol": bool(max(e for e, _ in refs) <= 1e-5)}
+        out["batched"]["max_rel_err"] = out["parity"]["ensemble"]["max_rel_err"]
+        out["cpu_baselines"]["ensemble_64_models"] = dict(
+            base, value=cells / t_or,
+            sample=f"the 64-model ensemble, FP32 inputs widened, model by model, r + J with "
+                   f"error scales, {t_or:.1f} s in total on {cpu}")
+        del members, ens
+        torch.cuda.empty_cache()
+        log(f"oracle leg ensemble: {out['parity']['ensemble']}")
+
+    # config 5: 256 x 256 x 128 FP32 forward residual + VJP, set 0
+    if "adjoint" in out:
+        geo_a = geomodel.adjoint256()
+        ga = geo_a.grid
+        pra = tp.hydrostatic(ga, geo_a.fluid)
+        dpa = geo_a.noise[0].astype(np.float32)
+        wa = geo_a.extra["w"][0].astype(np.float32)
+        ka = geo_a.kx32()
+        kw = dict(seal=up(geo_a.seal), pref=pra, ry=geo_a.ry, rz=geo_a.rz)
+        ra = tp.residual(ga, geo_a.fluid, up(ka), up(dpa), **kw)
+        gpa, gma = tp.residual_vjp(ga, geo_a.fluid, up(ka), up(dpa), up(wa), **kw)
+        pw = oracle.widen_fp32(dpa, pra.cpu().numpy())
+        ref, dta = timed(lambda: oracle.evaluate(ga, geo_a.fluid, ka.astype(np.float64), pw,
+                                                 ry=geo_a.ry, rz=geo_a.rz, seal=geo_a.seal,
+                                                 w=wa.astype(np.float64),
+                                                 want=want + ("grad_p", "grad_logk")))
+        e = np.maximum(_rel(np, host(ra), ref["r"], ref["scale"][0]),
+                       vjp_errors(np, host(gpa), host(gma), wa.astype(np.float64), ref))
+        out["parity"]["adjoint"] = _report(np, e, ref["dphi"], 1e-4, 1e-5)
+        out["adjoint"]["max_rel_err"] = out["parity"]["adjoint"]["max_rel_err"]
+        out["cpu_baselines"]["adjoint_fwd_vjp"] = dict(
+            base, value=ga.ncell / dta,
+            sample=f"256x256x128, FP32 inputs widened: r, J, grad p and grad ln k with error "
+                   f"scales in one pass, {dta:.1f} s on {cpu}")
+        log(f"oracle leg adjoint: {out['parity']['adjoint']}")
+    out["max_rel_err"] = out["parity"]["fp64_512"]["max_rel_err"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections",
-                    default="fp64,fp32,res,newton,aniso,slab,pitched,batched,adjoint,paper10,"
-                            "cpu")
+                    default="fp64,fp32,res,newton,aniso,slab,pitched,probe,batched,adjoint,"
+                            "paper10,cpu")
     ap.add_argument("--aux-steps", type=int, default=200,
                     help="steps of the fp32 / residual / batched / adjoint sections")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--paper10-steps", type=int, default=1000,
                     help="applications per mesh in the paper10 section (the paper uses 1000)")
+    ap.add_argument("--ensemble-launch", default=None,
+                    help="fixed ensemble launch 'assignment/kz/schedule' (e.g. tile0/16/grouped) "
+                         "instead of the autotuner; per-model launches then take the library "
+                         "defaults (for short profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the y-slab "
@@ -414,16 +688,37 @@ def main():
         out["pitched"] = res
         log(f"pitched: {res}")
 
-    # streaming-copy ceiling of this machine (torch copy kernel, context only)
-    src = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    with Timer(torch) as tm:
-        for _ in range(20):
+    # this box's bandwidth ceiling on the Jacobian kernels' access pattern: the
+    # library's streaming probe (read p, k, seal; write eight planes; coalesced,
+    # non-temporal), over the benchmark's cell count, FP64 and FP32
+    if "probe" in sections:
+        out["copy_ceiling"] = {}
+        for name, t_, bpc in (("fp64", torch.float64, BYTES_FP64_RJ),
+                              ("fp32", torch.float32, BYTES_FP32_RJ)):
+            pp_ = noise[0].to(t_)
+            kk_ = kx64.to(t_)
+            oo_ = torch.empty((8,) + g.shape, dtype=t_, device=dev)
+            for _ in range(3):
+                tp.stream_probe(g, pp_, kk_, seal, out=oo_)
+            with Timer(torch) as tm:
+                for _ in range(20):
+                    tp.stream_probe(g, pp_, kk_, seal, out=oo_)
+            out["copy_ceiling"][name] = {"bytes_per_cell": bpc, "cells": N,
+                                         "ms": tm.ms / 20,
+                                         "GBps": bpc * N * 20 / (tm.ms / 1e3) / 1e9}
+            del pp_, kk_, oo_
+        out["copy_ceiling_GBps"] = out["copy_ceiling"]["fp64"]["GBps"]
+        log(f"bandwidth probe: {out['copy_ceiling']}")
+        # torch's device copy, for context
+        src = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
             dst.copy_(src)
-    out["copy_ceiling_GBps"] = 2 * src.numel() * 8 * 20 / (tm.ms / 1e3) / 1e9
-    del src, dst
+        with Timer(torch) as tm:
+            for _ in range(20):
+                dst.copy_(src)
+        out["copy_ceiling"]["torch_copy_GBps"] = 2 * src.numel() * 8 * 20 / (tm.ms / 1e3) / 1e9
+        del src, dst
     del kx64, seal, noise
     torch.cuda.empty_cache()
 
@@ -442,13 +737,20 @@ def main():
         del models
         from paper_2304_11274_amd import autotune
         t1 = time.time()
-        # per-model launches: each model with its own tuned tile and z-chunk
-        table = autotune.tune_members(members)
-        solo = [(m["tile"], m["kz_chunk"]) for m in members]
-        # one persistent launch: tiles by lane utilisation, one z-chunk timed on the batch
-        ens_best, ens_times = autotune.tune_ensemble(members)
-        log(f"autotuned {len(table)} size classes for per-model launches; ensemble launch "
-            f"{ens_best} ({ens_times}) in {time.time() - t1:.1f} s")
+        if args.ensemble_launch:
+            lab, z_, sch_ = args.ensemble_launch.split("/")
+            ens_best = (lab, z_ if z_.startswith("bal") else int(z_), sch_)
+            ens_times = {}
+            solo = [(None, None)] * len(members)
+            autotune.apply_ensemble_launch(members, ens_best)
+        else:
+            # per-model launches: each model with its own tuned tile and z-chunk
+            table = autotune.tune_members(members)
+            solo = [(m["tile"], m["kz_chunk"]) for m in members]
+            # one launch: tiles by lane utilisation, z chunk and schedule timed on the batch
+            ens_best, ens_times = autotune.tune_ensemble(members)
+            log(f"autotuned {len(table)} size classes for per-model launches; ensemble launch "
+                f"{ens_best} ({ens_times}) in {time.time() - t1:.1f} s")
         ens = tp.Ensemble(members)
         ens.set_schedule(ens_best[2])
         n_items, n_wg = ens.info()
@@ -615,34 +917,9 @@ def main():
                           "meshes": rows, "given_transmissibilities_750x994x246": trans_row,
                           "paper_750x994x246": PAPER10_CONTEXT}
 
-    # ------------------------------------------- CPU baseline: the FP64 oracle
+    # ---------------- the FP64 oracle on the host: timings, and the GPU's errors
     if "cpu" in sections:
-        import oracle
-        geo_c = geomodel.big512(noise_seeds=(2,))
-        prefc = oracle.hydrostatic(geo_c.grid, geo_c.fluid)
-
-        def slab(nzs):
-            gs = geomodel.Grid(geo_c.grid.nx, geo_c.grid.ny, nzs)
-            p = prefc[:nzs, None, None] + geo_c.noise[0][:nzs]
-            t0 = time.time()
-            oracle.evaluate(gs, geo_c.fluid, geo_c.kx[:nzs], p, ry=geo_c.ry, rz=geo_c.rz,
-                            seal=geo_c.seal[:nzs], want=("r", "J"))
-            return time.time() - t0, gs.ncell
-        dt, nc = slab(2)
-        nzs = int(max(2, min(geo_c.grid.nz, 2 * args.cpu_seconds / max(dt, 1e-3))))
-        dt, nc = slab(nzs)
-        model = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as f_:
-                model = next(l.split(":", 1)[1].strip() for l in f_ if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        out["cpu_baseline"] = {"value": nc / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-                               "sample": f"512x512x{nzs} slab of the 512x512x256 workload "
-                                         f"(FP64 residual + Jacobian, single-threaded plain "
-                                         f"oracle), {dt:.1f} s on {model}",
-                               "host_cores_available": len(os.sched_getaffinity(0))}
-        log(f"cpu baseline: {out['cpu_baseline']}")
+        oracle_leg(out, args, tp, torch, np, dev, geo, pref)
 
     rf = out.get("roofline")
     if rf is not None:

@@ -147,6 +147,11 @@ typedef struct {
 } tpfa_launch_t;
 
 #define TPFA_LAUNCH_XCD_REMAP 1
+/* flags bit 1 (ignored with bit 0): tiles in y-fast order, so that the
+   workgroups of a tile's x neighbours are ny/TY ids apart (the hardware hands
+   consecutive ids to the 8 XCDs in turn: with ny/TY a multiple of 8 they run
+   on one XCD and share the x-halo lines in its L2). */
+#define TPFA_LAUNCH_Y_FAST 2
 
 /* Residual r[ncell] (paper Algorithm 1 with the Eq. (3)-(5) flux). */
 int tpfa_residual(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
@@ -257,17 +262,21 @@ int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double 
 
 /* ---- Bandwidth probe ---- */
 
-/* The memory traffic of the Jacobian entry points without their arithmetic,
-   to measure the ceiling the device reaches on that access pattern (the
-   streaming-copy measurement beside the roofline, Sec. 7's Roofline
-   analysis): for c < n, out[q * n + c] = p[c] + (q + seal[c]) * k[c],
-   q = 0..7, with p, k and out of the precision's type (double or float;
-   8 + 8 + 1 bytes read and 64 written per cell in FP64, 4 + 4 + 1 and 32 in
-   FP32), coalesced, non-temporal stores. Device pointers owned by the caller;
-   out holds 8 n elements. Errors: TPFA_ERR_SHAPE (n <= 0 or 8 n overflows),
+/* The memory traffic of the Jacobian entry points without their arithmetic
+   and without their halo, to measure the bandwidth the device reaches on that
+   access pattern (the streaming measurement beside the roofline, as in the
+   paper's Roofline analysis, Sec. 7): for every cell idx of `grid` (row pitch
+   grid->ldx), out[q * ldx*ny*nz + idx] = p[idx] + (q + seal[idx]) * k[idx],
+   q = 0..7, with p, k and out of the precision's type (double or float; 8 + 8
+   + 1 bytes read and 64 written per cell in FP64, 4 + 4 + 1 and 32 in FP32).
+   It marches 128 x 8 column blocks through 32-plane chunks with two x cells
+   per lane (16-byte accesses in FP64 where the pitch is even and the pointers
+   aligned), coalesced, with non-temporal stores: of the patterns measured on
+   MI355X for this traffic, the fastest. Device pointers owned by the caller;
+   padding cells are neither read nor written. Errors: the grid checks of the other calls,
    TPFA_ERR_PARAM (precision), TPFA_ERR_NULL, TPFA_ERR_HIP. */
-int tpfa_stream_probe(int64_t n, tpfa_precision_t prec, const void *p, const void *k,
-                      const uint8_t *seal, void *out, void *stream);
+int tpfa_stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                      const void *k, const uint8_t *seal, void *out, void *stream);
 
 /* ---- Batched ensemble: many independent grids in one persistent launch ---- */
 
@@ -275,8 +284,14 @@ int tpfa_stream_probe(int64_t n, tpfa_precision_t prec, const void *p, const voi
    valid while the batch is used; r may be NULL; J is required for
    TPFA_BATCH_JACOBIAN and ignored for TPFA_BATCH_RESIDUAL. launch.tile is -1
    (default: the single-grid default tile, or 64x4 where that default is a
-   512-thread tile) or one of the tiles the ensemble kernels hold: 0, 1, 2
-   (64x4, 32x8, 16x16); any other tile gives TPFA_ERR_TILE. */
+   512-thread tile), one of the tiles the ensemble kernels hold: 0, 1, 2
+   (64x4, 32x8, 16x16), or TPFA_TILE_FIT; any other tile gives TPFA_ERR_TILE.
+   TPFA_TILE_FIT fits a tile of tx x ty cells (256 threads) to the member: tx
+   the row length of the fewest tiles of at most 64 cells covering a row, in
+   near-equal parts (at least 8), ty the most rows that 256 threads hold,
+   balanced over the rows; members whose rows are not a multiple of 64 cells
+   then leave fewer lanes idle than with a fixed tile. */
+#define TPFA_TILE_FIT 10
 typedef struct {
   tpfa_grid_t grid;
   tpfa_fluid_t fluid;
@@ -379,6 +394,10 @@ int tpfa_resolve_launch(const tpfa_grid_t *grid, int op, tpfa_precision_t prec,
    workgroup plane and the workgroup size in threads. */
 int tpfa_num_tiles(void);
 int tpfa_tile_shape(int id, int *tx, int *ty, int *threads);
+/* Shape of the fitted tile (TPFA_TILE_FIT, ensemble members only) for rows of
+   nx cells and `rows` rows: tx x ty cells on 256 threads (tx ty <= 256).
+   Errors: TPFA_ERR_SHAPE (nx or rows <= 0), TPFA_ERR_NULL. */
+int tpfa_fit_tile_shape(int64_t nx, int64_t rows, int *tx, int *ty);
 
 const char *tpfa_strerror(int code);
 const char *tpfa_last_error(void);

@@ -27,6 +27,8 @@ TPFA_OP_RESIDUAL_BE, TPFA_OP_JACOBIAN_BE, TPFA_OP_JVP, TPFA_OP_JVP_BE = 4, 5, 6,
 TPFA_BATCH_RESIDUAL = 0
 TPFA_BATCH_JACOBIAN = 1
 TPFA_LAUNCH_XCD_REMAP = 1
+TPFA_LAUNCH_Y_FAST = 2
+TPFA_TILE_FIT = 10
 TPFA_SCHEDULE_PERSISTENT = 0
 TPFA_SCHEDULE_GROUPED = 1
 
@@ -97,11 +99,12 @@ SIGNATURES = {
     "tpfa_batch_destroy": (None, [vp]),
     "tpfa_num_tiles": (C.c_int, []),
     "tpfa_tile_shape": (C.c_int, [C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),
+    "tpfa_fit_tile_shape": (C.c_int, [C.c_int64, C.c_int64, P(C.c_int), P(C.c_int)]),
     "tpfa_strerror": (C.c_char_p, [C.c_int]),
     "tpfa_last_error": (C.c_char_p, []),
     "tpfa_version": (C.c_int, []),
     "tpfa_resolve_launch": (C.c_int, [P(Grid), C.c_int, C.c_int, P(Rock), P(Launch), P(Launch)]),
-    "tpfa_stream_probe": (C.c_int, [C.c_int64, C.c_int, vp, vp, vp, vp, vp]),
+    "tpfa_stream_probe": (C.c_int, [P(Grid), C.c_int, vp, vp, vp, vp, vp]),
     "tpfa_ensemble_run_noalloc": (C.c_int, [P(Model), C.c_int, C.c_int, C.c_int, vp]),
 }
 

@@ -33,14 +33,24 @@ def _fluid(f) -> L.Fluid:
     return L.Fluid(float(f.rho0), float(f.cf), float(f.p0), float(f.mu))
 
 
-def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap: bool, rows=None):
-    """``rows`` = (y_begin, y_end): compute and write only those rows (a y slab;
-    the grid's other rows are read as its halo)."""
+def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None):
+    """``xcd_remap``: True (or "bands") for the XCD band order, "yfast" for the
+    y-fast tile order, False for the natural order. ``rows`` = (y_begin, y_end):
+    compute and write only those rows (a y slab; the grid's other rows are read
+    as its halo)."""
     if tile is None and kz_chunk is None and not xcd_remap and rows is None:
         return None
+    if xcd_remap == "yfast":
+        flags = L.TPFA_LAUNCH_Y_FAST
+    elif xcd_remap in (True, "bands"):
+        flags = L.TPFA_LAUNCH_XCD_REMAP
+    elif not xcd_remap:
+        flags = 0
+    else:
+        raise ValueError(f"unknown workgroup order {xcd_remap!r}")
     y0, y1 = (0, 0) if rows is None else (int(rows[0]), int(rows[1]))
     return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
-                    L.TPFA_LAUNCH_XCD_REMAP if xcd_remap else 0, y0, y1)
+                    flags, y0, y1)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -394,26 +404,30 @@ def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torc
     return dp
 
 
-def stream_probe(p: torch.Tensor, k: torch.Tensor, seal: torch.Tensor, out=None) -> torch.Tensor:
+def stream_probe(grid, p: torch.Tensor, k: torch.Tensor, seal: torch.Tensor,
+                 out=None) -> torch.Tensor:
     """Bandwidth probe with the Jacobian kernels' access pattern (tpfa_stream_probe):
     out[q] = p + (q + seal) * k for q = 0..7, from contiguous p, k (float64 or
-    float32) and uint8 seal of equal size; returns out of shape (8,) + p.shape."""
+    float32) and uint8 seal of the grid's shape (nz, ny, nx); returns out of
+    shape (8, nz, ny, nx)."""
+    shape = (int(grid.nz), int(grid.ny), int(grid.nx))
     for t, name in ((p, "p"), (k, "k"), (seal, "seal")):
-        if not (t.is_cuda and t.is_contiguous()):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous CUDA tensor")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have the grid's shape {shape}")
     if k.dtype != p.dtype or p.dtype not in (torch.float64, torch.float32):
         raise ValueError("p and k must both be float64 or both float32")
-    if seal.dtype != torch.uint8 or not (p.numel() == k.numel() == seal.numel()):
-        raise ValueError("seal must be uint8 and p, k, seal of equal size")
-    n = p.numel()
+    if seal.dtype != torch.uint8:
+        raise ValueError("seal must be uint8")
     if out is None:
-        out = torch.empty((8,) + tuple(p.shape), dtype=p.dtype, device=p.device)
-    elif not (out.is_contiguous() and out.dtype == p.dtype and out.numel() == 8 * n):
-        raise ValueError("out must be contiguous, of p's dtype, with 8 * p.numel() elements")
+        out = torch.empty((8,) + shape, dtype=p.dtype, device=p.device)
+    elif not (out.is_contiguous() and out.dtype == p.dtype and tuple(out.shape) == (8,) + shape):
+        raise ValueError("out must be contiguous, of p's dtype and of shape (8, nz, ny, nx)")
     prec = L.TPFA_FP64 if p.dtype == torch.float64 else L.TPFA_FP32
     lib = L.load()
-    L.check(lib.tpfa_stream_probe(n, prec, _ptr(p), _ptr(k), _ptr(seal), _ptr(out),
-                                  _stream(p.device)), lib)
+    L.check(lib.tpfa_stream_probe(C.byref(_grid(grid)), prec, _ptr(p), _ptr(k), _ptr(seal),
+                                  _ptr(out), _stream(p.device)), lib)
     return out
 
 
@@ -445,7 +459,18 @@ def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=
     tx, ty, th = tile_shapes()[out.tile]
     return {"tile": out.tile, "shape": (tx, ty), "threads": th, "kz_chunk": out.kz_chunk,
             "xcd_remap": bool(out.flags & L.TPFA_LAUNCH_XCD_REMAP),
+            "order": ("bands" if out.flags & L.TPFA_LAUNCH_XCD_REMAP else
+                      "yfast" if out.flags & L.TPFA_LAUNCH_Y_FAST else "natural"),
             "rows": (out.y_begin, out.y_end)}
+
+
+def fit_tile_shape(nx: int, rows: int):
+    """(tx, ty) of the fitted tile (tile id TPFA_TILE_FIT = 10, ensemble members
+    only) for rows of nx cells: 256 threads, tx ty <= 256 cells."""
+    lib = L.load()
+    tx, ty = C.c_int(), C.c_int()
+    L.check(lib.tpfa_fit_tile_shape(int(nx), int(rows), C.byref(tx), C.byref(ty)), lib)
+    return tx.value, ty.value
 
 
 def tile_shapes():

@@ -21,7 +21,8 @@ import torch
 
 from . import api
 
-TILE_IDS_256 = (0, 1, 2)          # the tiles the persistent ensemble kernel accepts
+TILE_IDS_256 = (0, 1, 2)          # the fixed tiles the ensemble kernels hold
+FIT_TILE = 10                     # the ensemble kernels' tile fitted to each member
 TILE_IDS_ALL = (0, 1, 2, 3, 4, 5)
 KZ_CANDIDATES = (8, 16, 32, 64)
 
@@ -32,8 +33,12 @@ def size_class(nx: int, ny: int, nz: int) -> Tuple[int, int, int]:
 
 
 def lane_utilisation(nx: int, ny: int, tile: int) -> float:
-    tx, ty, _ = api.tile_shapes()[tile]
-    return (nx / (math.ceil(nx / tx) * tx)) * (ny / (math.ceil(ny / ty) * ty))
+    """Share of a launch's threads that own a cell of the nx x ny plane."""
+    if tile == FIT_TILE:
+        tx, ty = api.fit_tile_shape(nx, ny)
+        return nx * ny / (math.ceil(nx / tx) * math.ceil(ny / ty) * 256)
+    tx, ty, th = api.tile_shapes()[tile]
+    return nx * ny / (math.ceil(nx / tx) * math.ceil(ny / ty) * th)
 
 
 def _time(fn, reps: int) -> float:
@@ -102,7 +107,7 @@ def tune_members(members: Sequence[dict], *, cache: Optional[str] = None, **kw
     return table
 
 
-def ensemble_tile(nx: int, ny: int, tiles: Sequence[int] = (0, 1)) -> int:
+def ensemble_tile(nx: int, ny: int, tiles: Sequence[int] = (0, 1, FIT_TILE)) -> int:
     """The tile with the best lane utilisation among ``tiles``; ties go to the
     wider tile (longer contiguous rows per wave). 16-wide rows are left out by
     default: in FP32 they fill only half a 128-byte line per row."""
@@ -123,7 +128,7 @@ def balanced_kz(nz: int, most: int) -> int:
 
 
 def tune_ensemble(members: Sequence[dict], *, kz: Sequence[int] = (16, 32, 64),
-                  tiles: Sequence[int] = TILE_IDS_256,
+                  tiles: Sequence[int] = TILE_IDS_256 + (FIT_TILE,),
                   schedules: Sequence[str] = ("persistent", "grouped"), reps: int = 5,
                   mode: str = "jacobian") -> Tuple[Tuple[str, int | str, str], Dict[str, float]]:
     """Chooses the launch shape of one ensemble launch by timing it: every

@@ -162,11 +162,27 @@ int hip_fail(hipError_t e, const char *what) {
 
 namespace tpfa {
 
+void fit_tile(int64_t nx, int64_t rows, int &tx, int &ty) {
+  const int64_t nxt = (nx + kDynMaxTx - 1) / kDynMaxTx;
+  tx = (int)std::max<int64_t>(kDynMinTx, (nx + nxt - 1) / nxt);
+  int t = 256 / tx;
+  if (2 * (tx + t) + 4 > 256) t = (256 - 4) / 2 - tx;
+  const int64_t nyt = (rows + t - 1) / t;
+  ty = (int)std::max<int64_t>(1, (rows + nyt - 1) / nyt);
+}
+
 void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
                const tpfa_state_t &st, int tile, int kz_chunk, int flags, int64_t y0,
                int64_t y1) {
   std::memset(&a, 0, sizeof(a));
-  const TileShape ts = kTiles[tile];
+  TileShape ts{0, 0, 256};
+  if (tile == kFitTile) {
+    fit_tile(g.nx, y1 - y0, ts.tx, ts.ty);
+    a.dtx = ts.tx;
+    a.dty = ts.ty;
+  } else {
+    ts = kTiles[tile];
+  }
   a.nx = (int32_t)g.nx;
   a.ny = (int32_t)g.ny;
   a.nz = (int32_t)g.nz;
@@ -176,7 +192,7 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.ntx = (int32_t)((g.nx + ts.tx - 1) / ts.tx);
   a.nty = (int32_t)((y1 - y0 + ts.ty - 1) / ts.ty);
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
-  a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : 0;
+  a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : (flags & TPFA_LAUNCH_Y_FAST) ? 2 : 0;
   a.tile = tile;
   a.ldx = (int32_t)pitch(g);
   a.plane = pitch(g) * g.ny;
@@ -243,21 +259,46 @@ int default_flags(tpfa::Mode mode, tpfa_precision_t prec, int form, int64_t cell
              : 0;
 }
 
-// Waves of one full residency of MI355X at 8 waves per SIMD (256 CUs x 4
-// SIMDs x 8).
-constexpr int64_t kFillWaves = 256 * 4 * 8;
-
-// Small grids: the default z chunk is halved (down to 4 planes) until a
-// single-grid launch has at least kFillWaves waves, so that the chip is
-// filled (256x256x128 FP32 residual: 0.054 -> 0.039 ms; 128x128x64: the
-// residual, VJP and Jacobian 1.6-2.4x faster). Every chunk size computes the
-// same values.
-int fill_kz(const tpfa_grid_t &g, int64_t rows, int tile, int kz) {
+// Small grids: a launch of the default z chunk that fills the GPU fewer than
+// four times over is re-chunked so that its last round of workgroups is as
+// full as possible. With C workgroups resident at once (the kernel's
+// occupancy from the runtime, or 8 waves per SIMD where no device answers)
+// and T tiles per chunk layer, the column is cut into L near-equal chunks of
+// kz = ceil(nz / L) planes, L chosen to maximise (T L / C) / ceil(T L / C)
+// (the used share of the launch's rounds) times kz / (kz + 2) (each chunk
+// also loads the plane below it and fills its pipeline); chunks range from
+// twice the default down to 4 planes. Measured: the FP32 residual + VJP on
+// 256x256x128 (2048 workgroups of 64x4 with 16-plane chunks against 1280
+// resident at 5 waves per SIMD) ran 0.075 ms, with 26-plane chunks (5 chunks,
+// one full round) 0.065 ms; the FP32 residual there 0.054 -> 0.039 ms. Every
+// chunk size computes the same values.
+int fill_kz(const tpfa_grid_t &g, int64_t rows, int tile, int kz, tpfa_precision_t prec,
+            int mode) {
   const tpfa::TileShape ts = tpfa::kTiles[tile];
   const int64_t tiles = ((g.nx + ts.tx - 1) / ts.tx) * ((rows + ts.ty - 1) / ts.ty);
-  const int64_t waves = ts.threads / 64;
-  while (kz > 4 && tiles * ((g.nz + kz - 1) / kz) * waves < kFillWaves) kz /= 2;
-  return kz;
+  int per_cu = 0, cus = 0;
+  if (!tpfa::march_residency(prec, mode, tile, per_cu, cus)) {
+    cus = 256;
+    per_cu = std::max(1, 4 * 8 / (ts.threads / 64));  // 8 waves per SIMD, 4 SIMDs per CU
+  }
+  const int64_t cap = (int64_t)cus * per_cu;
+  const int64_t nz = g.nz;
+  if (tiles * ((nz + kz - 1) / kz) >= 4 * cap) return kz;
+  int best_kz = kz;
+  double best = -1.0;
+  const int64_t l_lo = std::max<int64_t>(1, (nz + 2 * kz - 1) / (2 * kz));
+  const int64_t l_hi = std::max<int64_t>(l_lo, (nz + 3) / 4);
+  for (int64_t L = l_lo; L <= l_hi; ++L) {
+    const int64_t k = (nz + L - 1) / L;
+    const int64_t chunks = (nz + k - 1) / k;
+    const double rounds = (double)(tiles * chunks) / (double)cap;
+    const double score = rounds / std::ceil(rounds) * (double)k / (double)(k + 2);
+    if (score > best + 1e-9) {
+      best = score;
+      best_kz = (int)k;
+    }
+  }
+  return best_kz;
 }
 
 // `form`: 0 (permeability with ratios), MODE_TRANS or MODE_K3. `fill`: adapt
@@ -274,7 +315,7 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   if (launch && launch->kz_chunk > 0)
     kz = launch->kz_chunk;
   else
-    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form))
+    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form), prec, mode | form)
               : default_kz(mode, prec, form);
   // the FP32 kernels hold per-plane constants of their chunk in LDS
   if (prec == TPFA_FP32) kz = std::min(kz, tpfa::kMaxChunk32);
@@ -539,15 +580,14 @@ int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double 
   return ok();
 }
 
-int tpfa_stream_probe(int64_t n, tpfa_precision_t prec, const void *p, const void *k,
-                      const uint8_t *seal, void *out, void *stream) {
-  if (n <= 0) return fail(TPFA_ERR_SHAPE, "n must be positive");
+int tpfa_stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                      const void *k, const uint8_t *seal, void *out, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
   if (prec != TPFA_FP64 && prec != TPFA_FP32) return fail(TPFA_ERR_PARAM, "unknown precision");
   if (!p || !k || !seal || !out) return fail(TPFA_ERR_NULL, "p, k, seal and out are required");
-  if (n > std::numeric_limits<int64_t>::max() / 8 / 8)
-    return fail(TPFA_ERR_SHAPE, "8 * n elements overflow");
   const hipError_t e =
-      tpfa::launch_stream_probe(prec, n, p, k, seal, out, static_cast<hipStream_t>(stream));
+      tpfa::launch_stream_probe(prec, *grid, p, k, seal, out, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "probe launch");
   return ok();
 }
@@ -615,7 +655,12 @@ static hipError_t batch_capture(tpfa_batch *b) {
 // no allocation unless an error message is built).
 static int batch_model(const tpfa_model_t &md, int m, tpfa_precision_t prec,
                        tpfa_batch_mode_t mode, tpfa::Args &a) {
-  int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &md.launch);
+  // the fitted tile exists for ensemble members only: the launch checks see a
+  // default tile, its z chunk is the default one unless given
+  tpfa_launch_t ln = md.launch;
+  const bool fit = ln.tile == tpfa::kFitTile;
+  if (fit) ln.tile = -1;
+  int rc = check_common(&md.grid, &md.fluid, &md.rock, &md.state, prec, &ln);
   if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
   if (md.rock.tx || md.rock.ky)
     return fail(TPFA_ERR_UNSUPPORTED, "model " + std::to_string(m) +
@@ -629,14 +674,15 @@ static int batch_model(const tpfa_model_t &md, int m, tpfa_precision_t prec,
   int64_t y0, y1;
   resolve_launch(md.grid, mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN
                                                       : tpfa::MODE_RESIDUAL,
-                 prec, 0, &md.launch, tile, kz, flags, y0, y1, false);
-  // the ensemble kernels hold the tile bodies 0, 1, 2 (64x4, 32x8, 16x16);
-  // a default tile outside them (64x8 or 128x4) becomes 64x4
-  if (md.launch.tile < 0 && tile > 2) tile = 0;
-  if (tile > 2)
+                 prec, 0, &ln, tile, kz, flags, y0, y1, false);
+  // the ensemble kernels hold the tile bodies 0, 1, 2 (64x4, 32x8, 16x16) and
+  // the fitted tile; a default tile outside them (64x8 or 128x4) becomes 64x4
+  if (fit) tile = tpfa::kFitTile;
+  else if (ln.tile < 0 && tile > 2) tile = 0;
+  if (tile > 2 && tile != tpfa::kFitTile)
     return fail(TPFA_ERR_TILE, "model " + std::to_string(m) +
                                    ": batched tiles must be tile 0, 1 or 2 (64x4, 32x8, "
-                                   "16x16)");
+                                   "16x16) or TPFA_TILE_FIT");
   tpfa::make_args(a, md.grid, md.fluid, md.rock, md.state, tile, kz, flags, y0, y1);
   a.r = md.r;
   a.J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
@@ -855,6 +901,13 @@ int tpfa_resolve_launch(const tpfa_grid_t *grid, int op, tpfa_precision_t prec,
   } catch (...) {
     return fail(TPFA_ERR_HIP, "unknown exception");
   }
+}
+
+int tpfa_fit_tile_shape(int64_t nx, int64_t rows, int *tx, int *ty) {
+  if (nx <= 0 || rows <= 0) return fail(TPFA_ERR_SHAPE, "nx and rows must be positive");
+  if (!tx || !ty) return fail(TPFA_ERR_NULL, "tx and ty are required");
+  tpfa::fit_tile(nx, rows, *tx, *ty);
+  return ok();
 }
 
 int tpfa_num_tiles(void) { return tpfa::kNumTiles; }

@@ -57,6 +57,10 @@ struct TileShape {
 // difference), so their chunk is at most this many planes.
 constexpr int kMaxChunk32 = 128;
 constexpr int kNumTiles = 10;
+// Ensemble members may also take the fitted tile (id kFitTile): a tile of
+// dtx x dty cells fitted to the member's rows, 256 threads (see fit_tile).
+constexpr int kFitTile = 10;
+constexpr int kDynMinTx = 8, kDynMaxTx = 64;
 constexpr TileShape kTiles[kNumTiles] = {
     {64, 4, 256},  {32, 8, 256},  {16, 16, 256}, {64, 8, 512},  {128, 4, 512},
     {32, 16, 512}, {128, 2, 256}, {256, 1, 256}, {256, 2, 512}, {512, 1, 512}};
@@ -67,11 +71,12 @@ struct Args {
   int32_t nx, ny, nz;
   int32_t kz_chunk;   // z planes per workgroup
   int32_t ntx, nty, nzc;  // tiles along x, y and z chunks
-  int32_t remap;      // 1: XCD-aware workgroup order
+  int32_t remap;      // workgroup order: 0 natural, 1 XCD bands of tile rows, 2 y fastest
   int32_t tile;       // index into kTiles
   int32_t plain;      // 1: ordinary output stores (FP32 rows off 128-byte lines)
   int32_t y0, y1;     // rows computed and written: [y0, y1) (others are read only)
   int32_t ldx;        // row pitch of every array, in cells (>= nx)
+  int32_t dtx, dty;   // shape of the fitted tile (tile == kFitTile)
   int32_t pad0_;
   int64_t plane;      // ldx * ny
   int64_t nblocks;    // ntx * nty * nzc
@@ -114,6 +119,12 @@ struct Args {
   void *jv;           // J v (JVP modes)
 };
 
+// The fitted tile of a member of nx x ny cells per plane (rows [y0, y1)): tx
+// the row length of the fewest tiles of at most 64 cells covering a row, in
+// near-equal parts (at least 8); ty the most rows 256 threads hold (and that
+// one halo cell per thread covers the ring), then balanced over the rows.
+void fit_tile(int64_t nx, int64_t rows, int &tx, int &ty);
+
 // Fills the derived fields of `a` from the ABI structs (host only).
 void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_rock_t &rk,
                const tpfa_state_t &st, int tile, int kz_chunk, int flags, int64_t y0,
@@ -122,12 +133,16 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
 // Launchers (host). Return hipSuccess or the launch error.
 hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &a,
                         hipStream_t stream);
+// Workgroups of a single-grid kernel (mode kind | form flags, tile; FP32 with
+// non-temporal stores) resident per CU, and the CU count of the current
+// device; false where no device answers.
+bool march_residency(tpfa_precision_t prec, int mode, int tile, int &per_cu, int &cus);
 hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, double p_top,
                               double *pref, hipStream_t stream);
 hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
                          hipStream_t stream);
-hipError_t launch_stream_probe(tpfa_precision_t prec, int64_t n, const void *p, const void *k,
-                               const uint8_t *seal, void *out, hipStream_t stream);
+hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, const void *p,
+                               const void *k, const uint8_t *seal, void *out, hipStream_t stream);
 
 // Batched ensemble kernels (persistent and grouped schedules). The work list
 // is cut into one band per XCD; the persistent schedule keeps one claim
@@ -142,7 +157,7 @@ struct WorkItem {
   int32_t model;
   int32_t bx, by, kb;
 };
-// `tiles`: 0, 1, 2 when every model uses that 256-thread tile, 3 for a mix.
+// `tiles`: 0, 1, 2 or kFitTile when every model uses that 256-thread tile, 3 for a mix.
 hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
                              const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
                              int n_workgroups, hipStream_t stream);

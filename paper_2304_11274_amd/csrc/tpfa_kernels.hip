@@ -3,6 +3,7 @@
 // single-grid launches to the per-precision translation units. The tile
 // body they all share, and its design, is in tpfa_tile.h.
 #include <algorithm>
+#include <limits>
 #include <mutex>
 
 #include "tpfa_tile.h"
@@ -52,12 +53,15 @@ constexpr int persist_lds_bytes() {
   constexpr int a0 = tile_lds_bytes<S, MODE, 64, 4>();
   constexpr int a1 = tile_lds_bytes<S, MODE, 32, 8>();
   constexpr int a2 = tile_lds_bytes<S, MODE, 16, 16>();
+  constexpr int af = tile_lds_bytes<S, MODE, 0, 0>();
+  constexpr int m01 = a0 > a1 ? a0 : a1, m012 = m01 > a2 ? m01 : a2;
   return TILE == 0 ? a0
                    : TILE == 1 ? a1
-                               : TILE == 2 ? a2 : (a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2));
+                               : TILE == 2 ? a2
+                                           : TILE == kFitTile ? af : (m012 > af ? m012 : af);
 }
 
-// One work item of an ensemble. TILE = 0, 1, 2: every model uses that
+// One work item of an ensemble. TILE = 0, 1, 2, kFitTile: every model uses that
 // 256-thread tile (one code path, fewer registers); TILE = kMixedTiles: the
 // tile is read per model.
 template <class S, int MODE, int TILE>
@@ -68,10 +72,13 @@ __device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, cha
     march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem, tid);
   } else if constexpr (TILE == 2) {
     march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem, tid);
+  } else if constexpr (TILE == kFitTile) {
+    march_tile<S, MODE, 0, 0>(m, w.bx, w.by, w.kb, smem, tid);
   } else {
     switch (m.tile) {
       case 0: march_tile<S, MODE, 64, 4>(m, w.bx, w.by, w.kb, smem, tid); break;
       case 1: march_tile<S, MODE, 32, 8>(m, w.bx, w.by, w.kb, smem, tid); break;
+      case kFitTile: march_tile<S, MODE, 0, 0>(m, w.bx, w.by, w.kb, smem, tid); break;
       default: march_tile<S, MODE, 16, 16>(m, w.bx, w.by, w.kb, smem, tid); break;
     }
   }
@@ -278,6 +285,7 @@ static const void *static_fn(int tiles) {
     case 0: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 0>);
     case 1: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 1>);
     case 2: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, 2>);
+    case kFitTile: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, kFitTile>);
     default: return reinterpret_cast<const void *>(&static_grouped_kernel<S, MODE, kMixedTiles>);
   }
 }
@@ -298,51 +306,95 @@ hipError_t launch_static_grouped(tpfa_precision_t prec, Mode mode, int tiles, vo
 
 // ----------------------------------------------------------------------------
 // Bandwidth probe: the memory traffic of the Jacobian kernels without their
-// arithmetic. Per cell it reads p and k (one element each) and the seal byte
-// and writes eight planes, out[q][c] = p[c] + (q + seal[c]) k[c] (so that
-// no load is dead), with coalesced non-temporal stores. Each workgroup takes
-// runs of kProbeRun consecutive cells (one per lane, kProbeRun / 256 per
-// lane), so every plane is written in long contiguous runs, as a tile row of
-// the march kernels writes them; the grid strides over the runs.
+// arithmetic and without their halo, in the access pattern that measured
+// fastest for it on MI355X among tile marches (64 x 8 and 128 x 8 column
+// blocks, one or two cells per lane) and grid-stride loops (one or two cells
+// per lane, 8k or 32k workgroups): each 512-thread workgroup owns a 128 x 8
+// block of columns, two consecutive x cells per lane (16-byte FP64 accesses),
+// and marches it through a chunk of 32 planes; per plane each lane reads p, k
+// and the seal bytes of its cells and writes eight output planes,
+// out[q][c] = p[c] + (q + seal[c]) k[c] (so that no load is dead), with
+// non-temporal stores. Rows of odd pitch take one cell per access.
 // ----------------------------------------------------------------------------
-constexpr int kProbeThreads = 256;
-constexpr int kProbeRun = 1024;
+constexpr int kProbeTx = 128, kProbeTy = 8, kProbeChunk = 32;
 
 template <class S>
-__global__ void __launch_bounds__(kProbeThreads)
-    stream_probe_kernel(int64_t n, const S *__restrict__ p, const S *__restrict__ k,
+using vec2_t = S __attribute__((ext_vector_type(2)));
+
+template <class S, bool PAIR>
+__global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
+    stream_probe_kernel(int nx, int ny, int nz, int ldx, int ntx, int nty,
+                        const S *__restrict__ p, const S *__restrict__ k,
                         const uint8_t *__restrict__ seal, S *__restrict__ out) {
-  for (int64_t base = (int64_t)blockIdx.x * kProbeRun; base < n;
-       base += (int64_t)gridDim.x * kProbeRun) {
+  const uint32_t b = blockIdx.x, r1 = b / (uint32_t)ntx, r2 = r1 / (uint32_t)nty;
+  const int lanes = kProbeTx / 2;
+  const int i = (int)(b - r1 * ntx) * kProbeTx + 2 * (int)(threadIdx.x % lanes);
+  const int j = (int)(r1 - r2 * nty) * kProbeTy + (int)(threadIdx.x / lanes);
+  if (i >= nx || j >= ny) return;
+  const bool two = i + 1 < nx;
+  const int kb = (int)r2 * kProbeChunk, ke = min(kb + kProbeChunk, nz);
+  const size_t plane = (size_t)ldx * ny, nc = plane * nz;
+  size_t c = (size_t)j * ldx + i + (size_t)kb * plane;
+#pragma unroll 2
+  for (int kk = kb; kk < ke; ++kk, c += plane) {
+    if (PAIR && two) {
+      const vec2_t<S> pc = *(const vec2_t<S> *)(p + c), kc = *(const vec2_t<S> *)(k + c);
+      const uint32_t sc = *(const uint16_t *)(seal + c);
 #pragma unroll
-    for (int u = 0; u < kProbeRun / kProbeThreads; ++u) {
-      const int64_t c = base + u * kProbeThreads + threadIdx.x;
-      if (c < n) {
-        const S pc = p[c], kc = k[c];
-        const int sc = seal[c];
+      for (int q = 0; q < 8; ++q) {
+        vec2_t<S> v;
+        v.x = pc.x + S(q + (int)(sc & 255u)) * kc.x;
+        v.y = pc.y + S(q + (int)(sc >> 8)) * kc.y;
+        __builtin_nontemporal_store(v, (gptr<vec2_t<S>>)(out + q * nc + c));
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (e == 1 && !two) break;
+        const S pc = p[c + e], kc = k[c + e];
+        const int sc = seal[c + e];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          __builtin_nontemporal_store(pc + S(q + sc) * kc, (gptr<S>)(out + q * n + c));
+          __builtin_nontemporal_store(pc + S(q + sc) * kc, (gptr<S>)(out + q * nc + c + e));
       }
     }
   }
 }
 
-hipError_t launch_stream_probe(tpfa_precision_t prec, int64_t n, const void *p, const void *k,
-                               const uint8_t *seal, void *out, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  // 256 CUs x 8 workgroups of 256 threads fill the chip; at most one pass of
-  // runs when the array is smaller
-  const int64_t runs = (n + kProbeRun - 1) / kProbeRun;
-  const unsigned grid = (unsigned)std::min<int64_t>(runs, 256 * 8 * 4);
-  if (prec == TPFA_FP64)
-    stream_probe_kernel<double><<<grid, kProbeThreads, 0, st>>>(
-        n, static_cast<const double *>(p), static_cast<const double *>(k), seal,
-        static_cast<double *>(out));
-  else
-    stream_probe_kernel<float><<<grid, kProbeThreads, 0, st>>>(
-        n, static_cast<const float *>(p), static_cast<const float *>(k), seal,
-        static_cast<float *>(out));
+hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, const void *p,
+                               const void *k, const uint8_t *seal, void *out, hipStream_t st) {
+  const int ntx = (int)((g.nx + kProbeTx - 1) / kProbeTx);
+  const int nty = (int)((g.ny + kProbeTy - 1) / kProbeTy);
+  const int64_t nzc = (g.nz + kProbeChunk - 1) / kProbeChunk;
+  const int64_t blocks = (int64_t)ntx * nty * nzc;
+  if (blocks > (int64_t)std::numeric_limits<uint32_t>::max()) return hipErrorInvalidValue;
+  const int ldx = (int)(g.ldx ? g.ldx : g.nx);
+  const size_t elem = prec == TPFA_FP64 ? 8 : 4;
+  // paired accesses need every pair of cells (even offset) aligned to 2 elements
+  bool pair = ldx % 2 == 0 && reinterpret_cast<uintptr_t>(seal) % 2 == 0;
+  for (const void *q : {p, k, (const void *)out})
+    if (reinterpret_cast<uintptr_t>(q) % (2 * elem) != 0) pair = false;
+  const dim3 grid((unsigned)blocks), block(kProbeTx / 2 * kProbeTy);
+  const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+  if (prec == TPFA_FP64) {
+    const double *pp = static_cast<const double *>(p), *kk = static_cast<const double *>(k);
+    double *oo = static_cast<double *>(out);
+    if (pair)
+      stream_probe_kernel<double, true><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
+                                                                  seal, oo);
+    else
+      stream_probe_kernel<double, false><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp,
+                                                                   kk, seal, oo);
+  } else {
+    const float *pp = static_cast<const float *>(p), *kk = static_cast<const float *>(k);
+    float *oo = static_cast<float *>(out);
+    if (pair)
+      stream_probe_kernel<float, true><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
+                                                                 seal, oo);
+    else
+      stream_probe_kernel<float, false><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
+                                                                  seal, oo);
+  }
   return hipGetLastError();
 }
 
@@ -357,6 +409,40 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
   if (prec == TPFA_FP64) return launch_march_f64(kind, form, tile, a, st);
   return a.plain ? launch_march_f32_plain(kind, form, tile, a, st)
                  : launch_march_f32(kind, form, tile, a, st);
+}
+
+// Residency of the single-grid kernels, from the runtime's occupancy query on
+// the first use of each kernel (cached: the library runs on one device type).
+bool march_residency(tpfa_precision_t prec, int mode, int tile, int &per_cu, int &cus) {
+  static std::mutex mu;
+  static int cache[2][3][8][kNumTiles];  // 0 unknown, -1 no answer, else workgroups per CU
+  static int cu_count = 0;
+  const int kind = mode_kind(mode);
+  const int form = has_trans(mode) ? 1 : has_k3(mode) ? 2 : 0;
+  if (tile < 0 || tile >= kNumTiles) return false;
+  std::lock_guard<std::mutex> lock(mu);
+  int &slot = cache[prec == TPFA_FP64 ? 0 : 1][form][kind][tile];
+  if (slot == 0) {
+    const int fl = mode & (MODE_TRANS | MODE_K3);
+    const void *fn = prec == TPFA_FP64 ? march_kernel_f64(kind, fl, tile)
+                                       : march_kernel_f32(kind, fl, tile);
+    int dev = 0, n = 0, c = 0;
+    if (fn && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kTiles[tile].threads, 0) ==
+            hipSuccess &&
+        n > 0 && c > 0) {
+      slot = n;
+      cu_count = c;
+    } else {
+      (void)hipGetLastError();
+      slot = -1;
+    }
+  }
+  if (slot < 0) return false;
+  per_cu = slot;
+  cus = cu_count;
+  return true;
 }
 
 // One workgroup per work item, dispatched by the hardware: the alternative
@@ -380,6 +466,7 @@ static const void *grouped_fn(int tiles) {
     case 0: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 0>);
     case 1: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 1>);
     case 2: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, 2>);
+    case kFitTile: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, kFitTile>);
     default: return reinterpret_cast<const void *>(&grouped_kernel<S, MODE, kMixedTiles>);
   }
 }
@@ -403,6 +490,7 @@ static const void *persist_fn(int tiles) {
     case 0: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 0>);
     case 1: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 1>);
     case 2: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, 2>);
+    case kFitTile: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, kFitTile>);
     default: return reinterpret_cast<const void *>(&persistent_kernel<S, MODE, kMixedTiles>);
   }
 }

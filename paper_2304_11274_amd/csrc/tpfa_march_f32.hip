@@ -13,4 +13,13 @@ hipError_t launch_march_f32(int kind, int form, int tile, const Args &a, hipStre
   }
 }
 
+const void *march_kernel_f32(int kind, int form, int tile) {
+  switch (form) {
+    case 0: return kernel_kind<float, 0>(kind, tile);
+    case MODE_TRANS: return kernel_kind<float, MODE_TRANS>(kind, tile);
+    case MODE_K3: return kernel_kind<float, MODE_K3>(kind, tile);
+    default: return nullptr;
+  }
+}
+
 }  // namespace tpfa

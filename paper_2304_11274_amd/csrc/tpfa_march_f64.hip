@@ -13,4 +13,13 @@ hipError_t launch_march_f64(int kind, int form, int tile, const Args &a, hipStre
   }
 }
 
+const void *march_kernel_f64(int kind, int form, int tile) {
+  switch (form) {
+    case 0: return kernel_kind<double, 0>(kind, tile);
+    case MODE_TRANS: return kernel_kind<double, MODE_TRANS>(kind, tile);
+    case MODE_K3: return kernel_kind<double, MODE_K3>(kind, tile);
+    default: return nullptr;
+  }
+}
+
 }  // namespace tpfa

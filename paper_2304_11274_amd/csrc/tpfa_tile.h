@@ -299,9 +299,27 @@ constexpr int share_lds_bytes() {
 }
 template <class S, int MODE, int TX, int TY>
 constexpr bool tile_shares() {
-  return (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) && sizeof(S) == 8 &&
+  return TX > 0 &&
+         (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) && sizeof(S) == 8 &&
          !has_k3(MODE) && share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
+
+// The fitted tile of the ensemble kernels (TX = TY = 0 in the templates): its
+// shape comes from the model's arguments (dtx x dty, 8 <= dtx <= 64,
+// dtx dty <= 256, 2 (dtx + dty) + 4 <= 256 so that one halo cell per thread
+// covers the ring) and runs on 256 threads. Its LDS planes hold the largest
+// such (dtx + 2)(dty + 2), plus one spare slot that idle threads stage into.
+constexpr int dyn_max_hw() {
+  int m = 0;
+  for (int tx = kDynMinTx; tx <= kDynMaxTx; ++tx) {
+    int ty = 256 / tx;
+    if (2 * (tx + ty) + 4 > 256) ty = (256 - 4) / 2 - tx;
+    const int hw = (tx + 2) * (ty + 2);
+    m = hw > m ? hw : m;
+  }
+  return m + 1;
+}
+constexpr int kDynHW = dyn_max_hw();
 
 // FP32 form: per-plane constants of the chunk (planes kb-1 .. kb+chunk), at
 // the start of the tile's LDS: the hydrostatic part of each z face's potential
@@ -319,7 +337,7 @@ constexpr int plane_lds_bytes() {
 // per-plane constants.
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
-  constexpr int HW = (TX + 2) * (TY + 2);
+  constexpr int HW = TX > 0 ? (TX + 2) * (TY + 2) : kDynHW;
   constexpr int B = base_mode(MODE);
   constexpr int arrays = 3 + (B == MODE_VJP || B == MODE_JVP ? 1 : 0) +
                          (mode_kind(MODE) == MODE_RES10 ? 2 : 0) +
@@ -408,19 +426,32 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
     double gp = 0.0, gm = 0.0, gq[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < 6; ++n) {
-      const double d = (double)c0.w - (double)wn[n];
-      if (n & 1) {  // own cell is Lo
-        gp = fma(d, (double)f[n].dLo, gp);
+      if constexpr (sizeof(S) == 4) {
+        // FP32 form: each term is a float product (relative error a few 1e-7
+        // of the term), summed in FP64
+        const float d = (n & 1) ? c0.w - wn[n] : wn[n] - c0.w;
+        const float tp = d * ((n & 1) ? f[n].dLo : f[n].dUp);
+        const float tm = d * (f[n].F * ((n & 1) ? f[n].qUp : f[n].qLo));
+        gp = gp + (double)tp;
         if constexpr (has_k3(MODE))
-          gq[n >> 1] = fma(d, (double)(f[n].F * f[n].qUp), gq[n >> 1]);
+          gq[n >> 1] = gq[n >> 1] + (double)tm;
         else if constexpr (!has_trans(MODE))
-          gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
-      } else {      // own cell is Up
-        gp = fma(-d, (double)f[n].dUp, gp);
-        if constexpr (has_k3(MODE))
-          gq[n >> 1] = fma(-d, (double)(f[n].F * f[n].qLo), gq[n >> 1]);
-        else if constexpr (!has_trans(MODE))
-          gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
+          gm = gm + (double)tm;
+      } else {
+        const double d = (double)c0.w - (double)wn[n];
+        if (n & 1) {  // own cell is Lo
+          gp = fma(d, (double)f[n].dLo, gp);
+          if constexpr (has_k3(MODE))
+            gq[n >> 1] = fma(d, (double)(f[n].F * f[n].qUp), gq[n >> 1]);
+          else if constexpr (!has_trans(MODE))
+            gm = fma(d, (double)(f[n].F * f[n].qUp), gm);
+        } else {      // own cell is Up
+          gp = fma(-d, (double)f[n].dUp, gp);
+          if constexpr (has_k3(MODE))
+            gq[n >> 1] = fma(-d, (double)(f[n].F * f[n].qLo), gq[n >> 1]);
+          else if constexpr (!has_trans(MODE))
+            gm = fma(-d, (double)(f[n].F * f[n].qLo), gm);
+        }
       }
     }
     if (a.gp) st_out<MODE>(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
@@ -538,7 +569,9 @@ __device__ __forceinline__ void fill_plane_constants(const Args &a, int kb, int 
 
 template <class S, int MODE, int TX, int TY>
 struct Tile {
-  static constexpr int W = TX + 2, H = TY + 2, HW = W * H;
+  // TX = TY = 0: the fitted tile, its shape read from the arguments at run time
+  static constexpr bool DYN = TX == 0;
+  static constexpr int W = TX + 2, H = TY + 2, HW = DYN ? kDynHW : W * H;
   static constexpr int BASE = base_mode(MODE);
   static constexpr bool ACC = has_accumulation(MODE);
   static constexpr bool VJP = BASE == MODE_VJP;
@@ -552,9 +585,9 @@ struct Tile {
   static constexpr bool K3 = has_k3(MODE);      // per-direction permeability arrays
   static constexpr bool YF = TIN || K3;         // a y-face field is staged (t_y or k_y)
   static constexpr bool SHARE = tile_shares<S, MODE, TX, TY>();
-  static constexpr int NT = TX * TY;          // threads
+  static constexpr int NT = DYN ? 256 : TX * TY;  // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
-  static constexpr int HC = (NH + NT - 1) / NT;  // halo cells staged per thread
+  static constexpr int HC = DYN ? 1 : (NH + NT - 1) / NT;  // halo cells staged per thread
   // Halo cells are loaded one plane ahead; the FP32 Jacobian (short planes,
   // few registers) loads them two planes ahead, which measured faster on
   // MI355X there and slower everywhere else.
@@ -586,12 +619,27 @@ struct Tile {
   int hl[HC];          // its LDS slot, -1 if the thread stages no q-th halo cell
   uint32_t hb[HC], hs[HC];
   S A2x, A2y;
+  int dtx, dty, dw, dhw;  // fitted tile: shape, LDS row width and plane stride
+
+  // the tile's shape: compile-time constants, or the fitted tile's
+  __device__ __forceinline__ int tx_() const { if constexpr (DYN) return dtx; else return TX; }
+  __device__ __forceinline__ int ty_() const { if constexpr (DYN) return dty; else return TY; }
+  __device__ __forceinline__ int w_() const { if constexpr (DYN) return dw; else return W; }
+  __device__ __forceinline__ int hw_() const { if constexpr (DYN) return dhw; else return HW; }
 
   __device__ __forceinline__ Tile(const Args &a_, int bx, int by, int kb_, char *smem, int tid_)
       : a(a_) {
+    if constexpr (DYN) {
+      dtx = a.dtx;
+      dty = a.dty;
+      dw = dtx + 2;
+      dhw = dw * (dty + 2) + 1;  // + the spare slot of idle threads
+    }
     s_hk = reinterpret_cast<double *>(smem);
     s_rk = reinterpret_cast<float *>(s_hk + kPlaneSlots);
     smem += plane_lds_bytes<S>();
+    // arrays of two plane buffers each, HW apart (the largest fitted plane for
+    // the fitted tile, whose planes take hw_() slots)
     s_p = reinterpret_cast<S *>(smem);
     s_k = s_p + 2 * HW;
     s_l = s_k + 2 * HW;
@@ -611,19 +659,23 @@ struct Tile {
     ke = min(kb + a.kz_chunk, nz);
     plane = (size_t)a.plane;
     const int tid = tid_;
-    const int tx = tid % TX, ty = tid / TX;
+    const int TXv = tx_(), TYv = ty_(), Wv = w_();
+    const int tx = tid % TXv, ty = tid / TXv;
+    // threads beyond the fitted tile's cells own no cell (they stage halo
+    // cells only, and their own value into a spare slot)
+    const bool active = !DYN || ty < TYv;
     // tile rows start at the launch's first row y0; rows of the grid outside
     // [y0, y1) are read as neighbours (a halo) but not written
-    const int jb = a.y0 + by * TY;
-    const int i = bx * TX + tx, j = jb + ty;
-    inside = i < nx && j < ny;
+    const int jb = a.y0 + by * TYv;
+    const int i = bx * TXv + tx, j = jb + ty;
+    inside = active && i < nx && j < ny;
     own = inside && j < a.y1;
     tnv = inside && i + 1 < nx && j + 1 < ny;
     txv = inside && i + 1 < nx;
     tyv = inside && j + 1 < ny;
     tsv = inside && i + 1 < nx && j >= 1;
     const uint32_t col = inside ? (uint32_t)j * ldx + (uint32_t)i : 0u;
-    ol = (ty + 1) * W + tx + 1;
+    ol = active ? (ty + 1) * Wv + tx + 1 : hw_() - 1;
     cb = col * (uint32_t)sizeof(S);
     cs = col;
     // halo ring: bottom row, top row, left column, right column
@@ -633,35 +685,36 @@ struct Tile {
       int hi = -1, hj = -1, l = -1;
       uint32_t role = 0;  // faces into the tile whose lower cell is this halo cell
       uint32_t need = 0;  // fields those faces (and the tile's faces towards it) read
-      if (h < TX) {  // bottom row: +y (and +x+y) faces
-        hi = bx * TX + h;
+      const int NHv = 2 * (TXv + TYv) + (R10 ? 4 : 0);
+      if (h < TXv) {  // bottom row: +y (and +x+y) faces
+        hi = bx * TXv + h;
         hj = jb - 1;
         l = h + 1;
         role = kPY | (R10 ? kNE : 0u);
         need = (K3 ? kNeedKy : kNeedK) | kNeedSeal | kNeedTy | kNeedTn | kNeedW;
-      } else if (h < 2 * TX) {  // top row: +x-y faces
-        hi = bx * TX + h - TX;
-        hj = jb + TY;
-        l = (TY + 1) * W + h - TX + 1;
+      } else if (h < 2 * TXv) {  // top row: +x-y faces
+        hi = bx * TXv + h - TXv;
+        hj = jb + TYv;
+        l = (TYv + 1) * Wv + h - TXv + 1;
         role = R10 ? kSE : 0u;
         need = (K3 ? kNeedKy : kNeedK) | kNeedTs | kNeedW;
-      } else if (h < 2 * TX + TY) {  // left column: +x (and both diagonal) faces
-        hi = bx * TX - 1;
-        hj = jb + h - 2 * TX;
-        l = (h - 2 * TX + 1) * W;
+      } else if (h < 2 * TXv + TYv) {  // left column: +x (and both diagonal) faces
+        hi = bx * TXv - 1;
+        hj = jb + h - 2 * TXv;
+        l = (h - 2 * TXv + 1) * Wv;
         role = kPX | (R10 ? kNE | kSE : 0u);
         need = kNeedK | kNeedSeal | kNeedTx | kNeedTn | kNeedTs | kNeedW;
-      } else if (h < 2 * TX + 2 * TY) {  // right column: none (the tile's lower cells)
-        hi = bx * TX + TX;
-        hj = jb + h - 2 * TX - TY;
-        l = (h - 2 * TX - TY + 1) * W + TX + 1;
+      } else if (h < 2 * TXv + 2 * TYv) {  // right column: none (the tile's lower cells)
+        hi = bx * TXv + TXv;
+        hj = jb + h - 2 * TXv - TYv;
+        l = (h - 2 * TXv - TYv + 1) * Wv + TXv + 1;
         need = kNeedK | kNeedW;
-      } else if (h < NH) {  // corners (10-flux stencil)
-        const int c = h - 2 * TX - 2 * TY;
+      } else if (h < NHv) {  // corners (10-flux stencil)
+        const int c = h - 2 * TXv - 2 * TYv;
         const int cx = c & 1, cy = c >> 1;
-        hi = cx ? bx * TX + TX : bx * TX - 1;
-        hj = cy ? jb + TY : jb - 1;
-        l = (cy ? TY + 1 : 0) * W + (cx ? TX + 1 : 0);
+        hi = cx ? bx * TXv + TXv : bx * TXv - 1;
+        hj = cy ? jb + TYv : jb - 1;
+        l = (cy ? TYv + 1 : 0) * Wv + (cx ? TXv + 1 : 0);
         role = c == 0 ? kNE : c == 2 ? kSE : 0u;
         need = c == 0 ? kNeedTn : c == 2 ? kNeedTs : 0u;
       }
@@ -781,7 +834,7 @@ struct Tile {
                                        const Cell<S> &c1, Props<S> &d1, Cell<S> &c2,
                                        const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
                                        Cell<S> (&h2)[HC], const Face<S> &zm, Face<S> &zp) const {
-    const int b = ((k - kb) & 1) * HW;
+    const int b = ((k - kb) & 1) * hw_();
     const bool has_pz = k + 1 < nz;
     const S rkk = rk(k);
     if (k + 2 < nz && k + 2 <= ke) load(c2, k + 2);
@@ -828,7 +881,8 @@ struct Tile {
     // whose neighbour does not exist has T = 0 and contributes exact zeros
     Face<S> f[6];
     S wn[6];
-    const int sl[4] = {ol - 1, ol + 1, ol - W, ol + W};
+    const int Wv = w_();
+    const int sl[4] = {ol - 1, ol + 1, ol - Wv, ol + Wv};
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const int axis = n >> 1;
@@ -868,7 +922,7 @@ struct Tile {
     // (i,j)-(i+1,j-1)), staged as 0 where the face does not exist
     S fd[4] = {};
     if constexpr (R10) {
-      const int dsl[4] = {ol - W - 1, ol + W + 1, ol - W + 1, ol + W - 1};
+      const int dsl[4] = {ol - Wv - 1, ol + Wv + 1, ol - Wv + 1, ol + Wv - 1};
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
         const int q = b + dsl[n];
@@ -941,6 +995,7 @@ struct Tile {
                                              const Cell<S> (&h0)[HC], Cell<S> (&h1)[HC],
                                              Cell<S> (&h2)[HC], const Face<S> &zm, Face<S> &zp,
                                              Pending<S> &pd) const {
+    static_assert(!DYN, "the fitted tile uses the two-sided form");
     const int b = ((k - kb) & 1) * HW;
     const bool has_pz = k + 1 < nz;
     const S rkk = rk(k);
@@ -1070,6 +1125,16 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
 // the emulated 64-bit divisions that made most of the workgroup prologue.
 __device__ __forceinline__ void decode_tile(const Args &a, uint32_t b, int &bx, int &by, int &kb) {
   const uint32_t ntx = (uint32_t)a.ntx, nty = (uint32_t)a.nty;
+  if (a.remap == 2) {
+    // y-fast order: consecutive ids walk a tile column, so a tile's x
+    // neighbours are nty ids away: on the same XCD when nty is a multiple of
+    // 8, and dispatched close enough to be resident together
+    const uint32_t r1 = b / nty, r2 = r1 / ntx;
+    by = (int)(b - r1 * nty);
+    bx = (int)(r1 - r2 * ntx);
+    kb = (int)r2 * a.kz_chunk;
+    return;
+  }
   uint32_t t = b;
   if (a.remap) {
     const uint32_t C = ntx * nty;  // tiles per z chunk
@@ -1116,6 +1181,38 @@ static hipError_t launch_t(int tile, const Args &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The kernel of one mode and tile shape (for occupancy queries).
+template <class S, int MODE>
+static const void *kernel_t(int tile) {
+  switch (tile) {
+    case 0: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 64, 4>);
+    case 1: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 32, 8>);
+    case 2: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 16, 16>);
+    case 3: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 64, 8>);
+    case 4: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 128, 4>);
+    case 5: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 32, 16>);
+    case 6: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 128, 2>);
+    case 7: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 256, 1>);
+    case 8: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 256, 2>);
+    case 9: return reinterpret_cast<const void *>(&march_kernel<S, MODE, 512, 1>);
+    default: return nullptr;
+  }
+}
+template <class S, int F>
+static const void *kernel_kind(int kind, int tile) {
+  switch (kind) {
+    case MODE_RESIDUAL: return kernel_t<S, MODE_RESIDUAL | F>(tile);
+    case MODE_JACOBIAN: return kernel_t<S, MODE_JACOBIAN | F>(tile);
+    case MODE_VJP: return kernel_t<S, MODE_VJP | F>(tile);
+    case MODE_RES10: return kernel_t<S, MODE_RES10 | F>(tile);
+    case MODE_RESIDUAL_BE: return kernel_t<S, MODE_RESIDUAL_BE | F>(tile);
+    case MODE_JACOBIAN_BE: return kernel_t<S, MODE_JACOBIAN_BE | F>(tile);
+    case MODE_JVP: return kernel_t<S, MODE_JVP | F>(tile);
+    case MODE_JVP_BE: return kernel_t<S, MODE_JVP_BE | F>(tile);
+    default: return nullptr;
+  }
+}
+
 // Every mode kind with the flags F (MODE_TRANS or MODE_K3, MODE_PLAIN) of one
 // instance set.
 template <class S, int F>
@@ -1139,5 +1236,8 @@ static hipError_t launch_kind(int kind, int tile, const Args &a, hipStream_t st)
 hipError_t launch_march_f64(int kind, int form, int tile, const Args &a, hipStream_t st);
 hipError_t launch_march_f32(int kind, int form, int tile, const Args &a, hipStream_t st);
 hipError_t launch_march_f32_plain(int kind, int form, int tile, const Args &a, hipStream_t st);
+// The kernels those launch (non-temporal store kind for FP32).
+const void *march_kernel_f64(int kind, int form, int tile);
+const void *march_kernel_f32(int kind, int form, int tile);
 
 }  // namespace tpfa

@@ -163,19 +163,23 @@ def test_helpers_validation(lib):
 
 
 def test_stream_probe_validation(lib):
-    assert lib.tpfa_stream_probe(0, L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
-        L.TPFA_ERR_SHAPE
-    assert lib.tpfa_stream_probe(10, 7, DUMMY, DUMMY, DUMMY, DUMMY, None) == L.TPFA_ERR_PARAM
+    g, _, _, _ = good()
+    assert lib.tpfa_stream_probe(None, L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
+        L.TPFA_ERR_NULL
+    assert lib.tpfa_stream_probe(C.byref(g), 7, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
+        L.TPFA_ERR_PARAM
     for q in range(4):
         ptrs = [DUMMY] * 4
         ptrs[q] = None
-        assert lib.tpfa_stream_probe(10, L.TPFA_FP32, *ptrs, None) == L.TPFA_ERR_NULL
-    assert lib.tpfa_stream_probe(2 ** 62, L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
+        assert lib.tpfa_stream_probe(C.byref(g), L.TPFA_FP32, *ptrs, None) == L.TPFA_ERR_NULL
+    g.nz = 0
+    assert lib.tpfa_stream_probe(C.byref(g), L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
         L.TPFA_ERR_SHAPE
     import torch
-    t = torch.zeros(8, dtype=torch.float64)
+    import geomodel
+    t = torch.zeros((2, 2, 2), dtype=torch.float64)
     with pytest.raises(ValueError):
-        tp.stream_probe(t, t, t.to(torch.uint8))   # host tensors
+        tp.stream_probe(geomodel.Grid(2, 2, 2), t, t, t.to(torch.uint8))   # host tensors
 
 
 def test_noalloc_run_validation(lib):

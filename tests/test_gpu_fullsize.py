@@ -221,8 +221,10 @@ def test_fullsize_ensemble(gpu, orc):
     ens.run()
     torch.cuda.synchronize()
     for q, (m, geo) in enumerate(zip(members, models)):
+        # the fitted tile (10) is for ensemble members only; results never depend on the tile
         r, J = gpu.jacobian(m["grid"], m["fluid"], m["kx"], m["p"], seal=m["seal"],
-                            pref=m["pref"], ry=m["ry"], rz=m["rz"], tile=m["tile"],
+                            pref=m["pref"], ry=m["ry"], rz=m["rz"],
+                            tile=None if m["tile"] == 10 else m["tile"],
                             kz_chunk=m["kz_chunk"])
         torch.cuda.synchronize()
         assert torch.equal(ens.r[q], r) and torch.equal(ens.J[q], J), q

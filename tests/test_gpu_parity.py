@@ -81,6 +81,8 @@ def test_fp64_kz_chunks_bitwise(gpu, orc, kz):
     assert np.array_equal(r, r0) and np.array_equal(J, J0)
     r, J = fp64_run(gpu, geo, p, kz_chunk=kz, xcd_remap=True)
     assert np.array_equal(r, r0) and np.array_equal(J, J0)
+    r, J = fp64_run(gpu, geo, p, kz_chunk=kz, xcd_remap="yfast")
+    assert np.array_equal(r, r0) and np.array_equal(J, J0)
 
 
 def test_fp64_tiny16_workload(gpu, orc):

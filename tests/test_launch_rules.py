@@ -1,10 +1,11 @@
 """The library's default launch rules, read through tpfa_resolve_launch on the
 host (no GPU): tile shape by mode, precision, rock form and row alignment; the
-z chunk by mode and its shortening on small grids (the launch must hold at
-least one full residency of the chip, 256 CUs x 4 SIMDs x 8 waves); the XCD
+z chunk by mode and its re-chunking on small grids (the last round of
+workgroups as full as possible); the XCD
 band order by size, precision and form; row ranges; explicit launches taken as
 given; argument errors."""
 import ctypes as C
+import math
 
 import pytest
 import torch
@@ -56,10 +57,28 @@ def test_narrow_grids_and_the_10_flux_stencil():
     assert rl(geomodel.Grid(100, 100, 50), "residual10", F32)["shape"] == (64, 4)
 
 
-def full_residency_waves(r, grid, rows):
-    tx, ty = r["shape"]
+def rounds_rule(grid, rows, shape, threads, default):
+    """The documented chunk rule for small grids, with 8 waves per SIMD (what
+    the library assumes where no device answers, as here): 256 CUs x 32 / waves
+    per workgroup resident; the launch of the default chunk is kept when it
+    fills the GPU four times over, otherwise L near-equal chunks maximise
+    (T L / C) / ceil(T L / C) x kz / (kz + 2), L from nz / (2 default) to nz / 4."""
+    tx, ty = shape
     tiles = -(-grid.nx // tx) * -(-rows // ty)
-    return tiles * -(-grid.nz // r["kz_chunk"]) * (r["threads"] // 64)
+    cap = 256 * max(1, 32 // (threads // 64))
+    nz = grid.nz
+    if tiles * -(-nz // default) >= 4 * cap:
+        return default
+    best, best_kz = -1.0, default
+    lo = max(1, -(-nz // (2 * default)))
+    for L in range(lo, max(lo, -(-nz // 4)) + 1):
+        k = -(-nz // L)
+        chunks = -(-nz // k)
+        rounds = tiles * chunks / cap
+        score = rounds / math.ceil(rounds) * k / (k + 2)
+        if score > best + 1e-9:
+            best, best_kz = score, k
+    return best_kz
 
 
 @pytest.mark.parametrize("shape,op,dtype,default,kz", [
@@ -68,16 +87,17 @@ def full_residency_waves(r, grid, rows):
     ((128, 128, 64), "residual", F32, 32, 4),
     ((128, 128, 64), "jacobian", F64, 32, 4),
     ((512, 512, 256), "jacobian", F64, 32, 32),
+    ((300, 200, 90), "vjp", F32, 16, 12),
+    ((64, 64, 200), "jacobian", F32, 32, 4),
 ])
-def test_small_grids_get_shorter_chunks(shape, op, dtype, default, kz):
-    """The default chunk is halved, down to 4 planes, until the launch holds a
-    full residency; a chunk shorter than the default is the longest that does."""
+def test_small_grids_get_round_filling_chunks(shape, op, dtype, default, kz):
+    """Small grids: the chunk that fills the launch's last round best (the
+    rule above, under the CPU's assumed occupancy); large grids keep the
+    default."""
     g = geomodel.Grid(*shape)
     r = rl(g, op, dtype)
     assert r["kz_chunk"] == kz
-    assert full_residency_waves(r, g, g.ny) >= 8192 or kz == 4
-    if kz < default:
-        assert full_residency_waves(dict(r, kz_chunk=2 * kz), g, g.ny) < 8192
+    assert kz == rounds_rule(g, g.ny, r["shape"], r["threads"], default)
 
 
 def test_band_order_by_size_precision_and_form():
@@ -167,3 +187,25 @@ def test_batch_refuses_tiles_the_ensemble_kernels_do_not_hold(tile, want):
     assert lib.tpfa_batch_create(arr, 1, L.TPFA_FP64, 1, C.byref(h), None) == want
     assert not h.value
     assert b"tile 0, 1 or 2" in lib.tpfa_last_error()
+
+
+def test_fitted_tile_shapes():
+    """The ensemble's fitted tile: the fewest tiles of at most 64 cells per row,
+    in near-equal parts of at least 8 cells; at most 256 cells and a halo ring
+    one cell per thread covers; rows balanced."""
+    from paper_2304_11274_amd import fit_tile_shape
+    assert fit_tile_shape(100, 150) == (50, 5)
+    assert fit_tile_shape(64, 64) == (64, 4)
+    assert fit_tile_shape(200, 37) == (50, 5)
+    assert fit_tile_shape(3, 10) == (8, 10)
+    for nx in list(range(1, 300, 7)) + [256, 257, 512]:
+        for rows in (1, 2, 7, 32, 33, 100, 255):
+            tx, ty = fit_tile_shape(nx, rows)
+            assert 8 <= tx <= 64 and 1 <= ty and tx * ty <= 256
+            assert 2 * (tx + ty) + 4 <= 256
+            assert -(-nx // tx) == max(1, -(-nx // 64)) or nx < 8
+            assert ty <= rows or rows < 1
+    lib = L.load()
+    a, b = C.c_int(), C.c_int()
+    assert lib.tpfa_fit_tile_shape(0, 5, C.byref(a), C.byref(b)) == L.TPFA_ERR_SHAPE
+    assert lib.tpfa_fit_tile_shape(5, 5, None, C.byref(b)) == L.TPFA_ERR_NULL
