@@ -35,8 +35,10 @@
  *  - Precision: TPFA_FP64 -> every array (p, kx, r, J, w, grads) is double.
  *    TPFA_FP32 -> the "precision form": p holds FP32 offsets dp from an FP64
  *    reference profile pref[nz] (p_K = pref[k] + dp_K in FP64), kx and outputs
- *    are float; the potential difference and the residual / diagonal / gradient
- *    accumulations are carried in FP64 and rounded once on store.
+ *    are float; the z-face potential differences and the residual and J v sums
+ *    are carried in FP64 and rounded once on store; the Jacobian diagonal and
+ *    the six terms of each gradient are summed in float (no cancellation
+ *    there beyond a few ulp of the sum of the terms' magnitudes).
  *  - Return value: TPFA_OK (0) or a negative TPFA_ERR_* code; the detail is in
  *    tpfa_last_error() (thread-local). No C++ exception crosses the ABI.
  *    Argument errors are detected on the host before anything is enqueued.
@@ -309,15 +311,16 @@ typedef struct tpfa_batch tpfa_batch_t; /* opaque */
 /* Builds the work list (one item per tile and z-chunk of every model, models
    in the given order, each in z-chunk, tile-row, tile order) and the model
    table on the device (the batch owns these two device buffers and a block
-   of work counters), and captures one persistent kernel launch into a HIP
-   graph.
+   of work counters), and captures the launch into a HIP graph: a one-
+   workgroup kernel that zeroes the work counters, then the persistent
+   kernel.
    `stream` orders the uploads. */
 int tpfa_batch_create(const tpfa_model_t *models, int n_models, tpfa_precision_t prec,
                       tpfa_batch_mode_t mode, tpfa_batch_t **out, void *stream);
 
 /* Replays the captured graph on `stream`: all models, one persistent launch.
-   Runs of one batch share its work counters (the launch's last workgroup
-   resets them for the next run), so they must not overlap: never run one
+   Runs of one batch share its work counters (zeroed at the start of each
+   run), so they must not overlap: never run one
    batch on two streams at once without ordering the runs (e.g. with an
    event). Different batches are independent. */
 int tpfa_batch_run(tpfa_batch_t *batch, void *stream);

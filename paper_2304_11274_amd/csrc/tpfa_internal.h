@@ -146,11 +146,10 @@ hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, cons
 
 // Batched ensemble kernels (persistent and grouped schedules). The work list
 // is cut into one band per XCD; the persistent schedule keeps one claim
-// counter per band plus a count of finished workgroups, each counter on its
-// own 128-byte line (kCounterStride words apart) so that the bands' atomics
-// do not contend for one line.
+// counter per band, each on its own 128-byte line (kCounterStride words
+// apart) so that the bands' atomics do not contend for one line.
 constexpr int kXcds = 8;
-constexpr int kBatchCounters = kXcds + 1;
+constexpr int kBatchCounters = kXcds;
 constexpr int kCounterStride = 32;
 constexpr int kCounterWords = kBatchCounters * kCounterStride;
 struct WorkItem {

@@ -46,9 +46,9 @@
 // relative to the deviations, not to rho G dz; it decides the upwind cell in
 // FP64. x-y faces subtract offsets of one plane in float (whose sign is exact,
 // so the upwind choice is the FP64 one); transmissibility, density, mobility,
-// the flux/derivative products and the Jacobian diagonal are FP32; the
-// residual, the gradients and J v are accumulated in FP64 and rounded once on
-// store.
+// the flux/derivative products, the Jacobian diagonal and the six terms of
+// each gradient are FP32; the residual and J v are accumulated in FP64 and
+// rounded once on store.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -396,10 +396,22 @@ __device__ __forceinline__ void accumulation(const Args &a, const Cell<float> &c
 // [kb, min(kb + kz_chunk, nz)).
 // ----------------------------------------------------------------------------
 
+// A per-thread byte offset passed through an empty asm that depends on the
+// plane index: the compiler can no longer hoist a 64-bit copy of it out of the
+// plane loop, so it keeps one 32-bit register and addresses with the
+// scalar-base + 32-bit-offset form. In the FP32 kernels this saves 8 to 19
+// registers (the VJP 81 -> 67, two more waves per SIMD); in FP64 it measured
+// slightly slower and is not used.
+__device__ __forceinline__ uint32_t per_plane(uint32_t boff, int k) {
+  asm("" : "+v"(boff) : "s"(k));
+  return boff;
+}
+
 // Uniform (scalar) base of plane k of an array plus a per-thread 32-bit byte
-// offset.
-template <class T>
+// offset (made opaque per plane with FRESH).
+template <bool FRESH = false, class T>
 __device__ __forceinline__ T at(const T *base, size_t plane_elems, int k, uint32_t boff) {
+  if constexpr (FRESH) boff = per_plane(boff, k);
   const char *pb = reinterpret_cast<const char *>(base + (size_t)k * plane_elems);
   return *(gptr<const T>)(pb + boff);
 }
@@ -417,26 +429,27 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
                                      const Cell<S> &c0, const Props<S> &d0, S xk, S rk,
                                      const Face<S> (&f)[6], const S (&wn)[6],
                                      const S (&fd)[4]) {
+  if constexpr (sizeof(S) == 4) cb = per_plane(cb, k);
   constexpr int BASE = base_mode(MODE);
   constexpr bool ACC = has_accumulation(MODE);
   const size_t ko = (size_t)k * plane;
   if constexpr (BASE == MODE_VJP) {
     // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
-    // per-direction form: the faces of axis d feed the ln k_d gradient only
-    double gp = 0.0, gm = 0.0, gq[3] = {0.0, 0.0, 0.0};
+    // per-direction form: the faces of axis d feed the ln k_d gradient only.
+    // FP64: terms and sums in FP64. FP32 form: float terms and float sums of
+    // the six terms (error below about 6 ulp of the sum of their magnitudes)
+    S gp = S(0), gm = S(0), gq[3] = {S(0), S(0), S(0)};
 #pragma unroll
     for (int n = 0; n < 6; ++n) {
       if constexpr (sizeof(S) == 4) {
-        // FP32 form: each term is a float product (relative error a few 1e-7
-        // of the term), summed in FP64
         const float d = (n & 1) ? c0.w - wn[n] : wn[n] - c0.w;
         const float tp = d * ((n & 1) ? f[n].dLo : f[n].dUp);
         const float tm = d * (f[n].F * ((n & 1) ? f[n].qUp : f[n].qLo));
-        gp = gp + (double)tp;
+        gp = gp + tp;
         if constexpr (has_k3(MODE))
-          gq[n >> 1] = gq[n >> 1] + (double)tm;
+          gq[n >> 1] = gq[n >> 1] + tm;
         else if constexpr (!has_trans(MODE))
-          gm = gm + (double)tm;
+          gm = gm + tm;
       } else {
         const double d = (double)c0.w - (double)wn[n];
         if (n & 1) {  // own cell is Lo
@@ -745,26 +758,26 @@ struct Tile {
   // Fields outside `need` keep their previous (finite) values; nothing reads them.
   __device__ __forceinline__ void load_at(Cell<S> &c, int k, bool ok, uint32_t b, uint32_t bs,
                                           uint32_t need = kNeedAll) const {
-    c.p = at(static_cast<const S *>(a.p), plane, k, b);
+    c.p = at<FP32>(static_cast<const S *>(a.p), plane, k, b);
     if (TIN) {
       c.k = S(0);
-      if (need & kNeedTx) c.tx = at(static_cast<const S *>(a.tx), plane, k, b);
-      if (need & kNeedTy) c.ty = at(static_cast<const S *>(a.ty), plane, k, b);
+      if (need & kNeedTx) c.tx = at<FP32>(static_cast<const S *>(a.tx), plane, k, b);
+      if (need & kNeedTy) c.ty = at<FP32>(static_cast<const S *>(a.ty), plane, k, b);
     } else {
       if (need & kNeedK) {
-        const S kx = at(static_cast<const S *>(a.kx), plane, k, b);
+        const S kx = at<FP32>(static_cast<const S *>(a.kx), plane, k, b);
         c.k = ok ? kx : S(0);
       }
       if (K3 && (need & kNeedKy)) {
-        const S ky = at(static_cast<const S *>(a.ky), plane, k, b);
+        const S ky = at<FP32>(static_cast<const S *>(a.ky), plane, k, b);
         c.ky = ok ? ky : S(0);
       }
     }
-    if (need & kNeedSeal) c.s = a.seal ? (uint32_t)at(a.seal, plane, k, bs) : 0u;
-    if (NEEDW && (need & kNeedW)) c.w = at(static_cast<const S *>(a.w), plane, k, b);
+    if (need & kNeedSeal) c.s = a.seal ? (uint32_t)at<FP32>(a.seal, plane, k, bs) : 0u;
+    if (NEEDW && (need & kNeedW)) c.w = at<FP32>(static_cast<const S *>(a.w), plane, k, b);
     if (R10) {
-      if (need & kNeedTn) c.tn = at(static_cast<const S *>(a.tne), plane, k, b);
-      if (need & kNeedTs) c.ts = at(static_cast<const S *>(a.tse), plane, k, b);
+      if (need & kNeedTn) c.tn = at<FP32>(static_cast<const S *>(a.tne), plane, k, b);
+      if (need & kNeedTs) c.ts = at<FP32>(static_cast<const S *>(a.tse), plane, k, b);
     }
   }
   // A diagonal face exists when both its cells lie in the domain; otherwise its
@@ -777,12 +790,12 @@ struct Tile {
       // a face with a cell outside the domain does not exist
       c.tx = txv ? c.tx : S(0);
       c.ty = tyv ? c.ty : S(0);
-      c.tz = at(static_cast<const S *>(a.tz), plane, k, cb);
+      c.tz = at<FP32>(static_cast<const S *>(a.tz), plane, k, cb);
     }
-    if (K3) c.kz = at(static_cast<const S *>(a.kz), plane, k, cb);
+    if (K3) c.kz = at<FP32>(static_cast<const S *>(a.kz), plane, k, cb);
     if (ACC) {
-      c.phi = at(static_cast<const S *>(a.phi), plane, k, cb);
-      c.pn = at(static_cast<const S *>(a.pprev), plane, k, cb);
+      c.phi = at<FP32>(static_cast<const S *>(a.phi), plane, k, cb);
+      c.pn = at<FP32>(static_cast<const S *>(a.pprev), plane, k, cb);
     }
     if (R10) {
       c.tn = tnv ? c.tn : S(0);
