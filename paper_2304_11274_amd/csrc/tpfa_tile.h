@@ -401,7 +401,10 @@ __device__ __forceinline__ void accumulation(const Args &a, const Cell<float> &c
 // plane loop, so it keeps one 32-bit register and addresses with the
 // scalar-base + 32-bit-offset form. In the FP32 kernels this saves 8 to 19
 // registers (the VJP 81 -> 67, two more waves per SIMD); in FP64 it measured
-// slightly slower and is not used.
+// slightly slower and is not used. With it, the plane's base address is also
+// pinned to scalar registers, or the compiler adds plane offset and thread
+// offset in 64-bit vector registers once for several arrays (six VALU
+// instructions per plane in the FP32 residual).
 __device__ __forceinline__ uint32_t per_plane(uint32_t boff, int k) {
   asm("" : "+v"(boff) : "s"(k));
   return boff;
@@ -413,6 +416,7 @@ template <bool FRESH = false, class T>
 __device__ __forceinline__ T at(const T *base, size_t plane_elems, int k, uint32_t boff) {
   if constexpr (FRESH) boff = per_plane(boff, k);
   const char *pb = reinterpret_cast<const char *>(base + (size_t)k * plane_elems);
+  if constexpr (FRESH) asm("" : "+s"(pb));
   return *(gptr<const T>)(pb + boff);
 }
 template <class T>
