@@ -135,6 +135,23 @@ class Timer:
 # upwind choice; the errors of cells away from such faces are reported apart.
 # ---------------------------------------------------------------------------
 
+def ensemble_members(tp, models, up, padded):
+    """Members of the uneven ensemble (FP32 form) on the device: contiguous
+    arrays, or rows padded to 128-byte lines (tpfa.pitch_for) with the outputs'
+    row padding writable (pad_writes), so that every row is stored in whole
+    lines."""
+    members = []
+    for geo_m in models:
+        g = geo_m.grid
+        arrs = [up(geo_m.kx32()), up(geo_m.dp32()), up(geo_m.seal)]
+        if padded:
+            arrs = [tp.to_pitched(a, g) for a in arrs]
+        members.append(dict(grid=g, fluid=geo_m.fluid, kx=arrs[0], p=arrs[1], seal=arrs[2],
+                            pref=tp.hydrostatic(g, geo_m.fluid), ry=geo_m.ry, rz=geo_m.rz,
+                            pad_writes=padded))
+    return members
+
+
 def _rel(np, got, ref, scale):
     d = np.abs(np.asarray(got, np.float64) - ref)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -313,13 +330,8 @@ def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
     # config 4: the 64-model ensemble (one graph-replayed launch), per model
     if "batched" in out:
         models = geomodel.ensemble()
-        members, refs, t_or, worst = [], [], 0.0, None
-        for geo_m in models:
-            gm_ = geo_m.grid
-            pr = tp.hydrostatic(gm_, geo_m.fluid)
-            members.append(dict(grid=gm_, fluid=geo_m.fluid, kx=up(geo_m.kx32()),
-                                p=up(geo_m.dp32()), seal=up(geo_m.seal), pref=pr,
-                                ry=geo_m.ry, rz=geo_m.rz))
+        refs, t_or, worst = [], 0.0, None
+        members = ensemble_members(tp, models, up, padded=True)  # the timed layout
         lt = out["batched"].get("ensemble_launch")
         if lt:
             from paper_2304_11274_amd import autotune
@@ -660,9 +672,10 @@ def main():
             return buf[..., :nxp]
 
         res = {"workload": f"{nxp}x{nyp}x{g.nz} (rows of 4000 / 2000 bytes, off 128-byte "
-                           f"lines), residual + Jacobian, contiguous vs row pitch {ldp}"}
+                           f"lines), residual + Jacobian, contiguous vs row pitch {ldp} "
+                           f"(and row pitch {ldp} with the outputs' padding written)"}
         for prec in ("fp64", "fp32"):
-            for ld in (nxp, ldp):
+            for ld, pw in ((nxp, False), (ldp, False), (ldp, True)):
                 sp = layout(seal, ld)
                 if prec == "fp64":
                     kp = layout(kx64, ld)
@@ -675,6 +688,7 @@ def main():
                     pp = [layout(nz_[:, :nyp, :nxp].float(), ld) for nz_ in noise[:2]]
                     kw = dict(seal=sp, pref=pref, ry=geo.ry, rz=geo.rz)
                     bpc = BYTES_FP32_RJ
+                kw["pad_writes"] = pw
                 r_, J_ = tp.jacobian(gp_, fl, kp, pp[0], **kw)
                 kw.update(r_out=r_, J_out=J_)
                 for s_ in range(W):
@@ -683,7 +697,7 @@ def main():
                     for s_ in range(KA):
                         tp.jacobian(gp_, fl, kp, pp[s_ % 2], **kw)
                 ms = tm.ms / KA
-                res.setdefault(prec, {})["pitch_%d" % ld] = {
+                res.setdefault(prec, {})["pitch_%d%s" % (ld, "_pad_writes" if pw else "")] = {
                     "ms_per_step": ms, "cells_per_s": cells / (ms / 1e3),
                     "algorithmic_GBps": bpc * cells / (ms / 1e3) / 1e9}
                 del kp, sp, pp, r_, J_, kw
@@ -731,15 +745,10 @@ def main():
     if "batched" in sections:
         t0 = time.time()
         models = geomodel.ensemble()
-        members = []
-        for geo_m in models:
-            gm_ = geo_m.grid
-            pr = tp.hydrostatic(gm_, geo_m.fluid)
-            members.append(dict(grid=gm_, fluid=geo_m.fluid, kx=up(geo_m.kx32()),
-                                p=up(geo_m.dp32()), seal=up(geo_m.seal), pref=pr,
-                                ry=geo_m.ry, rz=geo_m.rz))
+        # rows padded to 128-byte lines with writable output padding (whole-line
+        # stores); the contiguous layout is timed below with the same launch
+        members = ensemble_members(tp, models, up, padded=True)
         cells = sum(m.ncell for m in models)
-        del models
         from paper_2304_11274_amd import autotune
         t1 = time.time()
         if args.ensemble_launch:
@@ -768,9 +777,8 @@ def main():
                 ens.run()
         t_graph = tm.ms / KA
         # the same models, one launch per model on one stream
-        outs = [(torch.empty_like(m["p"]), torch.empty((7,) + tuple(m["p"].shape),
-                                                       dtype=torch.float32, device=dev))
-                for m in members]
+        outs = [(tp.empty_pitched(m["grid"], torch.float32, dev),
+                 tp.empty_pitched(m["grid"], torch.float32, dev, (7,))) for m in members]
         ens_tiles = sorted({(m["tile"], m["kz_chunk"]) for m in members})
         ens_tiles_of = [(m["tile"], m["kz_chunk"]) for m in members]
         for m, (t_, z_) in zip(members, solo):
@@ -780,15 +788,19 @@ def main():
             for m, (rr, JJ) in zip(members, outs):
                 tp.jacobian(m["grid"], m["fluid"], m["kx"], m["p"], seal=m["seal"],
                             pref=m["pref"], ry=m["ry"], rz=m["rz"], r_out=rr, J_out=JJ,
-                            tile=m["tile"], kz_chunk=m["kz_chunk"])
+                            tile=m["tile"], kz_chunk=m["kz_chunk"], pad_writes=True)
         for _ in range(W):
             per_model()
         with Timer(torch) as tm:
             for _ in range(KA):
                 per_model()
         t_loop = tm.ms / KA
+        pad_bytes = sum(m["p"].stride(-2) * m["grid"].ny * m["grid"].nz for m in members)
         out["batched"] = {"models": len(members), "cells": cells, "work_items": n_items,
                           "workgroups": n_wg, "schedule": ens_best[2], "dtype": "f32",
+                          "layout": "rows padded to 128-byte lines (pitch_for), output "
+                                    "padding written (pad_writes): whole-line stores",
+                          "cells_with_padding": pad_bytes,
                           "cells_per_s": cells / (t_graph / 1e3), "ms_per_step": t_graph,
                           "algorithmic_GBps": BYTES_FP32_RJ * cells / (t_graph / 1e3) / 1e9,
                           "ensemble_launch": ens_best, "ensemble_tiles": ens_tiles,
@@ -800,19 +812,12 @@ def main():
         if out["value"]:
             out["batched"]["cells_per_s_vs_fp64"] = out["batched"]["cells_per_s"] / out["value"]
         ens.close()
-        del ens, outs
+        del ens, outs, members
         torch.cuda.empty_cache()
-        # the same models with every array's rows padded to 128-byte lines
-        # (32 floats): the same launch, whole-line stores at every tile edge
+        # the same models in contiguous arrays (rows off 128-byte lines), same launch
+        members = ensemble_members(tp, models, up, padded=False)
         for m, (t_, z_) in zip(members, ens_tiles_of):
             m["tile"], m["kz_chunk"] = t_, z_
-            nx_ = m["grid"].nx
-            ld = (nx_ + 31) // 32 * 32
-            for key in ("kx", "p", "seal"):
-                buf = torch.zeros(tuple(m[key].shape[:-1]) + (ld,), dtype=m[key].dtype,
-                                  device=dev)
-                buf[..., :nx_].copy_(m[key])
-                m[key] = buf[..., :nx_]
         ens = tp.Ensemble(members)
         ens.set_schedule(ens_best[2])
         for _ in range(W):
@@ -820,12 +825,12 @@ def main():
         with Timer(torch) as tm:
             for _ in range(KA):
                 ens.run()
-        t_pad = tm.ms / KA
-        out["batched"]["padded_rows_ms"] = t_pad
-        out["batched"]["padded_rows_cells_per_s"] = cells / (t_pad / 1e3)
+        t_con = tm.ms / KA
+        out["batched"]["contiguous_rows_ms"] = t_con
+        out["batched"]["contiguous_rows_cells_per_s"] = cells / (t_con / 1e3)
         log(f"batched: {out['batched']}")
         ens.close()
-        del ens, members
+        del ens, members, models
         torch.cuda.empty_cache()
 
     # ---------------------------------------------------- adjoint fwd + VJP

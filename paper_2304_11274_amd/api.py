@@ -33,12 +33,14 @@ def _fluid(f) -> L.Fluid:
     return L.Fluid(float(f.rho0), float(f.cf), float(f.p0), float(f.mu))
 
 
-def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None):
+def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None,
+            pad_writes: bool = False):
     """``xcd_remap``: True (or "bands") for the XCD band order, "yfast" for the
     y-fast tile order, False for the natural order. ``rows`` = (y_begin, y_end):
     compute and write only those rows (a y slab; the grid's other rows are read
-    as its halo)."""
-    if tile is None and kz_chunk is None and not xcd_remap and rows is None:
+    as its halo). ``pad_writes``: the outputs' row padding may be overwritten
+    (zeros), so that rows of row-pitched outputs are written in whole lines."""
+    if tile is None and kz_chunk is None and not xcd_remap and rows is None and not pad_writes:
         return None
     if xcd_remap == "yfast":
         flags = L.TPFA_LAUNCH_Y_FAST
@@ -48,6 +50,8 @@ def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None):
         flags = 0
     else:
         raise ValueError(f"unknown workgroup order {xcd_remap!r}")
+    if pad_writes:
+        flags |= L.TPFA_LAUNCH_PAD_WRITES
     y0, y1 = (0, 0) if rows is None else (int(rows[0]), int(rows[1]))
     return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
                     flags, y0, y1)
@@ -174,6 +178,26 @@ def _need(t, name, dtype, n, device, lay=None):
     lay.take(t, name)
 
 
+def _pad_ok(pad_writes, lay, **outs):
+    """With pad_writes the kernels write each output row up to the pitch, the
+    last row of the last plane included: every output's buffer must hold it
+    (a (..., nz, ny, ldx) buffer, as empty_pitched allocates)."""
+    grid = lay.grid
+    nx, ny, nz, ld = int(grid.nx), int(grid.ny), int(grid.nz), lay.pitch
+    if not pad_writes or ld == nx:
+        return
+    for name, t in outs.items():
+        if t is None:
+            continue
+        planes = t.numel() // (nx * ny * nz)
+        need = t.storage_offset() + planes * nz * ny * ld
+        have = t.untyped_storage().nbytes() // t.element_size()
+        if need > have:
+            raise ValueError(f"pad_writes: {name} ends inside the padding of its last row "
+                             f"({need} elements from its storage start needed, {have} held); "
+                             f"use (..., nz, ny, ldx) buffers such as empty_pitched")
+
+
 def _kyz(ky, kz):
     if (ky is None) != (kz is None):
         raise ValueError("ky and kz go together (per-direction permeability arrays)")
@@ -218,27 +242,29 @@ def _rock(kx, seal, ry, rz, trans=None, ky=None, kz=None) -> L.Rock:
 
 def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
              out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
-             rows=None) -> torch.Tensor:
+             rows=None, pad_writes=False) -> torch.Tensor:
     """Flux residual r (paper Algorithm 1, Eqs. 3-5)."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = out if out is not None else _empty(p, lay)
     _need(r, "out", dt, n, dev, lay)
+    _pad_ok(pad_writes, lay, out=r)
     lib = L.load()
     L.check(lib.tpfa_residual(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r),
-                              _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
+                              _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                              _stream(dev)), lib)
     return r
 
 
-def _launch_ref(tile, kz_chunk, xcd_remap, rows=None):
-    ln = _launch(tile, kz_chunk, xcd_remap, rows)
+def _launch_ref(tile, kz_chunk, xcd_remap, rows=None, pad_writes=False):
+    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes)
     return None if ln is None else C.byref(ln)
 
 
 def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
              want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
-             xcd_remap=False, rows=None):
+             xcd_remap=False, rows=None, pad_writes=False):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
     [diag, -x, +x, -y, +y, -z, +z]."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -248,17 +274,19 @@ def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
         _need(r, "r_out", dt, n, dev, lay)
     J = J_out if J_out is not None else _empty(p, lay, (7,))
     _need(J, "J_out", dt, 7 * n, dev, lay)
+    _pad_ok(pad_writes, lay, r_out=r, J_out=J)
     lib = L.load()
     L.check(lib.tpfa_jacobian(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
-                              _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
+                              _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                              _stream(dev)), lib)
     return r, J
 
 
 def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
                  want_p=True, want_logk=True, gp_out=None, gm_out=None, trans=None, tile=None,
-                 kz_chunk=None, xcd_remap=False, rows=None):
+                 kz_chunk=None, xcd_remap=False, rows=None, pad_writes=False):
     """(grad_p, grad_logk) = (J^T w, d(w.r)/d ln kx); either may be None. With
     ``trans`` = (tx, ty, tz) the second output is grad_logt [3, nz, ny, nx]:
     d(w.r)/d ln T of each cell's +x, +y, +z face. With per-direction arrays
@@ -273,12 +301,14 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     if want_logk:
         gm = gm_out if gm_out is not None else _empty(p, lay, (3,) if planes == 3 else ())
         _need(gm, "gm_out", dt, planes * n, dev, lay)
+    _pad_ok(pad_writes, lay, gp_out=gp, gm_out=gm)
     lib = L.load()
     fn = lib.tpfa_residual_vjp_trans if trans is not None else lib.tpfa_residual_vjp
     L.check(fn(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w), _ptr(gp), _ptr(gm),
-               _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
+               _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                              _stream(dev)), lib)
     return gp, gm
 
 
@@ -294,7 +324,7 @@ def _accum(accum, dt_, n, dev, lay):
 
 def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
                 kz=None, out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
-                rows=None) -> torch.Tensor:
+                rows=None, pad_writes=False) -> torch.Tensor:
     """Full backward-Euler residual of Eq. (2): V (phi rho - phi_n rho_n)/dt plus
     the flux sum. ``accum`` = dict(phi, p_prev, dt, cr)."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -303,18 +333,19 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
         raise ValueError("residual_be needs accum")
     r = out if out is not None else _empty(p, lay)
     _need(r, "out", dt, n, dev, lay)
+    _pad_ok(pad_writes, lay, out=r)
     lib = L.load()
     L.check(lib.tpfa_residual_be(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
-                                 _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
+                                 _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
                                  _stream(dev)), lib)
     return r
 
 
 def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
                 kz=None, want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
-                xcd_remap=False, rows=None):
+                xcd_remap=False, rows=None, pad_writes=False):
     """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     acc = _accum(accum, dt, n, dev, lay)
@@ -326,18 +357,20 @@ def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
         _need(r, "r_out", dt, n, dev, lay)
     J = J_out if J_out is not None else _empty(p, lay, (7,))
     _need(J, "J_out", dt, 7 * n, dev, lay)
+    _pad_ok(pad_writes, lay, r_out=r, J_out=J)
     lib = L.load()
     L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
-                                 _ptr(r), _ptr(J), _launch_ref(tile, kz_chunk, xcd_remap, rows),
+                                 _ptr(r), _ptr(J),
+                                 _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
                                  _stream(dev)), lib)
     return r, J
 
 
 def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
         kz=None, want_r=False, out=None, r_out=None, trans=None, tile=None, kz_chunk=None,
-        xcd_remap=False, rows=None):
+        xcd_remap=False, rows=None, pad_writes=False):
     """Matrix-free J v of the flux residual, or of the backward-Euler residual
     when ``accum`` is given; returns (jv, r or None)."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -349,18 +382,20 @@ def jvp(grid, fluid, kx, p, v, *, accum=None, seal=None, pref=None, ry=1.0, rz=1
     if want_r:
         r = r_out if r_out is not None else _empty(p, lay)
         _need(r, "r_out", dt, n, dev, lay)
+    _pad_ok(pad_writes, lay, out=jv, r_out=r)
     lib = L.load()
     L.check(lib.tpfa_jvp(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                          C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                          C.byref(L.State(_ptr(p), _ptr(pref))),
                          None if acc is None else C.byref(acc), prec, _ptr(v), _ptr(jv),
-                         _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows), _stream(dev)), lib)
+                         _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                              _stream(dev)), lib)
     return jv, r
 
 
 def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
                kz=None, out=None, trans=None, tile=None, kz_chunk=None, xcd_remap=False,
-               rows=None) -> torch.Tensor:
+               rows=None, pad_writes=False) -> torch.Tensor:
     """Residual of the 10-flux stencil (six faces plus four in-plane diagonal
     faces with caller-supplied transmissibilities tne, tse)."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
@@ -368,11 +403,13 @@ def residual10(grid, fluid, kx, p, tne, tse, *, seal=None, pref=None, ry=1.0, rz
     _need(tse, "tse", dt, n, dev, lay)
     r = out if out is not None else _empty(p, lay)
     _need(r, "out", dt, n, dev, lay)
+    _pad_ok(pad_writes, lay, out=r)
     lib = L.load()
     L.check(lib.tpfa_residual10(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                 C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                 C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(tne),
-                                _ptr(tse), _ptr(r), _launch_ref(tile, kz_chunk, xcd_remap, rows),
+                                _ptr(tse), _ptr(r),
+                                _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
                                 _stream(dev)), lib)
     return r
 
@@ -438,7 +475,8 @@ _GIVEN = 1  # non-null marker for an array: tpfa_resolve_launch only reads which
 
 
 def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=None,
-                   kz_chunk=None, xcd_remap=False, rows=None, ldx: Optional[int] = None) -> dict:
+                   kz_chunk=None, xcd_remap=False, rows=None, ldx: Optional[int] = None,
+                   pad_writes: bool = False) -> dict:
     """The launch a call of ``op`` ('residual', 'jacobian', 'vjp', 'residual10',
     'residual_be', 'jacobian_be', 'jvp', 'jvp_be') would make on this grid in
     this precision, rock form ('k': kx with ratios, 'k3': kx, ky, kz arrays,
@@ -450,7 +488,7 @@ def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=
     rock = {"k": L.Rock(G, None, None, 1.0, 1.0, None),
             "k3": L.Rock(G, G, G, 1.0, 1.0, None),
             "trans": L.Rock(None, None, None, 1.0, 1.0, None, G, G, G)}[form]
-    ln = _launch(tile, kz_chunk, xcd_remap, rows)
+    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes)
     out = L.Launch()
     lib = L.load()
     L.check(lib.tpfa_resolve_launch(C.byref(_grid(grid, int(grid.nx) if ldx is None else ldx)),
@@ -461,7 +499,8 @@ def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=
             "xcd_remap": bool(out.flags & L.TPFA_LAUNCH_XCD_REMAP),
             "order": ("bands" if out.flags & L.TPFA_LAUNCH_XCD_REMAP else
                       "yfast" if out.flags & L.TPFA_LAUNCH_Y_FAST else "natural"),
-            "rows": (out.y_begin, out.y_end)}
+            "rows": (out.y_begin, out.y_end),
+            "pad_writes": bool(out.flags & L.TPFA_LAUNCH_PAD_WRITES)}
 
 
 def fit_tile_shape(nx: int, rows: int):
@@ -508,10 +547,13 @@ def ensemble_run_noalloc(members: Sequence[dict], outputs: Sequence[tuple], *,
             _need(J, "J", dt, 7 * n, dev, lay)
         if r is not None or bm == L.TPFA_BATCH_RESIDUAL:
             _need(r, "r", dt, n, dev, lay)
+        _pad_ok(d.get("pad_writes", False), lay, r=r,
+                J=J if bm == L.TPFA_BATCH_JACOBIAN else None)
         arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
                          _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                          L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
-                         _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"))
+                         _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"),
+                                 d.get("pad_writes", False))
                          or L.Launch(-1, 0, 0, 0, 0))
     lib = L.load()
     L.check(lib.tpfa_ensemble_run_noalloc(arr, len(members), prec, bm, _stream(device)), lib)
@@ -520,9 +562,9 @@ def ensemble_run_noalloc(members: Sequence[dict], outputs: Sequence[tuple], *,
 class Ensemble:
     """Many independent grids run by one persistent kernel replayed from a
     HIP graph. ``members`` is a sequence of dicts with keys grid, fluid, kx,
-    p, and optionally seal, pref, ry, rz, tile, kz_chunk, rows. Outputs are
-    allocated here in the layout of the member's ``p`` (``r[m]``, ``J[m]``)
-    and overwritten by every run."""
+    p, and optionally seal, pref, ry, rz, tile, kz_chunk, rows, pad_writes.
+    Outputs are allocated here in the layout of the member's ``p`` (``r[m]``,
+    ``J[m]``) and overwritten by every run."""
 
     def __init__(self, members: Sequence[dict], *, mode: str = "jacobian", want_r: bool = True):
         if not members:
@@ -548,8 +590,8 @@ class Ensemble:
             arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
                              _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                              L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
-                             _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"))
-                             or L.Launch(-1, 0, 0, 0, 0))
+                             _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"),
+                                     d.get("pad_writes", False)) or L.Launch(-1, 0, 0, 0, 0))
         self.prec = prec
         self._handle = C.c_void_p()
         self._lib = L.load()

@@ -63,12 +63,14 @@ def tune_member(m: dict, *, tiles: Sequence[int] = TILE_IDS_256,
     best_u = max(util.values())
     cands = [(t, z) for t in tiles if util[t] >= keep * best_u for z in kz if z <= 2 * g.nz]
     p = m["p"]
-    r = torch.empty_like(p)
-    J = torch.empty((7,) + tuple(p.shape), dtype=p.dtype, device=p.device)
+    # outputs in the member's layout (its row pitch)
+    ld = p.stride(-2) if g.ny > 1 else (p.stride(-3) if g.nz > 1 else g.nx)
+    r = api.empty_pitched(g, p.dtype, p.device, (), ld)
+    J = api.empty_pitched(g, p.dtype, p.device, (7,), ld)
     best = None
     for t, z in cands:
         kw = dict(seal=m.get("seal"), pref=m.get("pref"), ry=m.get("ry", 1.0),
-                  rz=m.get("rz", 1.0), tile=t, kz_chunk=z)
+                  rz=m.get("rz", 1.0), tile=t, kz_chunk=z, pad_writes=m.get("pad_writes", False))
         if mode == "jacobian":
             fn = lambda: api.jacobian(g, m["fluid"], m["kx"], p, r_out=r, J_out=J, **kw)  # noqa: E731
         else:

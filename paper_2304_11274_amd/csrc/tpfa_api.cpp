@@ -193,6 +193,7 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.nty = (int32_t)((y1 - y0 + ts.ty - 1) / ts.ty);
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
   a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : (flags & TPFA_LAUNCH_Y_FAST) ? 2 : 0;
+  a.padw = (flags & TPFA_LAUNCH_PAD_WRITES) && pitch(g) > g.nx ? 1 : 0;
   a.tile = tile;
   a.ldx = (int32_t)pitch(g);
   a.plane = pitch(g) * g.ny;

@@ -77,7 +77,7 @@ struct Args {
   int32_t y0, y1;     // rows computed and written: [y0, y1) (others are read only)
   int32_t ldx;        // row pitch of every array, in cells (>= nx)
   int32_t dtx, dty;   // shape of the fitted tile (tile == kFitTile)
-  int32_t pad0_;
+  int32_t padw;       // 1: tile lanes in the row padding (nx <= i < ldx) store zeros
   int64_t plane;      // ldx * ny
   int64_t nblocks;    // ntx * nty * nzc
   // transmissibility geometric factors a_d and directional ratios (y, z)

@@ -625,11 +625,12 @@ struct Tile {
   size_t plane;
   int nz, kb, ke;
   bool inside;         // the thread's cell lies in the grid (staged as a real cell)
-  bool own;            // ... and in the launch's row range (its outputs are written)
+  bool own;            // ... and in the launch's row range, or a pad lane: its outputs are written
   bool tnv, tsv;       // 10-flux: the own cell's +x+y / +x-y diagonal face exists
   bool txv, tyv;       // transmissibility input: the own cell's +x / +y face exists
   int ol;
   uint32_t cb, cs;     // byte offset of the own cell within a plane (S elements / seal bytes)
+  uint32_t sb;         // byte offset of the own cell's outputs (a padding cell's, for pad lanes)
   bool hv[HC];         // halo cell q lies in the domain
   uint32_t hr[HC];     // shared faces: lower-cell faces halo cell q evaluates (kPX | kPY | kNE | kSE)
   uint32_t hn[HC];     // fields halo cell q loads (kNeed*)
@@ -687,6 +688,9 @@ struct Tile {
     const int i = bx * TXv + tx, j = jb + ty;
     inside = active && i < nx && j < ny;
     own = inside && j < a.y1;
+    // lanes in the row padding store zeros there where the caller allows it
+    // (whole-line output rows); their loads stay those of an absent cell
+    const bool pad_lane = a.padw && active && i >= nx && i < (int)ldx && j < ny && j < a.y1;
     tnv = inside && i + 1 < nx && j + 1 < ny;
     txv = inside && i + 1 < nx;
     tyv = inside && j + 1 < ny;
@@ -695,6 +699,8 @@ struct Tile {
     ol = active ? (ty + 1) * Wv + tx + 1 : hw_() - 1;
     cb = col * (uint32_t)sizeof(S);
     cs = col;
+    sb = pad_lane ? ((uint32_t)j * ldx + (uint32_t)i) * (uint32_t)sizeof(S) : cb;
+    own = own || pad_lane;
     // halo ring: bottom row, top row, left column, right column
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
@@ -794,11 +800,18 @@ struct Tile {
       // a face with a cell outside the domain does not exist
       c.tx = txv ? c.tx : S(0);
       c.ty = tyv ? c.ty : S(0);
-      c.tz = at<FP32>(static_cast<const S *>(a.tz), plane, k, cb);
+      const S tz = at<FP32>(static_cast<const S *>(a.tz), plane, k, cb);
+      c.tz = inside ? tz : S(0);
     }
-    if (K3) c.kz = at<FP32>(static_cast<const S *>(a.kz), plane, k, cb);
+    // a lane without a cell (a padding lane) has closed z faces
+    if (K3) {
+      const S kz = at<FP32>(static_cast<const S *>(a.kz), plane, k, cb);
+      c.kz = inside ? kz : S(0);
+    }
     if (ACC) {
-      c.phi = at<FP32>(static_cast<const S *>(a.phi), plane, k, cb);
+      // a lane without a cell (a padding lane) gets porosity 0: no accumulation
+      const S phi = at<FP32>(static_cast<const S *>(a.phi), plane, k, cb);
+      c.phi = inside ? phi : S(0);
       c.pn = at<FP32>(static_cast<const S *>(a.pprev), plane, k, cb);
     }
     if (R10) {
@@ -944,8 +957,14 @@ struct Tile {
       for (int n = 0; n < 4; ++n) {
         const int q = b + dsl[n];
         const S pn = s_p[q], ln = s_l[q];
-        // face transmissibility: stored on the face's left (i) end
-        const S T = n == 0 ? s_tn[q] : n == 1 ? c0.tn : n == 2 ? c0.ts : s_ts[q];
+        // face transmissibility: stored on the face's left (i) end. A staged
+        // halo cell's value is checked only against its own presence, which
+        // covers every face towards a cell of the grid; a lane without a cell
+        // (a padding lane) takes none.
+        const S T = n == 0   ? (inside ? s_tn[q] : S(0))
+                    : n == 1 ? c0.tn
+                    : n == 2 ? c0.ts
+                             : (inside ? s_ts[q] : S(0));
         // the lower-index cell is the neighbour for n = 0, 2 and the own cell for 1, 3
         const S pLo = (n & 1) ? c0.p : pn, pUp = (n & 1) ? pn : c0.p;
         const S lLo = (n & 1) ? d0.lam : ln, lUp = (n & 1) ? ln : d0.lam;
@@ -954,7 +973,7 @@ struct Tile {
       }
     }
     if (!own) return;
-    emit<S, MODE>(a, k, plane, nz, cb, c0, d0, ACC ? xoff(k) : S(0), rkk, f, wn, fd);
+    emit<S, MODE>(a, k, plane, nz, sb, c0, d0, ACC ? xoff(k) : S(0), rkk, f, wn, fd);
   }
 
   // ---- shared-face form (residual-only modes) ----------------------------
@@ -997,12 +1016,13 @@ struct Tile {
     r = r - (double)pd.fzm;
     r = r + (double)pd.fzp;
     if constexpr (R10) {
-      r = r - (double)s_fne[bq + ol - W - 1];
+      // (a lane without a cell takes no diagonal flux of a halo cell, as above)
+      r = r - (inside ? (double)s_fne[bq + ol - W - 1] : 0.0);
       r = r + (double)pd.fne;
       r = r - (double)pd.fse;
-      r = r + (double)s_fse[bq + ol + W - 1];
+      r = r + (inside ? (double)s_fse[bq + ol + W - 1] : 0.0);
     }
-    if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), (size_t)k * plane, cb), (S)r);
+    if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), (size_t)k * plane, sb), (S)r);
   }
 
   // One plane k in the shared-face form: stage, complete plane k-1, evaluate

@@ -74,15 +74,16 @@ def case(prec, seed=5, shape=(70, 23, 9)):
     return geo, fields, pref, be
 
 
-def run_all(gpu, geo, f, pref, be, put, tile=None):
-    """Every output of every mode; `put` places a host array on the device."""
+def run_all(gpu, geo, f, pref, be, put, tile=None, **extra):
+    """Every output of every mode; `put` places a host array on the device;
+    `extra` keyword arguments go to every call."""
     g = geo.grid
     d = {k: put(v) for k, v in f.items()}
     kw = dict(seal=d["seal"], ry=geo.ry, rz=geo.rz, tile=tile,
-              pref=None if pref is None else dev(pref))
+              pref=None if pref is None else dev(pref), **extra)
     acc = dict(phi=d["phi"], p_prev=d["p_prev"], dt=be["dt"], cr=be["cr"])
     tr = (d["tx"], d["ty"], d["tz"])
-    pk = dict(pref=kw["pref"], tile=tile)
+    pk = dict(pref=kw["pref"], tile=tile, **extra)
     o = {}
     o["res"] = gpu.residual(g, geo.fluid, d["kx"], d["p"], **kw)
     o["resbe"] = gpu.residual_be(g, geo.fluid, d["kx"], d["p"], acc, **kw)

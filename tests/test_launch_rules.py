@@ -124,6 +124,35 @@ def test_explicit_launches_are_taken_as_given():
     assert rl(geomodel.Grid(64, 64, 5), "jacobian", kz_chunk=64)["kz_chunk"] == 5  # at most nz
 
 
+def test_pad_writes_flag_is_kept():
+    """The caller's pad-writes bit survives the default launch's own flags."""
+    g = geomodel.Grid(500, 64, 32)
+    for tile, order in ((None, False), (0, False), (3, True)):
+        r = rl(g, "jacobian", F32, tile=tile, xcd_remap=order, pad_writes=True, ldx=512)
+        assert r["pad_writes"], (tile, order)
+        assert not rl(g, "jacobian", F32, tile=tile, xcd_remap=order, ldx=512)["pad_writes"]
+    assert api._launch(None, None, False, None, True).flags == L.TPFA_LAUNCH_PAD_WRITES
+    assert api._launch(None, None, False) is None
+
+
+def test_pad_writes_need_whole_last_rows():
+    """The binding's host check: with pad_writes every output buffer must hold
+    the padding of its last row (views at a column offset into a buffer of the
+    same pitch do not)."""
+    g = geomodel.Grid(40, 7, 5)
+    lay = api._Layout(g)
+    buf = torch.zeros((5, 7, 64))
+    lay.take(buf[..., :40], "p")
+    api._pad_ok(True, lay, out=buf[..., :40])
+    api._pad_ok(False, lay, out=buf[..., 10:50])
+    with pytest.raises(ValueError, match="pad_writes"):
+        api._pad_ok(True, lay, out=buf[..., 10:50])
+    J = torch.zeros((7, 5, 7, 64))
+    api._pad_ok(True, lay, J_out=J[..., :40])
+    with pytest.raises(ValueError, match="pad_writes"):
+        api._pad_ok(True, lay, J_out=J[..., 10:50])
+
+
 def test_errors():
     lib = L.load()
     g = api._grid(G512)
