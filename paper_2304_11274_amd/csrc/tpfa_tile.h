@@ -287,12 +287,15 @@ __device__ __forceinline__ void st_out(T *p, T v) {
 // workgroup).
 constexpr int kMaxLds = 160 * 1024;
 
-// FP64 residual-only modes evaluate every in-plane face once, in its lower
-// cell, and hand the flux to the upper cell through LDS: two buffers of the
-// plane of p, k, mobility and of the +x, +y (and +x+y, +x-y) face fluxes. An
-// FP64 face costs a double reciprocal with two Newton steps, so sharing saves
-// more than the extra LDS traffic costs; in FP32 (one hardware reciprocal per
-// face) it measured slower on MI355X and the two-sided form is kept.
+// Residual-only modes evaluate every in-plane face once, in its lower cell,
+// and hand the flux to the upper cell through LDS: two buffers of the plane of
+// p, k, mobility and of the +x, +y (and +x+y, +x-y) face fluxes. An FP64 face
+// costs a double reciprocal with two Newton steps, so sharing saves more than
+// the extra LDS traffic costs. In FP32 it pays for the six-face residual
+// (512x512x256: 0.301 -> 0.287 ms; the kernel is VALU-bound) but not for the
+// 10-flux stencil, whose two extra shared diagonal fluxes cost more LDS
+// traffic than their arithmetic (750x994x246: 1.07 -> 1.18 ms): that one
+// keeps the two-sided form in FP32.
 template <class S, int MODE, int TX, int TY>
 constexpr int share_lds_bytes() {
   return 2 * (TX + 2) * (TY + 2) * (int)sizeof(S) * (mode_kind(MODE) == MODE_RES10 ? 7 : 5);
@@ -300,7 +303,8 @@ constexpr int share_lds_bytes() {
 template <class S, int MODE, int TX, int TY>
 constexpr bool tile_shares() {
   return TX > 0 &&
-         (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) && sizeof(S) == 8 &&
+         (base_mode(MODE) == MODE_RESIDUAL || mode_kind(MODE) == MODE_RES10) &&
+         (sizeof(S) == 8 || mode_kind(MODE) != MODE_RES10) &&
          !has_k3(MODE) && share_lds_bytes<S, MODE, TX, TY>() <= kMaxLds;
 }
 
