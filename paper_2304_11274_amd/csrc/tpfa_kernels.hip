@@ -449,6 +449,20 @@ bool march_residency(tpfa_precision_t prec, int mode, int tile, int &per_cu, int
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kTiles[tile].threads, 0) ==
             hipSuccess &&
         n > 0 && c > 0) {
+      // The runtime's answer counts LDS at byte granularity: for a tile of
+      // 26.9 KB of LDS it said 6 workgroups per CU where 5 ran (a launch of 6
+      // per CU took two rounds). Cap it by the CU's LDS in 2 KB granules.
+      hipFuncAttributes at{};
+      int lds_cu = 0;
+      if (hipFuncGetAttributes(&at, fn) == hipSuccess && at.sharedSizeBytes > 0 &&
+          hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                dev) == hipSuccess &&
+          lds_cu > 0) {
+        const size_t g = 2048, per = (at.sharedSizeBytes + g - 1) / g * g;
+        n = std::max(1, std::min(n, (int)((size_t)lds_cu / per)));
+      } else {
+        (void)hipGetLastError();
+      }
       slot = n;
       cu_count = c;
     } else {
