@@ -143,3 +143,28 @@ def test_binding_refuses_short_buffers(gpu, orc):
         gpu.residual(g, geo.fluid, kx, p, seal=s, out=out, pad_writes=True)
     gpu.residual(g, geo.fluid, kx, p, seal=s, out=out)
     torch.cuda.synchronize()
+
+
+def test_noalloc_run_with_pad_writes(gpu, orc):
+    """tpfa_ensemble_run_noalloc passes the members' flag to the same kernels:
+    its outputs equal the batch's, padding zeros included."""
+    members, outs = [], []
+    for m, (shape, ldx) in enumerate([((45, 20, 9), 64), ((70, 13, 6), 96)]):
+        geo = geomodel.random_small(80 + m, *shape, sigma=1.0, seal_prob=0.03)
+        pref = orc.hydrostatic(geo.grid, geo.fluid, geo.p_top)
+        members.append(dict(grid=geo.grid, fluid=geo.fluid, kx=pad(geo.kx32(), ldx),
+                            p=pad(geo.dp32(0), ldx), seal=pad(geo.seal, ldx), pref=dev(pref),
+                            ry=geo.ry, rz=geo.rz, tile=0, pad_writes=True))
+        outs.append((padded_out(geo.grid.shape, (), ldx, torch.float32),
+                     padded_out(geo.grid.shape, (7,), ldx, torch.float32)))
+    print("noalloc ensemble run with pad writes", flush=True)
+    ens = gpu.Ensemble(members)
+    ens.run()
+    gpu.ensemble_run_noalloc(members, [(r[1], J[1]) for r, J in outs])
+    torch.cuda.synchronize()
+    for q, ((rb, r), (Jb, J)) in enumerate(outs):
+        nx = members[q]["grid"].nx
+        assert torch.equal(r, ens.r[q]) and torch.equal(J, ens.J[q]), q
+        check_padding(rb, nx, rb.shape[-1])
+        check_padding(Jb, nx, Jb.shape[-1])
+    ens.close()
