@@ -100,13 +100,14 @@ def test_row_range_leaves_other_rows(gpu, prec):
 def test_ensemble_members(gpu, orc):
     """Ensemble members with and without the flag: identical real cells, zeros
     in the padding of the flagged members, both schedules."""
-    members = []
-    for m, (shape, ldx) in enumerate([((45, 20, 9), 64), ((70, 13, 6), 96), ((33, 31, 11), 64)]):
+    members, tiles = [], (0, 1, 10, 2)  # 10: the fitted tile
+    for m, (shape, ldx) in enumerate([((45, 20, 9), 64), ((70, 13, 6), 96), ((33, 31, 11), 64),
+                                      ((50, 17, 7), 64)]):
         geo = geomodel.random_small(60 + m, *shape, sigma=1.0, seal_prob=0.03)
         pref = orc.hydrostatic(geo.grid, geo.fluid, geo.p_top)
         members.append(dict(grid=geo.grid, fluid=geo.fluid, kx=pad(geo.kx32(), ldx),
                             p=pad(geo.dp32(0), ldx), seal=pad(geo.seal, ldx), pref=dev(pref),
-                            ry=geo.ry, rz=geo.rz, tile=m % 3))
+                            ry=geo.ry, rz=geo.rz, tile=tiles[m]))
     print("ensemble members with pad writes", flush=True)
     plain = gpu.Ensemble(members)
     flagged = gpu.Ensemble([dict(d, pad_writes=True) for d in members])
@@ -121,7 +122,9 @@ def test_ensemble_members(gpu, orc):
             assert torch.equal(plain.r[q], flagged.r[q]) and torch.equal(plain.J[q], flagged.J[q])
             for t in (flagged.r[q], flagged.J[q]):
                 full = t.as_strided(tuple(t.shape[:-1]) + (t.stride(-2),), t.stride())
-                tx = gpu.tile_shapes()[q % 3][0]
+                g_ = d["grid"]
+                tx = (gpu.fit_tile_shape(g_.nx, g_.ny)[0] if tiles[q] == 10
+                      else gpu.tile_shapes()[tiles[q]][0])
                 covered = min(t.stride(-2), (nx + tx - 1) // tx * tx)
                 assert bool((full[..., nx:covered] == 0).all()), (schedule, q)
     plain.close()
