@@ -7,7 +7,9 @@ leaves every other row and all padding untouched. The same random launches
 drive the VJP, the 10-flux residual, the per-direction and transmissibility
 forms and the backward-Euler J and J v against the oracle, and random uneven
 ensembles (either schedule, graph or direct launch) against the members'
-single-grid launches, bitwise."""
+single-grid launches, bitwise. The row-range launch is repeated with the
+outputs' padding writable (pad_writes): equal owned rows, zeros in the padding
+under the tile's lanes, everything else untouched."""
 import numpy as np
 import pytest
 import torch
@@ -77,6 +79,20 @@ def test_random_launches_against_oracle(gpu, orc, c):
     assert torch.isnan(rb[:, :y0]).all() and torch.isnan(rb[:, y1:]).all()
     assert torch.isnan(Jb[..., :y0, :]).all() and torch.isnan(Jb[..., y1:, :]).all()
     assert torch.isnan(rb[..., g.nx:]).all() and torch.isnan(Jb[..., g.nx:]).all()
+    # the same row-range launch with the outputs' padding writable: the owned
+    # rows' padding under the tile's lanes is zeros, the rest untouched
+    rp = torch.full_like(rb, float("nan"))
+    Jp = torch.full_like(Jb, float("nan"))
+    gpu.jacobian(g, geo.fluid, kp, pp, seal=sp, ry=geo.ry, rz=geo.rz, rows=(y0, y1),
+                 r_out=rp[..., :g.nx], J_out=Jp[..., :g.nx], pad_writes=True, **launch, **kw)
+    tx = gpu.resolve_launch(g, "jacobian", r.dtype, rows=(y0, y1), ldx=ldx, **launch)["shape"][0]
+    cov = min(ldx, -(-g.nx // tx) * tx)
+    torch.cuda.synchronize()
+    assert torch.equal(rp[:, y0:y1, :g.nx], rb[:, y0:y1, :g.nx])
+    assert torch.equal(Jp[..., y0:y1, :g.nx], Jb[..., y0:y1, :g.nx])
+    assert bool((rp[:, y0:y1, g.nx:cov] == 0).all()) and bool((Jp[..., y0:y1, g.nx:cov] == 0).all())
+    assert torch.isnan(rp[:, y0:y1, cov:]).all() and torch.isnan(Jp[..., y0:y1, cov:]).all()
+    assert torch.isnan(rp[:, :y0]).all() and torch.isnan(rp[:, y1:]).all()
     rep = compare_full(orc, g, geo.fluid, kwide, pw, r.double().cpu().numpy(),
                        J.double().cpu().numpy(), tol=tol, tau=tau, ry=geo.ry, rz=geo.rz,
                        seal=geo.seal)
