@@ -157,11 +157,13 @@ struct WorkItem {
   int32_t bx, by, kb;
 };
 // `tiles`: 0, 1, 2 or kFitTile when every model uses that 256-thread tile, 3 for a mix.
-hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
+// `mode`: MODE_RESIDUAL or MODE_JACOBIAN, in FP32 with MODE_PLAIN for ordinary stores
+// (the batch's choice: ordinary unless every member's output rows are whole lines).
+hipError_t launch_persistent(tpfa_precision_t prec, int mode, int tiles, const Args *d_models,
                              const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
                              int n_workgroups, hipStream_t stream);
-int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles);
-hipError_t launch_grouped(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
+int persistent_workgroups(tpfa_precision_t prec, int mode, int tiles);
+hipError_t launch_grouped(tpfa_precision_t prec, int mode, int tiles, const Args *d_models,
                           const WorkItem *d_items, int64_t n_items, hipStream_t stream);
 
 // Allocation-free ensemble run: the model table and each model's first work
@@ -177,7 +179,7 @@ struct UploadBlock {
 // The device address of this GPU's array (resolved once per device).
 hipError_t static_scratch(void **ptr);
 hipError_t launch_upload(const UploadBlock &blk, void *scratch, hipStream_t stream);
-hipError_t launch_static_grouped(tpfa_precision_t prec, Mode mode, int tiles, void *scratch,
+hipError_t launch_static_grouped(tpfa_precision_t prec, int mode, int tiles, void *scratch,
                                  int n_models, int64_t n_items, hipStream_t stream);
 
 }  // namespace tpfa

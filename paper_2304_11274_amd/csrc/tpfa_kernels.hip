@@ -92,16 +92,16 @@ __device__ __forceinline__ void march_item(const Args &m, const WorkItem &w, cha
   }
 }
 
-// The FP32 ensemble writes with ordinary stores: ensemble models mostly have
-// rows off 128-byte lines, where these measured much faster, and a per-model
-// choice (both tile bodies in one kernel) cost more registers than it saved
-// on the few aligned models.
+// One item; MODE carries the store kind (MODE_PLAIN: ordinary stores). The
+// FP32 ensemble writes with ordinary stores unless every member's output rows
+// are written in whole lines (padded rows with their padding writable): its
+// models mostly have rows off 128-byte lines, where ordinary stores measured
+// much faster (the partial lines of neighbouring tiles meet in L2), and a
+// per-model choice (both tile bodies in one kernel) cost more registers than
+// it saved. With whole-line rows non-temporal stores gained 2%.
 template <class S, int MODE, int TILE>
 __device__ __forceinline__ void run_item(const Args &m, const WorkItem &w, char *smem, int tid) {
-  if constexpr (sizeof(S) == 4)
-    march_item<S, MODE | MODE_PLAIN, TILE>(m, w, smem, tid);
-  else
-    march_item<S, MODE, TILE>(m, w, smem, tid);
+  march_item<S, MODE, TILE>(m, w, smem, tid);
 }
 
 // Zeroes the band counters of a persistent launch (stream-ordered before it).
@@ -307,15 +307,19 @@ static const void *static_fn(int tiles) {
   }
 }
 
-hipError_t launch_static_grouped(tpfa_precision_t prec, Mode mode, int tiles, void *scr,
-                                 int n_models, int64_t n_items, hipStream_t st) {
-  const void *fn;
+static const void *static_ptr(tpfa_precision_t prec, int mode, int tiles) {
+  const bool res = mode_kind(mode) == MODE_RESIDUAL;
   if (prec == TPFA_FP64)
-    fn = mode == MODE_RESIDUAL ? static_fn<double, MODE_RESIDUAL>(tiles)
-                               : static_fn<double, MODE_JACOBIAN>(tiles);
-  else
-    fn = mode == MODE_RESIDUAL ? static_fn<float, MODE_RESIDUAL>(tiles)
-                               : static_fn<float, MODE_JACOBIAN>(tiles);
+    return res ? static_fn<double, MODE_RESIDUAL>(tiles) : static_fn<double, MODE_JACOBIAN>(tiles);
+  if (has_plain_stores(mode))
+    return res ? static_fn<float, MODE_RESIDUAL | MODE_PLAIN>(tiles)
+               : static_fn<float, MODE_JACOBIAN | MODE_PLAIN>(tiles);
+  return res ? static_fn<float, MODE_RESIDUAL>(tiles) : static_fn<float, MODE_JACOBIAN>(tiles);
+}
+
+hipError_t launch_static_grouped(tpfa_precision_t prec, int mode, int tiles, void *scr,
+                                 int n_models, int64_t n_items, hipStream_t st) {
+  const void *fn = static_ptr(prec, mode, tiles);
   const unsigned char *p = static_cast<const unsigned char *>(scr);
   void *args[] = {(void *)&p, (void *)&n_models};
   return hipLaunchKernel(fn, dim3((unsigned)n_items), dim3(kPersistThreads), args, 0, st);
@@ -502,15 +506,19 @@ static const void *grouped_fn(int tiles) {
   }
 }
 
-hipError_t launch_grouped(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
-                          const WorkItem *d_items, int64_t n_items, hipStream_t st) {
-  const void *fn;
+static const void *grouped_ptr(tpfa_precision_t prec, int mode, int tiles) {
+  const bool res = mode_kind(mode) == MODE_RESIDUAL;
   if (prec == TPFA_FP64)
-    fn = mode == MODE_RESIDUAL ? grouped_fn<double, MODE_RESIDUAL>(tiles)
-                               : grouped_fn<double, MODE_JACOBIAN>(tiles);
-  else
-    fn = mode == MODE_RESIDUAL ? grouped_fn<float, MODE_RESIDUAL>(tiles)
-                               : grouped_fn<float, MODE_JACOBIAN>(tiles);
+    return res ? grouped_fn<double, MODE_RESIDUAL>(tiles) : grouped_fn<double, MODE_JACOBIAN>(tiles);
+  if (has_plain_stores(mode))
+    return res ? grouped_fn<float, MODE_RESIDUAL | MODE_PLAIN>(tiles)
+               : grouped_fn<float, MODE_JACOBIAN | MODE_PLAIN>(tiles);
+  return res ? grouped_fn<float, MODE_RESIDUAL>(tiles) : grouped_fn<float, MODE_JACOBIAN>(tiles);
+}
+
+hipError_t launch_grouped(tpfa_precision_t prec, int mode, int tiles, const Args *d_models,
+                          const WorkItem *d_items, int64_t n_items, hipStream_t st) {
+  const void *fn = grouped_ptr(prec, mode, tiles);
   void *args[] = {(void *)&d_models, (void *)&d_items};
   return hipLaunchKernel(fn, dim3((unsigned)n_items), dim3(kPersistThreads), args, 0, st);
 }
@@ -526,15 +534,17 @@ static const void *persist_fn(int tiles) {
   }
 }
 
-static const void *persist_ptr(tpfa_precision_t prec, Mode mode, int tiles) {
+static const void *persist_ptr(tpfa_precision_t prec, int mode, int tiles) {
+  const bool res = mode_kind(mode) == MODE_RESIDUAL;
   if (prec == TPFA_FP64)
-    return mode == MODE_RESIDUAL ? persist_fn<double, MODE_RESIDUAL>(tiles)
-                                 : persist_fn<double, MODE_JACOBIAN>(tiles);
-  return mode == MODE_RESIDUAL ? persist_fn<float, MODE_RESIDUAL>(tiles)
-                               : persist_fn<float, MODE_JACOBIAN>(tiles);
+    return res ? persist_fn<double, MODE_RESIDUAL>(tiles) : persist_fn<double, MODE_JACOBIAN>(tiles);
+  if (has_plain_stores(mode))
+    return res ? persist_fn<float, MODE_RESIDUAL | MODE_PLAIN>(tiles)
+               : persist_fn<float, MODE_JACOBIAN | MODE_PLAIN>(tiles);
+  return res ? persist_fn<float, MODE_RESIDUAL>(tiles) : persist_fn<float, MODE_JACOBIAN>(tiles);
 }
 
-int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles) {
+int persistent_workgroups(tpfa_precision_t prec, int mode, int tiles) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -546,7 +556,7 @@ int persistent_workgroups(tpfa_precision_t prec, Mode mode, int tiles) {
   return cus * per_cu;
 }
 
-hipError_t launch_persistent(tpfa_precision_t prec, Mode mode, int tiles, const Args *d_models,
+hipError_t launch_persistent(tpfa_precision_t prec, int mode, int tiles, const Args *d_models,
                              const WorkItem *d_items, int64_t n_items, unsigned int *d_counter,
                              int n_workgroups, hipStream_t st) {
   reset_counters_kernel<<<1, 64, 0, st>>>(d_counter);
