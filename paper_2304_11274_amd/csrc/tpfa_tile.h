@@ -87,7 +87,9 @@ struct Props {
 // exp(x) - 1 in float without the cancellation of exp(x) - 1 near 0: for
 // |x| < 1/8 its Taylor series through x^6 / 720 (truncation below 1e-9
 // relative), otherwise the hardware exponential (relative error then a few
-// 1e-7, as for the density itself).
+// 1e-7, as for the density itself). The second case needs |dp| above 1e8 Pa
+// at the workloads' compressibility, so the exponential is evaluated only
+// when a lane of the wave needs it (a wave-uniform branch).
 __device__ __forceinline__ float expm1_series(float x) {
   float c = fmaf(x, 1.0f / 720.0f, 1.0f / 120.0f);
   c = fmaf(x, c, 1.0f / 24.0f);
@@ -95,7 +97,12 @@ __device__ __forceinline__ float expm1_series(float x) {
   c = fmaf(x, c, 0.5f);
   c = fmaf(x, c, 1.0f);
   float m = x * c;
-  if (!(fabsf(x) < 0.125f)) m = __expf(x) - 1.0f;
+  const bool big = !(fabsf(x) < 0.125f);
+  if (__builtin_amdgcn_ballot_w64(big) != 0) {
+    asm volatile("");  // keeps the exponential inside the branch (not speculated)
+    const float e = __expf(x) - 1.0f;
+    m = big ? e : m;
+  }
   return m;
 }
 
@@ -261,6 +268,29 @@ __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open
   upwind<S, DERIV, true>(f, T, (S)dphi, dphi >= 0.0, Lo.lam, Up.lam, cf, fma(hc, Lo.rho, S(1)),
                          fma(hc, Up.rho, S(-1)));
   return f;
+}
+
+// FP32 vector-Jacobian product (permeability-ratio form), one in-plane face
+// seen from the own cell C towards its neighbour N. With q_N = k_N / (k_C + k_N)
+// the transmissibility is T = A2 k_C q_N, and with D = dp_C - dp_N and the
+// upwind mobility lam_u,
+//   F_CN = T lam_u D,   dF_CN/dp_C = T lam_u (1 + cf D) if C is upwind, else T lam_u,
+//   dF_CN/d ln k_C = F_CN q_N.
+// Both gradient terms carry the cotangent difference dw = w_C - w_N and the
+// factor A2 k_C, which is applied once per cell and axis: gp and gm receive
+// the terms divided by it. C_LO: C is the face's lower cell (its +x / +y face),
+// so a tie D = 0 makes C upwind; otherwise N is upwind at a tie.
+template <bool C_LO>
+__device__ __forceinline__ void vjp_face_own(float kC, float kN, bool open, float D, float lamC,
+                                             float lamN, float dw, float cf, float &gp,
+                                             float &gm) {
+  const float ks = fmaxf(kC + kN, 1.17549435e-38f);
+  const float qN = kN * __builtin_amdgcn_rcpf(ks);
+  const bool upC = C_LO ? D >= 0.0f : D > 0.0f;
+  const float X0 = (qN * (upC ? lamC : lamN)) * dw;
+  const float X = open ? X0 : 0.0f;
+  gp = fmaf(X, upC ? fmaf(cf, D, 1.0f) : 1.0f, gp);
+  gm = fmaf(X * D, qN, gm);
 }
 
 // Global-address-space views of the argument pointers: the ensemble kernel
@@ -429,14 +459,24 @@ __device__ __forceinline__ T *at_w(T *base, size_t elems, uint32_t boff) {
   return reinterpret_cast<T *>(pb + boff);
 }
 
+// The FP32 vector-Jacobian product of the permeability-ratio form takes its
+// in-plane faces in the own cell's orientation (vjp_face_own); every other
+// mode forms the faces' Face values.
+template <class S, int MODE>
+constexpr bool vjp_own() {
+  return sizeof(S) == 4 && base_mode(MODE) == MODE_VJP && !has_trans(MODE) && !has_k3(MODE);
+}
+
 // Accumulates and stores one cell's outputs from its six faces (neighbour
 // order -x, +x, -y, +y, -z, +z; odd faces have the cell as their lower cell).
 // In the backward-Euler modes the accumulation term comes first, as in Eq. (2).
+// vo: with vjp_own, the in-plane gradient sums of vjp_face_own (pressure x, y,
+// then ln k x, y), which replace faces 0-3.
 template <class S, int MODE>
 __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz, uint32_t cb,
                                      const Cell<S> &c0, const Props<S> &d0, S xk, S rk,
                                      const Face<S> (&f)[6], const S (&wn)[6],
-                                     const S (&fd)[4]) {
+                                     const S (&fd)[4], const S (&vo)[4]) {
   if constexpr (sizeof(S) == 4) cb = per_plane(cb, k);
   constexpr int BASE = base_mode(MODE);
   constexpr bool ACC = has_accumulation(MODE);
@@ -445,10 +485,18 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
     // grad_p[C] = sum (w_C - w_N) dF_CN/dp_C, grad_logk[C] = sum (w_C - w_N) F_CN k_N/(k_C+k_N)
     // per-direction form: the faces of axis d feed the ln k_d gradient only.
     // FP64: terms and sums in FP64. FP32 form: float terms and float sums of
-    // the six terms (error below about 6 ulp of the sum of their magnitudes)
+    // the six terms (error below about 6 ulp of the sum of their magnitudes);
+    // with vjp_own the in-plane terms arrive summed per axis and are scaled by
+    // the axis' A2 k_C here
+    constexpr bool OWN = vjp_own<S, MODE>();
     S gp = S(0), gm = S(0), gq[3] = {S(0), S(0), S(0)};
+    if constexpr (OWN) {
+      const float sx = a.a2xf * c0.k, sy = a.a2yf * c0.k;
+      gp = fmaf(sx, vo[0], sy * vo[1]);
+      gm = fmaf(sx, vo[2], sy * vo[3]);
+    }
 #pragma unroll
-    for (int n = 0; n < 6; ++n) {
+    for (int n = OWN ? 4 : 0; n < 6; ++n) {
       if constexpr (sizeof(S) == 4) {
         const float d = (n & 1) ? c0.w - wn[n] : wn[n] - c0.w;
         const float tp = d * ((n & 1) ? f[n].dLo : f[n].dUp);
@@ -915,31 +963,52 @@ struct Tile {
     // whose neighbour does not exist has T = 0 and contributes exact zeros
     Face<S> f[6];
     S wn[6];
+    S vo[4] = {};
     const int Wv = w_();
     const int sl[4] = {ol - 1, ol + 1, ol - Wv, ol + Wv};
+    if constexpr (vjp_own<S, MODE>()) {
+      const float cf = a.cff;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const int axis = n >> 1;
-      const int q = b + sl[n];
-      const S pn = s_p[q];
-      // k of the neighbour along this face's direction (k_y from its own
-      // array in the per-direction form)
-      const S kn = (K3 && axis == 1) ? s_yf[q] : s_k[q];
-      const S kc = (K3 && axis == 1) ? c0.ky : c0.k;
-      const S ln = s_l[q];
-      const uint32_t sn = s_s[q];
-      if (NEEDW) wn[n] = s_w[q];
-      const uint32_t bit = 1u << axis;
-      const S A2 = axis == 0 ? A2x : A2y;
-      if constexpr (TIN) {
-        // the face's transmissibility is stored on its lower cell
-        const S T = (n & 1) ? (axis == 0 ? c0.tx : c0.ty) : (axis == 0 ? kn : s_yf[q]);
-        f[n] = (n & 1) ? face_ht<DERIV>(a, T, c0.p, pn, d0.lam, ln)
-                       : face_ht<DERIV>(a, T, pn, c0.p, ln, d0.lam);
-      } else if (n & 1) {
-        f[n] = face_h<DERIV, VJP>(a, A2, kc, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
-      } else {
-        f[n] = face_h<DERIV, VJP>(a, A2, kn, kc, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
+      for (int n = 0; n < 4; ++n) {
+        const int axis = n >> 1;
+        const int q = b + sl[n];
+        const float D = c0.p - s_p[q];
+        const float dw = c0.w - s_w[q];
+        const uint32_t bit = 1u << axis;
+        // the face's seal bit is its lower cell's
+        const bool open = (((n & 1) ? c0.s : (uint32_t)s_s[q]) & bit) == 0u;
+        if (n & 1)
+          vjp_face_own<true>(c0.k, s_k[q], open, D, d0.lam, s_l[q], dw, cf, vo[axis],
+                             vo[2 + axis]);
+        else
+          vjp_face_own<false>(c0.k, s_k[q], open, D, d0.lam, s_l[q], dw, cf, vo[axis],
+                              vo[2 + axis]);
+      }
+    } else {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int axis = n >> 1;
+        const int q = b + sl[n];
+        const S pn = s_p[q];
+        // k of the neighbour along this face's direction (k_y from its own
+        // array in the per-direction form)
+        const S kn = (K3 && axis == 1) ? s_yf[q] : s_k[q];
+        const S kc = (K3 && axis == 1) ? c0.ky : c0.k;
+        const S ln = s_l[q];
+        const uint32_t sn = s_s[q];
+        if (NEEDW) wn[n] = s_w[q];
+        const uint32_t bit = 1u << axis;
+        const S A2 = axis == 0 ? A2x : A2y;
+        if constexpr (TIN) {
+          // the face's transmissibility is stored on its lower cell
+          const S T = (n & 1) ? (axis == 0 ? c0.tx : c0.ty) : (axis == 0 ? kn : s_yf[q]);
+          f[n] = (n & 1) ? face_ht<DERIV>(a, T, c0.p, pn, d0.lam, ln)
+                         : face_ht<DERIV>(a, T, pn, c0.p, ln, d0.lam);
+        } else if (n & 1) {
+          f[n] = face_h<DERIV, VJP>(a, A2, kc, kn, (c0.s & bit) == 0u, c0.p, pn, d0.lam, ln);
+        } else {
+          f[n] = face_h<DERIV, VJP>(a, A2, kn, kc, (sn & bit) == 0u, pn, c0.p, ln, d0.lam);
+        }
       }
     }
     f[4] = zm;
@@ -977,7 +1046,7 @@ struct Tile {
       }
     }
     if (!own) return;
-    emit<S, MODE>(a, k, plane, nz, sb, c0, d0, ACC ? xoff(k) : S(0), rkk, f, wn, fd);
+    emit<S, MODE>(a, k, plane, nz, sb, c0, d0, ACC ? xoff(k) : S(0), rkk, f, wn, fd, vo);
   }
 
   // ---- shared-face form (residual-only modes) ----------------------------
