@@ -8,6 +8,11 @@ vector changing every call as in the paper's protocol (Sec. 3: the flux
 computation is applied 1000 times with a different pressure vector each time);
 four pre-generated pressure fields rotate so that nothing is served from the
 256 MB last-level cache. Inputs are resident in HBM before the timed region.
+r and J are written in the library's sliced layout (TPFA_LAUNCH_SLICED: one
+array of 64-cell row slices, each holding r and the seven Jacobian values of
+its cells as eight runs of 64, the sliced ELLPACK order a matrix-vector product
+reads); the same call with r and the seven Jacobian planes in eight separate
+arrays is timed beside it (``--layouts``).
 
 The same run also times, as extra fields of the JSON line:
   fp32     - the precision form (FP32 storage, FP64 potential/accumulation) on the same grid
@@ -50,6 +55,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cells/s (residual+Jacobian) and % of HBM roofline, FP64 vs FP32 vs batched"
 HBM_PEAK_GBS = 8000.0
+LAYOUTS = {"sliced": "sliced (TPFA_LAUNCH_SLICED): one array of 64-cell row slices, each "
+                     "holding r and the 7 Jacobian values of its cells as 8 runs of 64",
+           "planes": "r and the 7 Jacobian planes in 8 separate (nz, ny, nx) arrays"}
 # algorithmic bytes per cell: each input read once, each output written once
 BYTES_FP64_RJ = 8 + 8 + 1 + 8 + 7 * 8      # p, kx, seal -> r, J  = 81
 BYTES_FP32_RJ = 4 + 4 + 1 + 4 + 7 * 4      # dp, kx, seal -> r, J = 41
@@ -236,6 +244,7 @@ def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
     cpu = _cpu_model()
     cores = len(os.sched_getaffinity(0))
     want = ("r", "J", "scale", "dphi")
+    layout = args.layouts.split(",")[0]  # the fp64 / fp32 sections' headline output layout
     base = {"unit": "cells/s", "cores": 1, "kind": "oracle", "host_cores_available": cores}
     out["cpu_baselines"], out["parity"] = {}, {}
 
@@ -294,9 +303,22 @@ def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
         sample=f"the whole 512x512x256 workload, pressure field 0: FP64 r + J with the error "
                f"scales and face potentials, single-threaded plain oracle, {dt2:.1f} s on {cpu}")
     kx64, sl = up(geo.kx), up(geo.seal)
-    r2, J2 = tp.jacobian(g, fl, kx64, up(p2), seal=sl, ry=geo.ry, rz=geo.rz)
+
+    def rj(kx_, p_, **kw):
+        """r, J of one application in the headline layout (planes copied out of
+        the sliced array), and whether they equal the plane layout's bitwise."""
+        rp, Jp = tp.jacobian(g, fl, kx_, p_, seal=sl, ry=geo.ry, rz=geo.rz, **kw)
+        if layout != "sliced":
+            return rp, Jp, True
+        _, Js = tp.jacobian(g, fl, kx_, p_, seal=sl, ry=geo.ry, rz=geo.rz, sliced=True, **kw)
+        rs, Js_ = tp.unslice(g, Js)
+        del Js
+        return rs, Js_, bool(torch.equal(rs, rp) and torch.equal(Js_, Jp))
+
+    r2, J2, same2 = rj(kx64, up(p2))
     rep2 = _report(np, rj_errors(np, host(r2), host(J2), ref2), ref2["dphi"],
-                   1e-9 * float(np.abs(p2).max()), 1e-12)
+                   1e-9 * float(np.abs(p2).max()), 1e-12,
+                   {"output_layout": layout, "equal_to_planes_layout_bitwise": same2})
     out["parity"]["fp64_512"] = rep2
     del r2, J2
     log(f"oracle leg 512^2x256 FP64: {rep2} (oracle {dt2:.1f} s)")
@@ -306,7 +328,7 @@ def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
     # on the widened FP32 inputs (the bound)
     k32 = geo.kx.astype(np.float32)
     dp32 = geo.noise[0].astype(np.float32)
-    r3, J3 = tp.jacobian(g, fl, up(k32), up(dp32), seal=sl, pref=pref, ry=geo.ry, rz=geo.rz)
+    r3, J3, same3 = rj(up(k32), up(dp32), pref=pref)
     r3, J3 = host(r3), host(J3)
     info = float(rj_errors(np, r3, J3, ref2).max())
     del ref2, p2
@@ -314,7 +336,8 @@ def oracle_leg(out, args, tp, torch, np, dev, geo, pref):
     ref3, dt3 = timed(lambda: oracle.evaluate(g, fl, k32.astype(np.float64), p3, ry=geo.ry,
                                               rz=geo.rz, seal=geo.seal, want=want))
     rep3 = _report(np, rj_errors(np, r3, J3, ref3), ref3["dphi"], 1e-4, 1e-5,
-                   {"max_rel_err_vs_unquantised_fp64_inputs": info})
+                   {"max_rel_err_vs_unquantised_fp64_inputs": info, "output_layout": layout,
+                    "equal_to_planes_layout_bitwise": same3})
     out["parity"]["fp32_512"] = rep3
     out["cpu_baselines"]["fp32_form_widened_inputs"] = dict(
         base, value=N / dt3,
@@ -411,6 +434,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--paper10-steps", type=int, default=1000,
                     help="applications per mesh in the paper10 section (the paper uses 1000)")
+    ap.add_argument("--layouts", default="sliced,planes",
+                    help="output layouts of the fp64 and fp32 sections: the first is the "
+                         "headline ('sliced' or 'planes'), the others are timed beside it")
     ap.add_argument("--ensemble-launch", default=None,
                     help="fixed ensemble launch 'assignment/kz/schedule' (e.g. tile0/16/grouped) "
                          "instead of the autotuner; per-model launches then take the library "
@@ -451,11 +477,24 @@ def main():
     noise = [up(nz_) for nz_ in geo.noise]
     del geo.logk
     log(f"inputs 512x512x256 generated and resident in {time.time() - t0:.1f} s")
+    layouts = args.layouts.split(",")
+    if not layouts or any(lo not in LAYOUTS for lo in layouts):
+        ap.error(f"--layouts takes a list of {sorted(LAYOUTS)}")
     out["config"] = {"workload": "512x512x256 FP64 residual + 7-point Jacobian (6-face TPFA), "
                                  "4 rotating pressure fields",
                      "cells": N, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
                      "sigma_lnk": 1.5, "ry": 1.0, "rz": 0.1, "seal_fraction": 0.01,
+                     "output_layout": LAYOUTS[layouts[0]],
                      "launch": "library default (64x8 tiles, 32 z-planes per workgroup)"}
+
+    def rj_call(prec_kx, pfields, layout, extra):
+        """One r + J application per step in an output layout (buffers allocated here)."""
+        if layout == "sliced":
+            o = dict(J_out=tp.empty_sliced(g, prec_kx.dtype, dev), sliced=True)
+        else:
+            o = dict(r_out=torch.empty(g.shape, dtype=prec_kx.dtype, device=dev),
+                     J_out=torch.empty((7,) + g.shape, dtype=prec_kx.dtype, device=dev))
+        return lambda s: tp.jacobian(g, fl, prec_kx, pfields[s % 4], **extra, **o)
 
     def rate(ms, k, bytes_per_cell):
         t = ms / 1e3 / k
@@ -466,11 +505,9 @@ def main():
     # ------------------------------------------------------- FP64 r + J (value)
     if "fp64" in sections:
         ps = [(pref[:, None, None] + nz_).contiguous() for nz_ in noise]
-        r = torch.empty(g.shape, dtype=torch.float64, device=dev)
-        J = torch.empty((7,) + g.shape, dtype=torch.float64, device=dev)
-        kw = dict(seal=seal, ry=geo.ry, rz=geo.rz, r_out=r, J_out=J)
+        step = rj_call(kx64, ps, layouts[0], dict(seal=seal, ry=geo.ry, rz=geo.rz))
         for s in range(W):
-            tp.jacobian(g, fl, kx64, ps[s % 4], **kw)
+            step(s)
         # five equal chunks of the K timed steps, each bracketed by events on the
         # same stream (no synchronisation inside the timed region): mean and
         # SD of the per-step time over the chunks
@@ -481,7 +518,7 @@ def main():
             marks[0].record()
             for c in range(n_chunks):
                 for s in range(bounds[c], bounds[c + 1]):
-                    tp.jacobian(g, fl, kx64, ps[s % 4], **kw)
+                    step(s)
                 marks[c + 1].record()
         res = rate(tm.ms, K, BYTES_FP64_RJ)
         per = [marks[c].elapsed_time(marks[c + 1]) / (bounds[c + 1] - bounds[c])
@@ -500,8 +537,22 @@ def main():
                            "algorithmic_bytes_per_launch": BYTES_FP64_RJ * N,
                            "kernel": "march_kernel<double, JACOBIAN, 64, 8>",
                            "bytes_per_cell": BYTES_FP64_RJ}
-        log(f"fp64 r+J: {res['ms_per_step']:.4f} ms/step, {res['cells_per_s'] / 1e9:.2f} "
-            f"Gcell/s, {res['algorithmic_GBps']:.0f} GB/s ({100 * res['hbm_frac']:.1f}% of 8 TB/s)")
+        log(f"fp64 r+J ({layouts[0]}): {res['ms_per_step']:.4f} ms/step, "
+            f"{res['cells_per_s'] / 1e9:.2f} Gcell/s, {res['algorithmic_GBps']:.0f} GB/s "
+            f"({100 * res['hbm_frac']:.1f}% of 8 TB/s)")
+        del step
+        out["fp64_layouts"] = {layouts[0]: res}
+        for lo in layouts[1:]:
+            other = rj_call(kx64, ps, lo, dict(seal=seal, ry=geo.ry, rz=geo.rz))
+            for s in range(W):
+                other(s)
+            with Timer(torch) as tm:
+                for s in range(K):
+                    other(s)
+            out["fp64_layouts"][lo] = rate(tm.ms, K, BYTES_FP64_RJ)
+            del other
+            log(f"fp64 r+J ({lo}): {out['fp64_layouts'][lo]}")
+        r = torch.empty(g.shape, dtype=torch.float64, device=dev)
         if "res" in sections:
             for s in range(W):
                 tp.residual(g, fl, kx64, ps[s % 4], seal=seal, ry=geo.ry, rz=geo.rz, out=r)
@@ -510,26 +561,30 @@ def main():
                     tp.residual(g, fl, kx64, ps[s % 4], seal=seal, ry=geo.ry, rz=geo.rz, out=r)
             out.setdefault("residual", {})["fp64"] = rate(tm.ms, KA, BYTES_FP64_R)
             log(f"fp64 residual: {out['residual']['fp64']}")
-        del r, J, ps
+        del r, ps
         torch.cuda.empty_cache()
 
     # ------------------------------------------------- FP32 precision form r + J
     if "fp32" in sections:
         dps = [nz_.float() for nz_ in noise]
         kx32 = kx64.float()
-        r = torch.empty(g.shape, dtype=torch.float32, device=dev)
-        J = torch.empty((7,) + g.shape, dtype=torch.float32, device=dev)
-        kw = dict(seal=seal, pref=pref, ry=geo.ry, rz=geo.rz, r_out=r, J_out=J)
-        for s in range(W):
-            tp.jacobian(g, fl, kx32, dps[s % 4], **kw)
-        with Timer(torch) as tm:
-            for s in range(KA):
-                tp.jacobian(g, fl, kx32, dps[s % 4], **kw)
-        res = rate(tm.ms, KA, BYTES_FP32_RJ)
+        kw = dict(seal=seal, pref=pref, ry=geo.ry, rz=geo.rz)
+        lay_res = {}
+        for lo in layouts:
+            step = rj_call(kx32, dps, lo, kw)
+            for s in range(W):
+                step(s)
+            with Timer(torch) as tm:
+                for s in range(KA):
+                    step(s)
+            lay_res[lo] = rate(tm.ms, KA, BYTES_FP32_RJ)
+            del step
+        res = dict(lay_res[layouts[0]], output_layout=layouts[0], layouts=lay_res)
         if out["value"]:
             res["speedup_vs_fp64"] = res["cells_per_s"] / out["value"]
         out["fp32"] = res
         log(f"fp32 r+J: {res}")
+        r = torch.empty(g.shape, dtype=torch.float32, device=dev)
         if "res" in sections:
             for s in range(W):
                 tp.residual(g, fl, kx32, dps[s % 4], seal=seal, pref=pref, ry=geo.ry,
@@ -540,7 +595,7 @@ def main():
                                 rz=geo.rz, out=r)
             out.setdefault("residual", {})["fp32"] = rate(tm.ms, KA, BYTES_FP32_R)
             log(f"fp32 residual: {out['residual']['fp32']}")
-        del r, J, dps, kx32
+        del r, dps, kx32
         torch.cuda.empty_cache()
 
     # ----------------------- Newton step operators: backward-Euler r and J v

@@ -166,6 +166,23 @@ typedef struct {
    Values of real cells do not change; inputs' padding is still never read.
    Kept from the caller's flags also with tile = -1. */
 #define TPFA_LAUNCH_PAD_WRITES 4
+/* flags bit 3, tpfa_jacobian and tpfa_jacobian_be only (TPFA_ERR_UNSUPPORTED
+   elsewhere): r and J are written into ONE array, J, of 64-cell row slices,
+   and r must be NULL (TPFA_ERR_PARAM otherwise). With S = ceil(nx / 64)
+   slices per row, slice s of row j of plane k holds 8 runs of 64 values:
+   run 0 the residual, runs 1..7 the Jacobian planes 0..6 of tpfa_jacobian,
+   value (q, i, j, k) at element (((k ny + j) S + i / 64) 8 + q) 64 + i % 64;
+   the array holds nz ny S 512 elements. This is the sliced ELLPACK order
+   (slices of C = 64 rows, 7 diagonals) that a matrix-vector product reads in
+   whole lines. The lanes of a row's last slice beyond nx store zeros, so
+   every slice of a computed row is written whole; rows outside the launch's
+   row range are left untouched. ldx applies to the inputs only; one z plane
+   of the array must hold fewer than 2^32 bytes (TPFA_ERR_SHAPE). On MI355X
+   the one output stream wrote faster than eight planes: a streaming kernel
+   with the FP64 Jacobian's traffic (17 B read, 64 B written per cell) ran
+   at 4.92 TB/s with eight output planes and 5.49 TB/s with the slices.
+   The batch takes it per member (member r NULL). */
+#define TPFA_LAUNCH_SLICED 8
 
 /* Residual r[ncell] (paper Algorithm 1 with the Eq. (3)-(5) flux). */
 int tpfa_residual(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,

@@ -29,6 +29,7 @@ TPFA_BATCH_JACOBIAN = 1
 TPFA_LAUNCH_XCD_REMAP = 1
 TPFA_LAUNCH_Y_FAST = 2
 TPFA_LAUNCH_PAD_WRITES = 4
+TPFA_LAUNCH_SLICED = 8
 TPFA_TILE_FIT = 10
 TPFA_SCHEDULE_PERSISTENT = 0
 TPFA_SCHEDULE_GROUPED = 1

@@ -12,6 +12,7 @@ take the layout of ``p``.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from typing import Optional, Sequence
 
 import torch
@@ -34,13 +35,15 @@ def _fluid(f) -> L.Fluid:
 
 
 def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None,
-            pad_writes: bool = False):
+            pad_writes: bool = False, sliced: bool = False):
     """``xcd_remap``: True (or "bands") for the XCD band order, "yfast" for the
     y-fast tile order, False for the natural order. ``rows`` = (y_begin, y_end):
     compute and write only those rows (a y slab; the grid's other rows are read
     as its halo). ``pad_writes``: the outputs' row padding may be overwritten
-    (zeros), so that rows of row-pitched outputs are written in whole lines."""
-    if tile is None and kz_chunk is None and not xcd_remap and rows is None and not pad_writes:
+    (zeros), so that rows of row-pitched outputs are written in whole lines.
+    ``sliced``: r and J go to one array of 64-cell slices (see sliced_shape)."""
+    if (tile is None and kz_chunk is None and not xcd_remap and rows is None and not pad_writes
+            and not sliced):
         return None
     if xcd_remap == "yfast":
         flags = L.TPFA_LAUNCH_Y_FAST
@@ -52,6 +55,8 @@ def _launch(tile: Optional[int], kz_chunk: Optional[int], xcd_remap, rows=None,
         raise ValueError(f"unknown workgroup order {xcd_remap!r}")
     if pad_writes:
         flags |= L.TPFA_LAUNCH_PAD_WRITES
+    if sliced:
+        flags |= L.TPFA_LAUNCH_SLICED
     y0, y1 = (0, 0) if rows is None else (int(rows[0]), int(rows[1]))
     return L.Launch(-1 if tile is None else int(tile), 0 if kz_chunk is None else int(kz_chunk),
                     flags, y0, y1)
@@ -147,6 +152,36 @@ def empty_pitched(grid, dtype, device=None, lead=(), ldx: Optional[int] = None) 
         raise ValueError(f"row pitch {ld} is below nx = {grid.nx}")
     buf = torch.empty(tuple(lead) + (int(grid.nz), int(grid.ny), ld), dtype=dtype, device=device)
     return buf[..., :int(grid.nx)]
+
+
+def sliced_shape(grid):
+    """Shape (nz, ny, S, 8, 64) of the sliced r + J array, S = ceil(nx / 64):
+    slice s of row j of plane k holds the residual (run 0) and the Jacobian
+    planes diag, -x, +x, -y, +y, -z, +z (runs 1..7) of the cells
+    64 s <= i < 64 s + 64; lanes beyond nx hold zeros."""
+    return (int(grid.nz), int(grid.ny), (int(grid.nx) + 63) // 64, 8, 64)
+
+
+def empty_sliced(grid, dtype, device=None) -> torch.Tensor:
+    """Uninitialised sliced r + J array (sliced_shape)."""
+    return torch.empty(sliced_shape(grid), dtype=dtype, device=device)
+
+
+def unslice(grid, Js: torch.Tensor):
+    """(r[nz, ny, nx], J[7, nz, ny, nx]) copied out of a sliced r + J array."""
+    nz, ny, S = sliced_shape(grid)[:3]
+    planes = Js.reshape(nz, ny, S, 8, 64).permute(3, 0, 1, 2, 4).reshape(8, nz, ny, S * 64)
+    planes = planes[..., :int(grid.nx)].contiguous()
+    return planes[0], planes[1:]
+
+
+def _sliced_out(J_out, p, grid, want_r, r_out, dt, dev):
+    """The sliced r + J array of a Jacobian call (allocated unless given)."""
+    if want_r is not True or r_out is not None:
+        raise ValueError("sliced=True writes the residual into J (run 0): leave want_r and r_out")
+    J = J_out if J_out is not None else empty_sliced(grid, dt, dev)
+    _need(J, "J_out", dt, math.prod(sliced_shape(grid)), dev)
+    return J
 
 
 def to_pitched(t: torch.Tensor, grid, ldx: Optional[int] = None) -> torch.Tensor:
@@ -257,29 +292,33 @@ def residual(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=Non
     return r
 
 
-def _launch_ref(tile, kz_chunk, xcd_remap, rows=None, pad_writes=False):
-    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes)
+def _launch_ref(tile, kz_chunk, xcd_remap, rows=None, pad_writes=False, sliced=False):
+    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes, sliced)
     return None if ln is None else C.byref(ln)
 
 
 def jacobian(grid, fluid, kx, p, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None, kz=None,
              want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
-             xcd_remap=False, rows=None, pad_writes=False):
+             xcd_remap=False, rows=None, pad_writes=False, sliced=False):
     """Residual (or None) and Jacobian J[7, nz, ny, nx], planes
-    [diag, -x, +x, -y, +y, -z, +z]."""
+    [diag, -x, +x, -y, +y, -z, +z]. With ``sliced``: (None, the sliced r + J
+    array of sliced_shape), which unslice turns into planes."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     r = None
-    if want_r:
-        r = r_out if r_out is not None else _empty(p, lay)
-        _need(r, "r_out", dt, n, dev, lay)
-    J = J_out if J_out is not None else _empty(p, lay, (7,))
-    _need(J, "J_out", dt, 7 * n, dev, lay)
-    _pad_ok(pad_writes, lay, r_out=r, J_out=J)
+    if sliced:
+        J = _sliced_out(J_out, p, grid, want_r, r_out, dt, dev)
+    else:
+        if want_r:
+            r = r_out if r_out is not None else _empty(p, lay)
+            _need(r, "r_out", dt, n, dev, lay)
+        J = J_out if J_out is not None else _empty(p, lay, (7,))
+        _need(J, "J_out", dt, 7 * n, dev, lay)
+        _pad_ok(pad_writes, lay, r_out=r, J_out=J)
     lib = L.load()
     L.check(lib.tpfa_jacobian(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                               C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                               C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(r), _ptr(J),
-                              _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                              _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes, sliced),
                               _stream(dev)), lib)
     return r, J
 
@@ -345,25 +384,29 @@ def residual_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1
 
 def jacobian_be(grid, fluid, kx, p, accum, *, seal=None, pref=None, ry=1.0, rz=1.0, ky=None,
                 kz=None, want_r=True, r_out=None, J_out=None, trans=None, tile=None, kz_chunk=None,
-                xcd_remap=False, rows=None, pad_writes=False):
-    """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]."""
+                xcd_remap=False, rows=None, pad_writes=False, sliced=False):
+    """Backward-Euler residual (or None) and its Jacobian J[7, nz, ny, nx]
+    (with ``sliced``: None and the sliced r + J array, as for jacobian)."""
     n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref, trans, _kyz(ky, kz))
     acc = _accum(accum, dt, n, dev, lay)
     if acc is None:
         raise ValueError("jacobian_be needs accum")
     r = None
-    if want_r:
-        r = r_out if r_out is not None else _empty(p, lay)
-        _need(r, "r_out", dt, n, dev, lay)
-    J = J_out if J_out is not None else _empty(p, lay, (7,))
-    _need(J, "J_out", dt, 7 * n, dev, lay)
-    _pad_ok(pad_writes, lay, r_out=r, J_out=J)
+    if sliced:
+        J = _sliced_out(J_out, p, grid, want_r, r_out, dt, dev)
+    else:
+        if want_r:
+            r = r_out if r_out is not None else _empty(p, lay)
+            _need(r, "r_out", dt, n, dev, lay)
+        J = J_out if J_out is not None else _empty(p, lay, (7,))
+        _need(J, "J_out", dt, 7 * n, dev, lay)
+        _pad_ok(pad_writes, lay, r_out=r, J_out=J)
     lib = L.load()
     L.check(lib.tpfa_jacobian_be(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
                                  C.byref(_rock(kx, seal, ry, rz, trans, ky, kz)),
                                  C.byref(L.State(_ptr(p), _ptr(pref))), C.byref(acc), prec,
                                  _ptr(r), _ptr(J),
-                                 _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                                 _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes, sliced),
                                  _stream(dev)), lib)
     return r, J
 
@@ -476,7 +519,7 @@ _GIVEN = 1  # non-null marker for an array: tpfa_resolve_launch only reads which
 
 def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=None,
                    kz_chunk=None, xcd_remap=False, rows=None, ldx: Optional[int] = None,
-                   pad_writes: bool = False) -> dict:
+                   pad_writes: bool = False, sliced: bool = False) -> dict:
     """The launch a call of ``op`` ('residual', 'jacobian', 'vjp', 'residual10',
     'residual_be', 'jacobian_be', 'jvp', 'jvp_be') would make on this grid in
     this precision, rock form ('k': kx with ratios, 'k3': kx, ky, kz arrays,
@@ -488,7 +531,7 @@ def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=
     rock = {"k": L.Rock(G, None, None, 1.0, 1.0, None),
             "k3": L.Rock(G, G, G, 1.0, 1.0, None),
             "trans": L.Rock(None, None, None, 1.0, 1.0, None, G, G, G)}[form]
-    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes)
+    ln = _launch(tile, kz_chunk, xcd_remap, rows, pad_writes, sliced)
     out = L.Launch()
     lib = L.load()
     L.check(lib.tpfa_resolve_launch(C.byref(_grid(grid, int(grid.nx) if ldx is None else ldx)),
@@ -500,7 +543,8 @@ def resolve_launch(grid, op: str, dtype=torch.float64, *, form: str = "k", tile=
             "order": ("bands" if out.flags & L.TPFA_LAUNCH_XCD_REMAP else
                       "yfast" if out.flags & L.TPFA_LAUNCH_Y_FAST else "natural"),
             "rows": (out.y_begin, out.y_end),
-            "pad_writes": bool(out.flags & L.TPFA_LAUNCH_PAD_WRITES)}
+            "pad_writes": bool(out.flags & L.TPFA_LAUNCH_PAD_WRITES),
+            "sliced": bool(out.flags & L.TPFA_LAUNCH_SLICED)}
 
 
 def fit_tile_shape(nx: int, rows: int):
@@ -543,17 +587,22 @@ def ensemble_run_noalloc(members: Sequence[dict], outputs: Sequence[tuple], *,
             prec, device = pr, dev
         elif pr != prec or dev != device:
             raise ValueError("all ensemble members need the same precision and device")
-        if bm == L.TPFA_BATCH_JACOBIAN:
-            _need(J, "J", dt, 7 * n, dev, lay)
-        if r is not None or bm == L.TPFA_BATCH_RESIDUAL:
-            _need(r, "r", dt, n, dev, lay)
-        _pad_ok(d.get("pad_writes", False), lay, r=r,
-                J=J if bm == L.TPFA_BATCH_JACOBIAN else None)
+        if d.get("sliced", False):
+            if r is not None:
+                raise ValueError("a sliced member takes r = None (the residual is in J)")
+            _need(J, "J", dt, math.prod(sliced_shape(g)), dev)
+        else:
+            if bm == L.TPFA_BATCH_JACOBIAN:
+                _need(J, "J", dt, 7 * n, dev, lay)
+            if r is not None or bm == L.TPFA_BATCH_RESIDUAL:
+                _need(r, "r", dt, n, dev, lay)
+            _pad_ok(d.get("pad_writes", False), lay, r=r,
+                    J=J if bm == L.TPFA_BATCH_JACOBIAN else None)
         arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
                          _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                          L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
                          _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"),
-                                 d.get("pad_writes", False))
+                                 d.get("pad_writes", False), d.get("sliced", False))
                          or L.Launch(-1, 0, 0, 0, 0))
     lib = L.load()
     L.check(lib.tpfa_ensemble_run_noalloc(arr, len(members), prec, bm, _stream(device)), lib)
@@ -562,9 +611,10 @@ def ensemble_run_noalloc(members: Sequence[dict], outputs: Sequence[tuple], *,
 class Ensemble:
     """Many independent grids run by one persistent kernel replayed from a
     HIP graph. ``members`` is a sequence of dicts with keys grid, fluid, kx,
-    p, and optionally seal, pref, ry, rz, tile, kz_chunk, rows, pad_writes.
-    Outputs are allocated here in the layout of the member's ``p`` (``r[m]``,
-    ``J[m]``) and overwritten by every run."""
+    p, and optionally seal, pref, ry, rz, tile, kz_chunk, rows, pad_writes,
+    sliced. Outputs are allocated here in the layout of the member's ``p``
+    (``r[m]``, ``J[m]``; a sliced member: ``r[m]`` None and ``J[m]`` its sliced
+    r + J array) and overwritten by every run."""
 
     def __init__(self, members: Sequence[dict], *, mode: str = "jacobian", want_r: bool = True):
         if not members:
@@ -581,17 +631,21 @@ class Ensemble:
                 prec, self.device = pr, dev
             elif pr != prec or dev != self.device:
                 raise ValueError("all ensemble members need the same precision and device")
-            r = _empty(p, lay) if (
-                want_r or self.mode == L.TPFA_BATCH_RESIDUAL) else None
-            J = _empty(p, lay, (7,)) if (
-                self.mode == L.TPFA_BATCH_JACOBIAN) else None
+            if d.get("sliced", False):
+                r, J = None, empty_sliced(g, dt, dev)
+            else:
+                r = _empty(p, lay) if (
+                    want_r or self.mode == L.TPFA_BATCH_RESIDUAL) else None
+                J = _empty(p, lay, (7,)) if (
+                    self.mode == L.TPFA_BATCH_JACOBIAN) else None
             self.r.append(r)
             self.J.append(J)
             arr[m] = L.Model(_grid(g, lay.pitch), _fluid(d["fluid"]),
                              _rock(d["kx"], d.get("seal"), d.get("ry", 1.0), d.get("rz", 1.0)),
                              L.State(_ptr(p), _ptr(d.get("pref"))), _ptr(r), _ptr(J),
                              _launch(d.get("tile"), d.get("kz_chunk"), False, d.get("rows"),
-                                     d.get("pad_writes", False)) or L.Launch(-1, 0, 0, 0, 0))
+                                     d.get("pad_writes", False), d.get("sliced", False))
+                             or L.Launch(-1, 0, 0, 0, 0))
         self.prec = prec
         self._handle = C.c_void_p()
         self._lib = L.load()

@@ -63,15 +63,19 @@ def tune_member(m: dict, *, tiles: Sequence[int] = TILE_IDS_256,
     best_u = max(util.values())
     cands = [(t, z) for t in tiles if util[t] >= keep * best_u for z in kz if z <= 2 * g.nz]
     p = m["p"]
-    # outputs in the member's layout (its row pitch)
+    # outputs in the member's layout (its row pitch, or the sliced r + J array)
+    sliced = mode == "jacobian" and m.get("sliced", False)
     ld = p.stride(-2) if g.ny > 1 else (p.stride(-3) if g.nz > 1 else g.nx)
     r = api.empty_pitched(g, p.dtype, p.device, (), ld)
-    J = api.empty_pitched(g, p.dtype, p.device, (7,), ld)
+    J = (api.empty_sliced(g, p.dtype, p.device) if sliced
+         else api.empty_pitched(g, p.dtype, p.device, (7,), ld))
     best = None
     for t, z in cands:
         kw = dict(seal=m.get("seal"), pref=m.get("pref"), ry=m.get("ry", 1.0),
                   rz=m.get("rz", 1.0), tile=t, kz_chunk=z, pad_writes=m.get("pad_writes", False))
-        if mode == "jacobian":
+        if sliced:
+            fn = lambda: api.jacobian(g, m["fluid"], m["kx"], p, J_out=J, sliced=True, **kw)  # noqa: E731
+        elif mode == "jacobian":
             fn = lambda: api.jacobian(g, m["fluid"], m["kx"], p, r_out=r, J_out=J, **kw)  # noqa: E731
         else:
             fn = lambda: api.residual(g, m["fluid"], m["kx"], p, out=r, **kw)  # noqa: E731

@@ -124,8 +124,10 @@ int check_common(const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa_rock_t 
 // on grids at least 128 cells wide; narrow grids take narrower tiles. The
 // FP64 Jacobian of the per-direction form (`form` = MODE_K3) needs more than
 // 128 VGPRs, which leaves one 512-thread workgroup per CU: 64x4 measured 20%
-// faster there.
-int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form) {
+// faster there. Sliced outputs are written in whole slices whatever nx is:
+// 64x8 there (500x500x256 FP64: 1.01 ms against 1.10 ms with 128x4).
+int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, int form,
+                 bool sliced) {
   if (g.nx <= 16) return 2;
   if (g.nx <= 32) return 1;
   const int b = tpfa::base_mode(mode);
@@ -133,7 +135,7 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
   if (b == tpfa::MODE_VJP || b == tpfa::MODE_JVP) return 0;
   if (b == tpfa::MODE_RESIDUAL && prec == TPFA_FP64) return 0;
   if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && form == tpfa::MODE_K3) return 0;
-  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && (pitch(g) * 8) % 128 != 0) {
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64 && !sliced && (pitch(g) * 8) % 128 != 0) {
     // rows off 128-byte lines: 128-wide tiles halve the partial lines at tile
     // edges (10-15% faster on 500- and 750-wide grids) where they waste no
     // more lanes than 64-wide ones
@@ -189,7 +191,10 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.y0 = (int32_t)y0;
   a.y1 = (int32_t)y1;
   a.kz_chunk = (int32_t)std::min<int64_t>(kz_chunk, g.nz);
-  a.ntx = (int32_t)((g.nx + ts.tx - 1) / ts.tx);
+  // sliced outputs: the tiles reach the end of each row's last 64-cell slice,
+  // so that every slice is written whole
+  const int64_t xw = (flags & TPFA_LAUNCH_SLICED) ? (g.nx + 63) / 64 * 64 : g.nx;
+  a.ntx = (int32_t)((xw + ts.tx - 1) / ts.tx);
   a.nty = (int32_t)((y1 - y0 + ts.ty - 1) / ts.ty);
   a.nzc = (int32_t)((g.nz + a.kz_chunk - 1) / a.kz_chunk);
   a.remap = (flags & TPFA_LAUNCH_XCD_REMAP) ? 1 : (flags & TPFA_LAUNCH_Y_FAST) ? 2 : 0;
@@ -197,6 +202,8 @@ void make_args(Args &a, const tpfa_grid_t &g, const tpfa_fluid_t &f, const tpfa_
   a.tile = tile;
   a.ldx = (int32_t)pitch(g);
   a.plane = pitch(g) * g.ny;
+  a.oplane = a.plane;
+  a.orun = a.plane * g.nz;
   a.nblocks = (int64_t)a.ntx * a.nty * a.nzc;
   // face area over centre distance, per direction
   a.ax = g.dy * g.dz / g.dx;
@@ -309,7 +316,9 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
                    const tpfa_launch_t *launch, int &tile, int &kz, int &flags, int64_t &y0,
                    int64_t &y1, bool fill = true) {
   const bool dflt = !launch || launch->tile < 0;
-  tile = dflt ? default_tile(g, mode, prec, form) : launch->tile;
+  tile = dflt ? default_tile(g, mode, prec, form,
+                             launch && (launch->flags & TPFA_LAUNCH_SLICED))
+              : launch->tile;
   const bool rows = launch && launch->y_end > 0;
   y0 = rows ? launch->y_begin : 0;
   y1 = rows ? launch->y_end : g.ny;
@@ -330,11 +339,33 @@ int rock_form(const tpfa_rock_t &rk) {
   return rk.tx ? tpfa::MODE_TRANS : rk.ky ? tpfa::MODE_K3 : 0;
 }
 
+// TPFA_LAUNCH_SLICED: r and J in one array of 64-cell slices, for the
+// Jacobian calls; r must be NULL (the residual is each slice's first run).
+int set_sliced(tpfa::Args &a, int flags, int base_mode, tpfa_precision_t prec) {
+  if (!(flags & TPFA_LAUNCH_SLICED)) return TPFA_OK;
+  if (base_mode != tpfa::MODE_JACOBIAN)
+    return fail(TPFA_ERR_UNSUPPORTED, "TPFA_LAUNCH_SLICED is for the Jacobian calls only");
+  if (a.r)
+    return fail(TPFA_ERR_PARAM,
+                "with TPFA_LAUNCH_SLICED the residual is part of J: pass r = NULL");
+  const int64_t es = prec == TPFA_FP64 ? 8 : 4;
+  const int64_t slices = ((int64_t)a.nx + 63) / 64;
+  if ((int64_t)a.ny * slices * 512 * es >= (int64_t(1) << 32))
+    return fail(TPFA_ERR_SHAPE, "one z plane of the sliced r + J array holds 2^32 bytes or more");
+  a.slices = (int32_t)slices;
+  a.oplane = (int64_t)a.ny * slices * 512;
+  a.orun = 64;
+  a.r = a.J;
+  a.J = static_cast<char *>(a.J) + 64 * es;
+  return TPFA_OK;
+}
+
 // Output store kind: the FP32 kernels write with ordinary stores unless every
-// output row starts on a 128-byte line (row pitch and output base pointers);
-// the FP64 kernels always write non-temporal (measured faster either way).
+// output row starts on a 128-byte line (row pitch and output base pointers;
+// sliced outputs: tiles of whole 64-cell slices); the FP64 kernels always
+// write non-temporal (measured faster either way).
 void set_store_kind(tpfa::Args &a, tpfa_precision_t prec) {
-  bool lines = ((int64_t)a.ldx * 4) % 128 == 0;
+  bool lines = a.slices ? tpfa::kTiles[a.tile].tx % 64 == 0 : ((int64_t)a.ldx * 4) % 128 == 0;
   for (const void *q : {a.r, a.J, a.gp, a.gm, a.jv})
     if (q && reinterpret_cast<uintptr_t>(q) % 128 != 0) lines = false;
   a.plain = prec == TPFA_FP32 && !lines ? 1 : 0;
@@ -364,6 +395,8 @@ int run(tpfa::Mode mode, const tpfa_grid_t *g, const tpfa_fluid_t *f, const tpfa
   b.cr = a.cr;
   b.vdtf = a.vdtf;
   b.crf = a.crf;
+  const int rc = set_sliced(b, flags, tpfa::base_mode(mode), prec);
+  if (rc) return rc;
   set_store_kind(b, prec);
   if (b.nblocks > (int64_t)std::numeric_limits<uint32_t>::max())
     return fail(TPFA_ERR_SHAPE, "too many workgroups; use a larger kz_chunk");
@@ -632,6 +665,7 @@ static void batch_free(tpfa_batch *b) {
 // cells only), where non-temporal ones measured 5% faster; FP64 always
 // non-temporal.
 static bool whole_line_rows(const tpfa::Args &a) {
+  if (a.slices) return a.tile != tpfa::kFitTile && tpfa::kTiles[a.tile].tx % 64 == 0;
   if (a.ldx % 32 != 0) return false;
   if (a.ldx == a.nx) return true;
   return a.padw && a.tile != tpfa::kFitTile &&
@@ -704,6 +738,9 @@ static int batch_model(const tpfa_model_t &md, int m, tpfa_precision_t prec,
   tpfa::make_args(a, md.grid, md.fluid, md.rock, md.state, tile, kz, flags, y0, y1);
   a.r = md.r;
   a.J = mode == TPFA_BATCH_JACOBIAN ? md.J : nullptr;
+  rc = set_sliced(a, flags,
+                  mode == TPFA_BATCH_JACOBIAN ? tpfa::MODE_JACOBIAN : tpfa::MODE_RESIDUAL, prec);
+  if (rc) return fail(rc, "model " + std::to_string(m) + ": " + g_last_error);
   return TPFA_OK;
 }
 

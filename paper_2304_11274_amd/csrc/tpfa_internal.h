@@ -78,7 +78,11 @@ struct Args {
   int32_t ldx;        // row pitch of every array, in cells (>= nx)
   int32_t dtx, dty;   // shape of the fitted tile (tile == kFitTile)
   int32_t padw;       // 1: tile lanes in the row padding (nx <= i < ldx) store zeros
+  int32_t slices;     // 0: outputs in planes of the arrays' row pitch; n > 0: r and J in
+                      // one sliced array of n slices of 64 cells per row
   int64_t plane;      // ldx * ny
+  int64_t oplane;     // elements per z plane of an output array (plane; sliced: ny * slices * 512)
+  int64_t orun;       // elements between the Jacobian's seven planes (ncell; sliced: 64)
   int64_t nblocks;    // ntx * nty * nzc
   // transmissibility geometric factors a_d and directional ratios (y, z)
   double ax, ay, az, ry, rz;

@@ -551,6 +551,9 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
     double acc = 0.0;
     S dacc = S(0);
     if constexpr (ACC) accumulation(a, c0, d0, xk, rk, acc, dacc);
+    // r and J: planes of the arrays, or the runs of a sliced array (oplane,
+    // orun); the other outputs always take planes
+    const size_t oko = (size_t)k * (size_t)a.oplane;
     // residual in the neighbour order, accumulated in FP64
     if (BASE != MODE_JVP || a.r) {
       double r = acc;
@@ -562,18 +565,18 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
 #pragma unroll
         for (int n = 0; n < 4; ++n) r = (n & 1) ? r + (double)fd[n] : r - (double)fd[n];
       }
-      if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
+      if (a.r) st_out<MODE>(at_w(static_cast<S *>(a.r), oko, cb), (S)r);
     }
     if constexpr (BASE == MODE_JACOBIAN) {
       S *J = static_cast<S *>(a.J);
-      const size_t nc = (size_t)nz * plane;
+      const size_t nc = (size_t)a.orun;
       S dg = dacc;
 #pragma unroll
       for (int n = 0; n < 6; ++n) dg = (n & 1) ? dg + f[n].dLo : dg - f[n].dUp;
-      st_out<MODE>(at_w(J, ko, cb), dg);
+      st_out<MODE>(at_w(J, oko, cb), dg);
 #pragma unroll
       for (int n = 0; n < 6; ++n)
-        st_out<MODE>(at_w(J, (size_t)(n + 1) * nc + ko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
+        st_out<MODE>(at_w(J, (size_t)(n + 1) * nc + oko, cb), (n & 1) ? f[n].dUp : -f[n].dLo);
     }
     if constexpr (BASE == MODE_JVP) {
       // (J v)_C = dacc v_C + sum over faces of dF_CN/dp_C v_C + dF_CN/dp_N v_N,
@@ -741,8 +744,11 @@ struct Tile {
     inside = active && i < nx && j < ny;
     own = inside && j < a.y1;
     // lanes in the row padding store zeros there where the caller allows it
-    // (whole-line output rows); their loads stay those of an absent cell
-    const bool pad_lane = a.padw && active && i >= nx && i < (int)ldx && j < ny && j < a.y1;
+    // (whole-line output rows), and so do the lanes of a row's last 64-cell
+    // slice beyond nx with sliced outputs; their loads stay those of an absent
+    // cell
+    const int padx = a.slices ? a.slices * 64 : a.padw ? (int)ldx : nx;
+    const bool pad_lane = active && i >= nx && i < padx && j < ny && j < a.y1;
     tnv = inside && i + 1 < nx && j + 1 < ny;
     txv = inside && i + 1 < nx;
     tyv = inside && j + 1 < ny;
@@ -751,7 +757,11 @@ struct Tile {
     ol = active ? (ty + 1) * Wv + tx + 1 : hw_() - 1;
     cb = col * (uint32_t)sizeof(S);
     cs = col;
-    sb = pad_lane ? ((uint32_t)j * ldx + (uint32_t)i) * (uint32_t)sizeof(S) : cb;
+    // sliced outputs: slice i / 64 of row j, 8 runs of 64 cells
+    sb = a.slices ? (((uint32_t)j * (uint32_t)a.slices + (uint32_t)(i >> 6)) * 512u +
+                     (uint32_t)(i & 63)) * (uint32_t)sizeof(S)
+         : pad_lane ? ((uint32_t)j * ldx + (uint32_t)i) * (uint32_t)sizeof(S)
+                    : cb;
     own = own || pad_lane;
     // halo ring: bottom row, top row, left column, right column
 #pragma unroll

@@ -152,6 +152,23 @@ def test_jacobian_and_vjp_validation(lib):
     assert lib.tpfa_jacobian(*args, DUMMY, DUMMY, None, None) == L.TPFA_ERR_SHAPE
 
 
+def test_sliced_validation(lib):
+    """TPFA_LAUNCH_SLICED: Jacobian calls only, r NULL, one z plane of the
+    sliced array below 2^32 bytes."""
+    g, f, rk, st = good()
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st), L.TPFA_FP64)
+    ln = L.Launch(-1, 0, L.TPFA_LAUNCH_SLICED, 0, 0)
+    assert lib.tpfa_jacobian(*args, DUMMY, DUMMY, C.byref(ln), None) == L.TPFA_ERR_PARAM
+    assert b"r = NULL" in lib.tpfa_last_error()
+    assert lib.tpfa_residual(*args, DUMMY, C.byref(ln), None) == L.TPFA_ERR_UNSUPPORTED
+    assert lib.tpfa_residual_vjp(*args, DUMMY, DUMMY, DUMMY, C.byref(ln),
+                                 None) == L.TPFA_ERR_UNSUPPORTED
+    # 2^16 cells per row (1024 slices) and 1024 rows in FP64: 2^32 bytes per plane
+    big = L.Grid(65536, 1024, 2, 10.0, 10.0, 2.0, 9.81)
+    assert lib.tpfa_jacobian(C.byref(big), C.byref(f), C.byref(rk), C.byref(st), L.TPFA_FP64,
+                             None, DUMMY, C.byref(ln), None) == L.TPFA_ERR_SHAPE
+
+
 def test_helpers_validation(lib):
     g, f, _, _ = good()
     assert lib.tpfa_hydrostatic(C.byref(g), C.byref(f), 1e7, None, None) == L.TPFA_ERR_NULL

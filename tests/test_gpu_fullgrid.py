@@ -1,7 +1,8 @@
 """Every cell of the benchmark's 512 x 512 x 256 grid against the oracle, in
-the launch the benchmark times (library defaults): the FP64 residual +
-Jacobian at 1e-12 and the FP32 precision form of the same geomodel (on its
-widened inputs) at 1e-5, in the per-cell relative metric of tests/helpers.py.
+the launch the benchmark times (library defaults, r and J in the sliced
+layout, which equals the plane layout bitwise): the FP64 residual + Jacobian
+at 1e-12 and the FP32 precision form of the same geomodel (on its widened
+inputs) at 1e-5, in the per-cell relative metric of tests/helpers.py.
 
 The oracle evaluates z slabs of 32 planes plus one halo plane on each side
 (the halo planes are inputs only: the slab's own planes see all six
@@ -28,6 +29,19 @@ def big(orc):
     geo = geomodel.big512(noise_seeds=(2,))
     pref = orc.hydrostatic(geo.grid, geo.fluid)
     return geo, pref
+
+
+def headline(gpu, geo, k, p, **kw):
+    """r, J of the sliced launch copied out to planes, checked bitwise against
+    the plane layout's."""
+    g = geo.grid
+    rp, Jp = gpu.jacobian(g, geo.fluid, k, p, seal=dev(geo.seal), ry=geo.ry, rz=geo.rz, **kw)
+    _, Js = gpu.jacobian(g, geo.fluid, k, p, seal=dev(geo.seal), ry=geo.ry, rz=geo.rz,
+                         sliced=True, **kw)
+    r, J = gpu.unslice(g, Js)
+    torch.cuda.synchronize()
+    assert torch.equal(r, rp) and torch.equal(J, Jp), "sliced and plane layouts differ"
+    return r, J
 
 
 def slabwise(orc, geo, k, p, r, J, tol, tau):
@@ -57,9 +71,7 @@ def test_every_cell_fp64(gpu, orc, big):
     geo, pref = big
     print("512x512x256 fp64, every cell", flush=True)
     p = pref[:, None, None] + geo.noise[0]
-    r, J = gpu.jacobian(geo.grid, geo.fluid, dev(geo.kx), dev(p), seal=dev(geo.seal),
-                        ry=geo.ry, rz=geo.rz)
-    torch.cuda.synchronize()
+    r, J = headline(gpu, geo, dev(geo.kx), dev(p))
     rep = slabwise(orc, geo, geo.kx, p, r, J, 1e-12, 1e-9 * float(np.abs(p).max()))
     print("fp64 every cell:", rep)
     assert rep["max_err"] <= 1e-12
@@ -69,9 +81,7 @@ def test_every_cell_fp32(gpu, orc, big):
     geo, pref = big
     print("512x512x256 fp32, every cell", flush=True)
     dp, k32 = geo.dp32(0), geo.kx32()
-    r, J = gpu.jacobian(geo.grid, geo.fluid, dev(k32), dev(dp), seal=dev(geo.seal),
-                        pref=dev(pref), ry=geo.ry, rz=geo.rz)
-    torch.cuda.synchronize()
+    r, J = headline(gpu, geo, dev(k32), dev(dp), pref=dev(pref))
     p_w = orc.widen_fp32(dp, pref)
     rep = slabwise(orc, geo, k32.astype(np.float64), p_w, r, J, 1e-5, 1e-4)
     print("fp32 every cell:", rep)

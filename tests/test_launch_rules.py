@@ -135,6 +135,14 @@ def test_pad_writes_flag_is_kept():
     assert api._launch(None, None, False) is None
 
 
+def test_sliced_flag_is_kept():
+    g = geomodel.Grid(500, 64, 32)
+    for op in ("jacobian", "jacobian_be"):
+        assert rl(g, op, F32, sliced=True)["sliced"]
+        assert rl(g, op, F64, tile=3, sliced=True)["sliced"]
+        assert not rl(g, op, F64)["sliced"]
+
+
 def test_pad_writes_need_whole_last_rows():
     """The binding's host check: with pad_writes every output buffer must hold
     the padding of its last row (views at a column offset into a buffer of the
