@@ -763,24 +763,30 @@ def main():
         log(f"pitched: {res}")
 
     # this box's bandwidth ceiling on the Jacobian kernels' access pattern: the
-    # library's streaming probe (read p, k, seal; write eight planes; coalesced,
-    # non-temporal), over the benchmark's cell count, FP64 and FP32
+    # library's streaming probe (read p, k, seal; write eight outputs in the
+    # output layout; coalesced, non-temporal), over the benchmark's cell count,
+    # FP64 and FP32; the headline layout's probe is the ceiling
     if "probe" in sections:
         out["copy_ceiling"] = {}
         for name, t_, bpc in (("fp64", torch.float64, BYTES_FP64_RJ),
                               ("fp32", torch.float32, BYTES_FP32_RJ)):
             pp_ = noise[0].to(t_)
             kk_ = kx64.to(t_)
-            oo_ = torch.empty((8,) + g.shape, dtype=t_, device=dev)
-            for _ in range(3):
-                tp.stream_probe(g, pp_, kk_, seal, out=oo_)
-            with Timer(torch) as tm:
-                for _ in range(20):
-                    tp.stream_probe(g, pp_, kk_, seal, out=oo_)
-            out["copy_ceiling"][name] = {"bytes_per_cell": bpc, "cells": N,
-                                         "ms": tm.ms / 20,
-                                         "GBps": bpc * N * 20 / (tm.ms / 1e3) / 1e9}
-            del pp_, kk_, oo_
+            for lo in layouts:
+                sl_ = lo == "sliced"
+                oo_ = (tp.empty_sliced(g, t_, dev) if sl_
+                       else torch.empty((8,) + g.shape, dtype=t_, device=dev))
+                for _ in range(3):
+                    tp.stream_probe(g, pp_, kk_, seal, out=oo_, sliced=sl_)
+                with Timer(torch) as tm:
+                    for _ in range(20):
+                        tp.stream_probe(g, pp_, kk_, seal, out=oo_, sliced=sl_)
+                key = name if lo == layouts[0] else f"{name}_{lo}"
+                out["copy_ceiling"][key] = {"bytes_per_cell": bpc, "cells": N,
+                                            "output_layout": lo, "ms": tm.ms / 20,
+                                            "GBps": bpc * N * 20 / (tm.ms / 1e3) / 1e9}
+                del oo_
+            del pp_, kk_
         out["copy_ceiling_GBps"] = out["copy_ceiling"]["fp64"]["GBps"]
         log(f"bandwidth probe: {out['copy_ceiling']}")
         # torch's device copy, for context

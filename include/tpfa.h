@@ -26,7 +26,9 @@
  *    (inputs and outputs, each plane of J and of the gradients) uses the same
  *    pitch; an array of P planes holds plane q at offset q * ldx * ny * nz.
  *    Cells with nx <= i < ldx are padding: never read as cells, and never
- *    written unless the launch sets TPFA_LAUNCH_PAD_WRITES.
+ *    written unless the launch sets TPFA_LAUNCH_PAD_WRITES. With
+ *    TPFA_LAUNCH_SLICED the Jacobian calls write r and J into one array of
+ *    64-cell row slices instead (layout at that flag).
  *  - Array pointers are DEVICE pointers (hipMalloc'ed or torch CUDA tensors)
  *    owned by the caller, unless stated otherwise. Structs are read on the host
  *    during the call and may be freed when it returns.
@@ -56,8 +58,9 @@ extern "C" {
 
 /* Library version: major * 10000 + minor * 100 + patch (tpfa_version() returns
    the built library's). The major number changes with the layout of the ABI
-   structs: version 2 added tpfa_grid_t.ldx (row-pitched arrays). */
-#define TPFA_VERSION 20000
+   structs: version 2 added tpfa_grid_t.ldx (row-pitched arrays); 2.1 added
+   TPFA_LAUNCH_SLICED and tpfa_stream_probe_sliced. */
+#define TPFA_VERSION 20100
 
 #define TPFA_OK 0
 #define TPFA_ERR_NULL (-1)        /* a required pointer is NULL */
@@ -308,6 +311,14 @@ int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double 
    TPFA_ERR_PARAM (precision), TPFA_ERR_NULL, TPFA_ERR_HIP. */
 int tpfa_stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
                       const void *k, const uint8_t *seal, void *out, void *stream);
+
+/* The same probe with the eight outputs in the layout of TPFA_LAUNCH_SLICED:
+   output q of cell (i, j, k) at element (((k ny + j) S + i / 64) 8 + q) 64 +
+   i % 64 of out (S = ceil(nx / 64), nz ny S 512 elements; lanes beyond nx are
+   not written). TPFA_ERR_SHAPE where one z plane of out holds 2^32 bytes or
+   more; the other errors as tpfa_stream_probe. */
+int tpfa_stream_probe_sliced(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                             const void *k, const uint8_t *seal, void *out, void *stream);
 
 /* ---- Batched ensemble: many independent grids in one persistent launch ---- */
 

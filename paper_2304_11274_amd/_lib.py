@@ -107,6 +107,7 @@ SIGNATURES = {
     "tpfa_version": (C.c_int, []),
     "tpfa_resolve_launch": (C.c_int, [P(Grid), C.c_int, C.c_int, P(Rock), P(Launch), P(Launch)]),
     "tpfa_stream_probe": (C.c_int, [P(Grid), C.c_int, vp, vp, vp, vp, vp]),
+    "tpfa_stream_probe_sliced": (C.c_int, [P(Grid), C.c_int, vp, vp, vp, vp, vp]),
     "tpfa_ensemble_run_noalloc": (C.c_int, [P(Model), C.c_int, C.c_int, C.c_int, vp]),
 }
 

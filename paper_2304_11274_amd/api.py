@@ -485,11 +485,12 @@ def offset_pressure(grid, p: torch.Tensor, pref: torch.Tensor, out=None) -> torc
 
 
 def stream_probe(grid, p: torch.Tensor, k: torch.Tensor, seal: torch.Tensor,
-                 out=None) -> torch.Tensor:
+                 out=None, sliced: bool = False) -> torch.Tensor:
     """Bandwidth probe with the Jacobian kernels' access pattern (tpfa_stream_probe):
     out[q] = p + (q + seal) * k for q = 0..7, from contiguous p, k (float64 or
     float32) and uint8 seal of the grid's shape (nz, ny, nx); returns out of
-    shape (8, nz, ny, nx)."""
+    shape (8, nz, ny, nx), or with ``sliced`` (tpfa_stream_probe_sliced) the
+    array of sliced_shape with output q in run q (lanes beyond nx untouched)."""
     shape = (int(grid.nz), int(grid.ny), int(grid.nx))
     for t, name in ((p, "p"), (k, "k"), (seal, "seal")):
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
@@ -500,14 +501,16 @@ def stream_probe(grid, p: torch.Tensor, k: torch.Tensor, seal: torch.Tensor,
         raise ValueError("p and k must both be float64 or both float32")
     if seal.dtype != torch.uint8:
         raise ValueError("seal must be uint8")
+    oshape = sliced_shape(grid) if sliced else (8,) + shape
     if out is None:
-        out = torch.empty((8,) + shape, dtype=p.dtype, device=p.device)
-    elif not (out.is_contiguous() and out.dtype == p.dtype and tuple(out.shape) == (8,) + shape):
-        raise ValueError("out must be contiguous, of p's dtype and of shape (8, nz, ny, nx)")
+        out = torch.empty(oshape, dtype=p.dtype, device=p.device)
+    elif not (out.is_contiguous() and out.dtype == p.dtype and tuple(out.shape) == oshape):
+        raise ValueError(f"out must be contiguous, of p's dtype and of shape {oshape}")
     prec = L.TPFA_FP64 if p.dtype == torch.float64 else L.TPFA_FP32
     lib = L.load()
-    L.check(lib.tpfa_stream_probe(C.byref(_grid(grid)), prec, _ptr(p), _ptr(k), _ptr(seal),
-                                  _ptr(out), _stream(p.device)), lib)
+    fn = lib.tpfa_stream_probe_sliced if sliced else lib.tpfa_stream_probe
+    L.check(fn(C.byref(_grid(grid)), prec, _ptr(p), _ptr(k), _ptr(seal), _ptr(out),
+               _stream(p.device)), lib)
     return out
 
 

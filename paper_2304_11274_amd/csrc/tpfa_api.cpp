@@ -614,16 +614,30 @@ int tpfa_offset_pressure(const tpfa_grid_t *grid, const double *p, const double 
   return ok();
 }
 
-int tpfa_stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
-                      const void *k, const uint8_t *seal, void *out, void *stream) {
+static int stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                        const void *k, const uint8_t *seal, void *out, bool sliced,
+                        void *stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   if (prec != TPFA_FP64 && prec != TPFA_FP32) return fail(TPFA_ERR_PARAM, "unknown precision");
   if (!p || !k || !seal || !out) return fail(TPFA_ERR_NULL, "p, k, seal and out are required");
-  const hipError_t e =
-      tpfa::launch_stream_probe(prec, *grid, p, k, seal, out, static_cast<hipStream_t>(stream));
+  const int64_t es = prec == TPFA_FP64 ? 8 : 4;
+  if (sliced && grid->ny * ((grid->nx + 63) / 64) * 512 * es >= (int64_t(1) << 32))
+    return fail(TPFA_ERR_SHAPE, "one z plane of the sliced array holds 2^32 bytes or more");
+  const hipError_t e = tpfa::launch_stream_probe(prec, *grid, p, k, seal, out, sliced,
+                                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "probe launch");
   return ok();
+}
+
+int tpfa_stream_probe(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                      const void *k, const uint8_t *seal, void *out, void *stream) {
+  return stream_probe(grid, prec, p, k, seal, out, false, stream);
+}
+
+int tpfa_stream_probe_sliced(const tpfa_grid_t *grid, tpfa_precision_t prec, const void *p,
+                             const void *k, const uint8_t *seal, void *out, void *stream) {
+  return stream_probe(grid, prec, p, k, seal, out, true, stream);
 }
 
 // ---------------------------------------------------------------------------

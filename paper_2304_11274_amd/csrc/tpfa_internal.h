@@ -146,7 +146,8 @@ hipError_t launch_hydrostatic(const tpfa_grid_t &g, const tpfa_fluid_t &f, doubl
 hipError_t launch_offset(const tpfa_grid_t &g, const double *p, const double *pref, float *dp,
                          hipStream_t stream);
 hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, const void *p,
-                               const void *k, const uint8_t *seal, void *out, hipStream_t stream);
+                               const void *k, const uint8_t *seal, void *out, bool sliced,
+                               hipStream_t stream);
 
 // Batched ensemble kernels (persistent and grouped schedules). The work list
 // is cut into one band per XCD; the persistent schedule keeps one claim

@@ -335,7 +335,9 @@ hipError_t launch_static_grouped(tpfa_precision_t prec, int mode, int tiles, voi
 // and marches it through a chunk of 32 planes; per plane each lane reads p, k
 // and the seal bytes of its cells and writes eight output planes,
 // out[q][c] = p[c] + (q + seal[c]) k[c] (so that no load is dead), with
-// non-temporal stores. Rows of odd pitch take one cell per access.
+// non-temporal stores. Rows of odd pitch take one cell per access. The eight
+// outputs go to eight planes, or to the runs of the sliced r + J layout
+// (`slices` > 0: slice i / 64 of row j holds eight runs of 64 cells).
 // ----------------------------------------------------------------------------
 constexpr int kProbeTx = 128, kProbeTy = 8, kProbeChunk = 32;
 
@@ -344,7 +346,7 @@ using vec2_t = S __attribute__((ext_vector_type(2)));
 
 template <class S, bool PAIR>
 __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
-    stream_probe_kernel(int nx, int ny, int nz, int ldx, int ntx, int nty,
+    stream_probe_kernel(int nx, int ny, int nz, int ldx, int ntx, int nty, int slices,
                         const S *__restrict__ p, const S *__restrict__ k,
                         const uint8_t *__restrict__ seal, S *__restrict__ out) {
   const uint32_t b = blockIdx.x, r1 = b / (uint32_t)ntx, r2 = r1 / (uint32_t)nty;
@@ -354,10 +356,15 @@ __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
   if (i >= nx || j >= ny) return;
   const bool two = i + 1 < nx;
   const int kb = (int)r2 * kProbeChunk, ke = min(kb + kProbeChunk, nz);
-  const size_t plane = (size_t)ldx * ny, nc = plane * nz;
+  const size_t plane = (size_t)ldx * ny;
+  // output: plane stride, run stride and the cell's offset in its plane
+  const size_t oplane = slices ? (size_t)ny * slices * 512 : plane;
+  const size_t nc = slices ? 64 : plane * nz;
   size_t c = (size_t)j * ldx + i + (size_t)kb * plane;
+  size_t o = (slices ? ((size_t)j * slices + (i >> 6)) * 512 + (i & 63) : (size_t)j * ldx + i) +
+             (size_t)kb * oplane;
 #pragma unroll 2
-  for (int kk = kb; kk < ke; ++kk, c += plane) {
+  for (int kk = kb; kk < ke; ++kk, c += plane, o += oplane) {
     if (PAIR && two) {
       const vec2_t<S> pc = *(const vec2_t<S> *)(p + c), kc = *(const vec2_t<S> *)(k + c);
       const uint32_t sc = *(const uint16_t *)(seal + c);
@@ -366,7 +373,7 @@ __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
         vec2_t<S> v;
         v.x = pc.x + S(q + (int)(sc & 255u)) * kc.x;
         v.y = pc.y + S(q + (int)(sc >> 8)) * kc.y;
-        __builtin_nontemporal_store(v, (gptr<vec2_t<S>>)(out + q * nc + c));
+        __builtin_nontemporal_store(v, (gptr<vec2_t<S>>)(out + q * nc + o));
       }
     } else {
 #pragma unroll
@@ -376,14 +383,16 @@ __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
         const int sc = seal[c + e];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          __builtin_nontemporal_store(pc + S(q + sc) * kc, (gptr<S>)(out + q * nc + c + e));
+          __builtin_nontemporal_store(pc + S(q + sc) * kc, (gptr<S>)(out + q * nc + o + e));
       }
     }
   }
 }
 
 hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, const void *p,
-                               const void *k, const uint8_t *seal, void *out, hipStream_t st) {
+                               const void *k, const uint8_t *seal, void *out, bool sliced,
+                               hipStream_t st) {
+  const int slices = sliced ? (int)((g.nx + 63) / 64) : 0;
   const int ntx = (int)((g.nx + kProbeTx - 1) / kProbeTx);
   const int nty = (int)((g.ny + kProbeTy - 1) / kProbeTy);
   const int64_t nzc = (g.nz + kProbeChunk - 1) / kProbeChunk;
@@ -401,20 +410,20 @@ hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, cons
     const double *pp = static_cast<const double *>(p), *kk = static_cast<const double *>(k);
     double *oo = static_cast<double *>(out);
     if (pair)
-      stream_probe_kernel<double, true><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
-                                                                  seal, oo);
+      stream_probe_kernel<double, true>
+          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
     else
-      stream_probe_kernel<double, false><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp,
-                                                                   kk, seal, oo);
+      stream_probe_kernel<double, false>
+          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
   } else {
     const float *pp = static_cast<const float *>(p), *kk = static_cast<const float *>(k);
     float *oo = static_cast<float *>(out);
     if (pair)
-      stream_probe_kernel<float, true><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
-                                                                 seal, oo);
+      stream_probe_kernel<float, true>
+          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
     else
-      stream_probe_kernel<float, false><<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, pp, kk,
-                                                                  seal, oo);
+      stream_probe_kernel<float, false>
+          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
   }
   return hipGetLastError();
 }

@@ -192,6 +192,16 @@ def test_stream_probe_validation(lib):
     g.nz = 0
     assert lib.tpfa_stream_probe(C.byref(g), L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY, None) == \
         L.TPFA_ERR_SHAPE
+    assert lib.tpfa_stream_probe_sliced(C.byref(g), L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY,
+                                        None) == L.TPFA_ERR_SHAPE
+    g.nz = 8
+    assert lib.tpfa_stream_probe_sliced(C.byref(g), 7, DUMMY, DUMMY, DUMMY, DUMMY,
+                                        None) == L.TPFA_ERR_PARAM
+    assert lib.tpfa_stream_probe_sliced(C.byref(g), L.TPFA_FP64, None, DUMMY, DUMMY, DUMMY,
+                                        None) == L.TPFA_ERR_NULL
+    big = L.Grid(65536, 1024, 2, 10.0, 10.0, 2.0, 9.81)  # 2^32 bytes per sliced FP64 plane
+    assert lib.tpfa_stream_probe_sliced(C.byref(big), L.TPFA_FP64, DUMMY, DUMMY, DUMMY, DUMMY,
+                                        None) == L.TPFA_ERR_SHAPE
     import torch
     import geomodel
     t = torch.zeros((2, 2, 2), dtype=torch.float64)

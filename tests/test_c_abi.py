@@ -56,7 +56,7 @@ def test_c_program_against_the_header(tmp_path):
                     os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", lib_dir,
                     "-l:libtpfa.so", f"-Wl,-rpath,{lib_dir}"], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
-    assert out[0] == "version 20000 rc 0 tile 64x8 kz 32 flags 0 rows 0 512", out
+    assert out[0] == "version 20100 rc 0 tile 64x8 kz 32 flags 0 rows 0 512", out
     assert out[1].startswith(f"mu0 {L.TPFA_ERR_PARAM} ") and "mu" in out[1], out
     assert out[2] == f"ldx {L.TPFA_ERR_SHAPE}", out
 
