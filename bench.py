@@ -19,7 +19,8 @@ The same run also times, as extra fields of the JSON line:
   residual - the residual-only kernels (FP64 and FP32)
   batched  - the 64-model uneven ensemble: one persistent kernel replayed from a
              HIP graph vs one launch per model
-  adjoint  - FP32 forward residual + vector-Jacobian product on 256 x 256 x 128
+  adjoint  - FP32 forward residual + vector-Jacobian product on 256 x 256 x 128 (two
+             calls), and the same results from one call (tpfa_residual_and_vjp)
   newton   - the backward-Euler residual of Eq. (2) and the matrix-free J v (the
              operator of a Newton-Krylov step) on 512 x 512 x 256, FP64 and FP32
   aniso    - residual + Jacobian with per-direction permeability arrays (kx, ky,
@@ -64,6 +65,7 @@ BYTES_FP32_RJ = 4 + 4 + 1 + 4 + 7 * 4      # dp, kx, seal -> r, J = 41
 BYTES_FP64_R = 8 + 8 + 1 + 8               # 25
 BYTES_FP32_R = 4 + 4 + 1 + 4               # 13
 BYTES_FP32_VJP = 4 + 4 + 1 + 4 + 4 + 4     # dp, kx, seal, w -> grad_p, grad_logk = 21
+BYTES_FP32_R_VJP = 4 + 4 + 1 + 4 + 3 * 4   # dp, kx, seal, w -> r, grad_p, grad_logk = 25
 BYTES_FP32_R10 = 4 + 4 + 4 + 4 + 4         # dp, kx, tne, tse -> r (no seals) = 20
 BYTES_FP32_R10T = 4 + 5 * 4 + 4            # dp, tx, ty, tz, tne, tse -> r = 28
 # backward-Euler forms: + phi_ref, p_prev (and v in, J v out for the product)
@@ -485,7 +487,8 @@ def main():
                      "cells": N, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
                      "sigma_lnk": 1.5, "ry": 1.0, "rz": 0.1, "seal_fraction": 0.01,
                      "output_layout": LAYOUTS[layouts[0]],
-                     "launch": "library default (64x8 tiles, 32 z-planes per workgroup)"}
+                     "launch": "library default: " + json.dumps(tp.resolve_launch(
+                         g, "jacobian", torch.float64, sliced=layouts[0] == "sliced"))}
 
     def rj_call(prec_kx, pfields, layout, extra):
         """One r + J application per step in an output layout (buffers allocated here)."""
@@ -924,6 +927,25 @@ def main():
                           "algorithmic_GBps": (BYTES_FP32_R + BYTES_FP32_VJP) * Na / (t / 1e3)
                           / 1e9}
         out["adjoint"]["hbm_frac"] = out["adjoint"]["algorithmic_GBps"] / HBM_PEAK_GBS
+
+        # the same results from tpfa_residual_and_vjp: r and the VJP in one pass
+        # (value and gradient of w.r; r, grad p and grad ln k bitwise as above)
+        def fused(s):
+            tp.residual_and_vjp(ga, geo_a.fluid, ka, dpa[s % 4], wa[s % 4], r_out=ra,
+                                gp_out=gpa, gm_out=gma, **kw)
+        for s in range(W):
+            fused(s)
+        with Timer(torch) as tm:
+            for s in range(KA):
+                fused(s)
+        t1 = tm.ms / KA
+        out["adjoint"]["one_pass"] = {
+            "call": "tpfa_residual_and_vjp", "ms_per_step": t1, "cells_per_s": Na / (t1 / 1e3),
+            "speedup_vs_two_calls": t / t1,
+            "algorithmic_GBps": BYTES_FP32_R_VJP * Na / (t1 / 1e3) / 1e9,
+            "bytes_per_cell": BYTES_FP32_R_VJP}
+        out["adjoint"]["one_pass"]["hbm_frac"] = (out["adjoint"]["one_pass"]["algorithmic_GBps"]
+                                                  / HBM_PEAK_GBS)
         log(f"adjoint: {out['adjoint']}")
         del ka, sa, dpa, wa, ra, gpa, gma
         torch.cuda.empty_cache()

@@ -216,6 +216,19 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                       tpfa_precision_t prec, const void *w, void *grad_p,
                       void *grad_logk, const tpfa_launch_t *launch, void *stream);
 
+/* The residual r[ncell] and the vector-Jacobian product of tpfa_residual_vjp
+   in one pass over the grid: the value and the gradient of w.r (the adjoint
+   of a linear functional of the residual, Sec. 3 residual and its
+   derivatives). r (required) is bitwise the r of tpfa_residual, grad_p and
+   grad_logk (either may be NULL, not both) bitwise those of
+   tpfa_residual_vjp. It reads p, k, seal and w once and evaluates each
+   face's flux and derivative terms once for both results. Permeability form
+   with ry, rz ratios only (TPFA_ERR_UNSUPPORTED otherwise). */
+int tpfa_residual_and_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                          const tpfa_rock_t *rock, const tpfa_state_t *state,
+                          tpfa_precision_t prec, const void *w, void *r, void *grad_p,
+                          void *grad_logk, const tpfa_launch_t *launch, void *stream);
+
 /* Accumulation term of the full backward-Euler residual, Eq. (2):
      V_K (phi(p_K) rho(p_K) - phi(pn_K) rho(pn_K)) / dt,  V_K = dx dy dz,
    with rho from Eq. (5) and the porosity linear in pressure (Sec. 3 states

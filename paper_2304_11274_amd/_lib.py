@@ -81,6 +81,8 @@ SIGNATURES = {
                                 vp]),
     "tpfa_residual_vjp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp, vp,
                                     P(Launch), vp]),
+    "tpfa_residual_and_vjp": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), C.c_int, vp, vp,
+                                        vp, vp, P(Launch), vp]),
     "tpfa_residual_be": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int,
                                    vp, P(Launch), vp]),
     "tpfa_jacobian_be": (C.c_int, [P(Grid), P(Fluid), P(Rock), P(State), P(Accum), C.c_int,

@@ -351,6 +351,36 @@ def residual_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
     return gp, gm
 
 
+def residual_and_vjp(grid, fluid, kx, p, w, *, seal=None, pref=None, ry=1.0, rz=1.0,
+                     want_p=True, want_logk=True, r_out=None, gp_out=None, gm_out=None,
+                     tile=None, kz_chunk=None, xcd_remap=False, rows=None, pad_writes=False):
+    """(r, grad_p, grad_logk) in one pass (tpfa_residual_and_vjp): the value and
+    gradient of w.r. r equals residual(), the gradients residual_vjp(), bit
+    for bit; permeability form with ratios only."""
+    n, prec, dt, dev, lay = _inputs(grid, kx, p, seal, pref)
+    _need(w, "w", dt, n, dev, lay)
+    if not (want_p or want_logk):
+        raise ValueError("residual_and_vjp needs a gradient; use residual() for r alone")
+    r = r_out if r_out is not None else _empty(p, lay)
+    _need(r, "r_out", dt, n, dev, lay)
+    gp = gm = None
+    if want_p:
+        gp = gp_out if gp_out is not None else _empty(p, lay)
+        _need(gp, "gp_out", dt, n, dev, lay)
+    if want_logk:
+        gm = gm_out if gm_out is not None else _empty(p, lay)
+        _need(gm, "gm_out", dt, n, dev, lay)
+    _pad_ok(pad_writes, lay, r_out=r, gp_out=gp, gm_out=gm)
+    lib = L.load()
+    L.check(lib.tpfa_residual_and_vjp(C.byref(_grid(grid, lay.pitch)), C.byref(_fluid(fluid)),
+                                      C.byref(_rock(kx, seal, ry, rz)),
+                                      C.byref(L.State(_ptr(p), _ptr(pref))), prec, _ptr(w),
+                                      _ptr(r), _ptr(gp), _ptr(gm),
+                                      _launch_ref(tile, kz_chunk, xcd_remap, rows, pad_writes),
+                                      _stream(dev)), lib)
+    return r, gp, gm
+
+
 def _accum(accum, dt_, n, dev, lay):
     """``accum`` = dict(phi=..., p_prev=..., dt=..., cr=...) -> L.Accum."""
     if accum is None:

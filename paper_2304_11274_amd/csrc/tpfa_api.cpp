@@ -146,13 +146,14 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
 }
 
 // z planes per workgroup: 32 for the residual-only modes and the FP64
-// Jacobians (0.7% faster than 16 there) and for the FP32 Jacobian of the ratio
-// form (1% faster), 16 for the other products (the FP32 backward-Euler and
+// Jacobians (0.7% faster than 16 there; 64 with sliced outputs, 0.4% faster
+// than 32 on 512x512x256) and for the FP32 Jacobian of the ratio form (1%
+// faster), 16 for the other products (the FP32 backward-Euler and
 // per-direction Jacobians ran 0.6-1.3% slower with 32).
-int default_kz(tpfa::Mode mode, tpfa_precision_t prec, int form) {
+int default_kz(tpfa::Mode mode, tpfa_precision_t prec, int form, bool sliced) {
   const int b = tpfa::base_mode(mode);
   if (b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10) return 32;
-  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64) return 32;
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64) return sliced ? 64 : 32;
   return mode == tpfa::MODE_JACOBIAN && form == 0 ? 32 : 16;
 }
 
@@ -322,15 +323,26 @@ int resolve_launch(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec,
   const bool rows = launch && launch->y_end > 0;
   y0 = rows ? launch->y_begin : 0;
   y1 = rows ? launch->y_end : g.ny;
+  const bool sliced = launch && (launch->flags & TPFA_LAUNCH_SLICED);
   if (launch && launch->kz_chunk > 0)
     kz = launch->kz_chunk;
   else
-    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form), prec, mode | form)
-              : default_kz(mode, prec, form);
+    kz = fill ? fill_kz(g, y1 - y0, tile, default_kz(mode, prec, form, sliced), prec, mode | form)
+              : default_kz(mode, prec, form, sliced);
   // the FP32 kernels hold per-plane constants of their chunk in LDS
   if (prec == TPFA_FP32) kz = std::min(kz, tpfa::kMaxChunk32);
   flags = launch ? launch->flags : 0;
-  if (dflt) flags |= default_flags(mode, prec, form, g.nx * (y1 - y0) * g.nz);
+  if (dflt) {
+    const int64_t cells = g.nx * (y1 - y0) * g.nz;
+    flags |= default_flags(mode, prec, form, cells);
+    // the FP64 Jacobian with sliced outputs on large grids: the y-fast order
+    // where a tile's x neighbours land on its XCD (tile rows a multiple of 8;
+    // 512x512x256 with 64-plane chunks: 1.006 -> 1.001 ms)
+    const int64_t nty = (y1 - y0 + tpfa::kTiles[tile].ty - 1) / tpfa::kTiles[tile].ty;
+    if (sliced && prec == TPFA_FP64 && tpfa::base_mode(mode) == tpfa::MODE_JACOBIAN &&
+        form == 0 && !(flags & TPFA_LAUNCH_XCD_REMAP) && nty % 8 == 0)
+      flags |= TPFA_LAUNCH_Y_FAST;
+  }
   return TPFA_OK;
 }
 
@@ -463,6 +475,33 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
     a.gp = grad_p;
     a.gm = grad_logk;
     return run(tpfa::MODE_VJP, grid, fluid, rock, state, prec, launch, a, stream);
+  } catch (const std::exception &e) {
+    return fail(TPFA_ERR_HIP, e.what());
+  } catch (...) {
+    return fail(TPFA_ERR_HIP, "unknown exception");
+  }
+}
+
+int tpfa_residual_and_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
+                          const tpfa_rock_t *rock, const tpfa_state_t *state,
+                          tpfa_precision_t prec, const void *w, void *r, void *grad_p,
+                          void *grad_logk, const tpfa_launch_t *launch, void *stream) {
+  try {
+    int rc = check_common(grid, fluid, rock, state, prec, launch);
+    if (rc) return rc;
+    if (!w) return fail(TPFA_ERR_NULL, "w is NULL");
+    if (!r) return fail(TPFA_ERR_NULL, "r is NULL (without it, call tpfa_residual_vjp)");
+    if (!grad_p && !grad_logk) return fail(TPFA_ERR_NULL, "grad_p and grad_logk are both NULL");
+    if (rock->tx || rock->ky)
+      return fail(TPFA_ERR_UNSUPPORTED,
+                  "the residual with the VJP needs the permeability form with ry, rz ratios");
+    tpfa::Args a{};
+    a.w = w;
+    a.r = r;
+    a.gp = grad_p;
+    a.gm = grad_logk;
+    return run(static_cast<tpfa::Mode>(tpfa::MODE_VJP | tpfa::MODE_WITH_R), grid, fluid, rock,
+               state, prec, launch, a, stream);
   } catch (const std::exception &e) {
     return fail(TPFA_ERR_HIP, e.what());
   } catch (...) {

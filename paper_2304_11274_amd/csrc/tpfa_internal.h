@@ -31,7 +31,11 @@ constexpr int MODE_PLAIN = 16;
 // Flag added to a mode: per-direction permeability arrays (kx, ky, kz), each
 // face taking the harmonic average of its own direction's k (no ratios).
 constexpr int MODE_K3 = 32;
+// Flag added to MODE_VJP (permeability form with ratios): the kernel also
+// writes the residual, the value and gradient of w.r in one pass.
+constexpr int MODE_WITH_R = 64;
 constexpr int mode_kind(int m) { return m & 7; }
+constexpr bool has_with_r(int m) { return (m & MODE_WITH_R) != 0; }
 constexpr bool has_trans(int m) { return (m & MODE_TRANS) != 0; }
 constexpr bool has_plain_stores(int m) { return (m & MODE_PLAIN) != 0; }
 constexpr bool has_k3(int m) { return (m & MODE_K3) != 0; }

@@ -435,7 +435,7 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
                         hipStream_t st) {
   if (a.nblocks <= 0) return hipSuccess;
   const int kind = mode_kind(mode);
-  const int form = mode & (MODE_TRANS | MODE_K3);
+  const int form = mode & (MODE_TRANS | MODE_K3 | MODE_WITH_R);
   if (prec == TPFA_FP64) return launch_march_f64(kind, form, tile, a, st);
   return a.plain ? launch_march_f32_plain(kind, form, tile, a, st)
                  : launch_march_f32(kind, form, tile, a, st);
@@ -445,15 +445,15 @@ hipError_t launch_march(tpfa_precision_t prec, Mode mode, int tile, const Args &
 // the first use of each kernel (cached: the library runs on one device type).
 bool march_residency(tpfa_precision_t prec, int mode, int tile, int &per_cu, int &cus) {
   static std::mutex mu;
-  static int cache[2][3][8][kNumTiles];  // 0 unknown, -1 no answer, else workgroups per CU
+  static int cache[2][4][8][kNumTiles];  // 0 unknown, -1 no answer, else workgroups per CU
   static int cu_count = 0;
   const int kind = mode_kind(mode);
-  const int form = has_trans(mode) ? 1 : has_k3(mode) ? 2 : 0;
+  const int form = has_trans(mode) ? 1 : has_k3(mode) ? 2 : has_with_r(mode) ? 3 : 0;
   if (tile < 0 || tile >= kNumTiles) return false;
   std::lock_guard<std::mutex> lock(mu);
   int &slot = cache[prec == TPFA_FP64 ? 0 : 1][form][kind][tile];
   if (slot == 0) {
-    const int fl = mode & (MODE_TRANS | MODE_K3);
+    const int fl = mode & (MODE_TRANS | MODE_K3 | MODE_WITH_R);
     const void *fn = prec == TPFA_FP64 ? march_kernel_f64(kind, fl, tile)
                                        : march_kernel_f32(kind, fl, tile);
     int dev = 0, n = 0, c = 0;

@@ -280,17 +280,29 @@ __device__ __forceinline__ Face<S> face_z(const Args &a, S kLo, S kUp, bool open
 // factor A2 k_C, which is applied once per cell and axis: gp and gm receive
 // the terms divided by it. C_LO: C is the face's lower cell (its +x / +y face),
 // so a tie D = 0 makes C upwind; otherwise N is upwind at a tie.
-template <bool C_LO>
-__device__ __forceinline__ void vjp_face_own(float kC, float kN, bool open, float D, float lamC,
-                                             float lamN, float dw, float cf, float &gp,
-                                             float &gm) {
+// WITH_F: also the face's flux F_Lo,Up (outflow of its lower cell) with the
+// operands and operation order of the two-sided form (face_h), so that a
+// residual summed from it is bitwise the residual kernels'.
+template <bool C_LO, bool WITH_F = false>
+__device__ __forceinline__ void vjp_face_own(float kC, float kN, bool open, float pC, float pN,
+                                             float lamC, float lamN, float dw, float cf,
+                                             float &gp, float &gm, float A2 = 0.0f,
+                                             float *F = nullptr) {
+  const float D = pC - pN;
   const float ks = fmaxf(kC + kN, 1.17549435e-38f);
-  const float qN = kN * __builtin_amdgcn_rcpf(ks);
+  const float inv = __builtin_amdgcn_rcpf(ks);
+  const float qN = kN * inv;
   const bool upC = C_LO ? D >= 0.0f : D > 0.0f;
-  const float X0 = (qN * (upC ? lamC : lamN)) * dw;
+  const float lu = upC ? lamC : lamN;
+  const float X0 = (qN * lu) * dw;
   const float X = open ? X0 : 0.0f;
   gp = fmaf(X, upC ? fmaf(cf, D, 1.0f) : 1.0f, gp);
   gm = fmaf(X * D, qN, gm);
+  if constexpr (WITH_F) {
+    // T = (A2 k_Lo) (k_Up / (k_Lo + k_Up)), dPhi = p_Lo - p_Up
+    const float T = C_LO ? (A2 * kC) * qN : (A2 * kN) * (kC * inv);
+    *F = ((open ? T : 0.0f) * lu) * (C_LO ? D : pN - pC);
+  }
 }
 
 // Global-address-space views of the argument pointers: the ensemble kernel
@@ -524,6 +536,14 @@ __device__ __forceinline__ void emit(const Args &a, int k, size_t plane, int nz,
       }
     }
     if (a.gp) st_out<MODE>(at_w(static_cast<S *>(a.gp), ko, cb), (S)gp);
+    if constexpr (has_with_r(MODE)) {
+      // the residual in the residual kernels' order and precision (the faces'
+      // F are theirs, bit for bit)
+      double r = 0.0;
+#pragma unroll
+      for (int n = 0; n < 6; ++n) r = (n & 1) ? r + (double)f[n].F : r - (double)f[n].F;
+      st_out<MODE>(at_w(static_cast<S *>(a.r), ko, cb), (S)r);
+    }
     if constexpr (has_k3(MODE)) {
       // d(w.r)/d ln kx, ln ky, ln kz of the own cell, three planes [x, y, z]
       if (a.gm) {
@@ -978,21 +998,22 @@ struct Tile {
     const int sl[4] = {ol - 1, ol + 1, ol - Wv, ol + Wv};
     if constexpr (vjp_own<S, MODE>()) {
       const float cf = a.cff;
+      constexpr bool WR = has_with_r(MODE);
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
         const int axis = n >> 1;
         const int q = b + sl[n];
-        const float D = c0.p - s_p[q];
         const float dw = c0.w - s_w[q];
         const uint32_t bit = 1u << axis;
+        const float A2 = axis == 0 ? A2x : A2y;
         // the face's seal bit is its lower cell's
         const bool open = (((n & 1) ? c0.s : (uint32_t)s_s[q]) & bit) == 0u;
         if (n & 1)
-          vjp_face_own<true>(c0.k, s_k[q], open, D, d0.lam, s_l[q], dw, cf, vo[axis],
-                             vo[2 + axis]);
+          vjp_face_own<true, WR>(c0.k, s_k[q], open, c0.p, s_p[q], d0.lam, s_l[q], dw, cf,
+                                 vo[axis], vo[2 + axis], A2, &f[n].F);
         else
-          vjp_face_own<false>(c0.k, s_k[q], open, D, d0.lam, s_l[q], dw, cf, vo[axis],
-                              vo[2 + axis]);
+          vjp_face_own<false, WR>(c0.k, s_k[q], open, c0.p, s_p[q], d0.lam, s_l[q], dw, cf,
+                                  vo[axis], vo[2 + axis], A2, &f[n].F);
       }
     } else {
 #pragma unroll

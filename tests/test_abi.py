@@ -169,6 +169,23 @@ def test_sliced_validation(lib):
                              None, DUMMY, C.byref(ln), None) == L.TPFA_ERR_SHAPE
 
 
+def test_residual_and_vjp_validation(lib):
+    g, f, rk, st = good()
+    args = (C.byref(g), C.byref(f), C.byref(rk), C.byref(st), L.TPFA_FP64)
+    fn = lib.tpfa_residual_and_vjp
+    assert fn(*args, None, DUMMY, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL  # w
+    assert fn(*args, DUMMY, None, DUMMY, DUMMY, None, None) == L.TPFA_ERR_NULL  # r
+    assert fn(*args, DUMMY, DUMMY, None, None, None, None) == L.TPFA_ERR_NULL  # both grads
+    k3 = L.Rock(DUMMY.value, DUMMY.value, DUMMY.value, 1.0, 1.0, None)
+    assert fn(C.byref(g), C.byref(f), C.byref(k3), C.byref(st), L.TPFA_FP64, DUMMY, DUMMY,
+              DUMMY, DUMMY, None, None) == L.TPFA_ERR_UNSUPPORTED
+    tr = L.Rock(None, None, None, 1.0, 1.0, None, DUMMY.value, DUMMY.value, DUMMY.value)
+    assert fn(C.byref(g), C.byref(f), C.byref(tr), C.byref(st), L.TPFA_FP64, DUMMY, DUMMY,
+              DUMMY, DUMMY, None, None) == L.TPFA_ERR_UNSUPPORTED
+    ln = L.Launch(-1, 0, L.TPFA_LAUNCH_SLICED, 0, 0)
+    assert fn(*args, DUMMY, DUMMY, DUMMY, DUMMY, C.byref(ln), None) == L.TPFA_ERR_UNSUPPORTED
+
+
 def test_helpers_validation(lib):
     g, f, _, _ = good()
     assert lib.tpfa_hydrostatic(C.byref(g), C.byref(f), 1e7, None, None) == L.TPFA_ERR_NULL
