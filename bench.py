@@ -731,9 +731,11 @@ def main():
 
         res = {"workload": f"{nxp}x{nyp}x{g.nz} (rows of 4000 / 2000 bytes, off 128-byte "
                            f"lines), residual + Jacobian, contiguous vs row pitch {ldp} "
-                           f"(and row pitch {ldp} with the outputs' padding written)"}
+                           f"(and row pitch {ldp} with the outputs' padding written), and "
+                           f"contiguous inputs with the sliced r + J output"}
         for prec in ("fp64", "fp32"):
-            for ld, pw in ((nxp, False), (ldp, False), (ldp, True)):
+            for ld, pw, sl_ in ((nxp, False, False), (ldp, False, False), (ldp, True, False),
+                                (nxp, False, True)):
                 sp = layout(seal, ld)
                 if prec == "fp64":
                     kp = layout(kx64, ld)
@@ -747,15 +749,20 @@ def main():
                     kw = dict(seal=sp, pref=pref, ry=geo.ry, rz=geo.rz)
                     bpc = BYTES_FP32_RJ
                 kw["pad_writes"] = pw
-                r_, J_ = tp.jacobian(gp_, fl, kp, pp[0], **kw)
-                kw.update(r_out=r_, J_out=J_)
+                if sl_:
+                    r_, J_ = tp.jacobian(gp_, fl, kp, pp[0], sliced=True, **kw)
+                    kw.update(J_out=J_, sliced=True)
+                else:
+                    r_, J_ = tp.jacobian(gp_, fl, kp, pp[0], **kw)
+                    kw.update(r_out=r_, J_out=J_)
                 for s_ in range(W):
                     tp.jacobian(gp_, fl, kp, pp[s_ % 2], **kw)
                 with Timer(torch) as tm:
                     for s_ in range(KA):
                         tp.jacobian(gp_, fl, kp, pp[s_ % 2], **kw)
                 ms = tm.ms / KA
-                res.setdefault(prec, {})["pitch_%d%s" % (ld, "_pad_writes" if pw else "")] = {
+                key = "pitch_%d%s" % (ld, "_pad_writes" if pw else "_sliced" if sl_ else "")
+                res.setdefault(prec, {})[key] = {
                     "ms_per_step": ms, "cells_per_s": cells / (ms / 1e3),
                     "algorithmic_GBps": bpc * cells / (ms / 1e3) / 1e9}
                 del kp, sp, pp, r_, J_, kw
