@@ -203,6 +203,11 @@ def test_fullsize_adjoint(gpu, orc):
                       rz=geo.rz, seal=geo.seal)
     print("adjoint vjp:", rep)
     assert rep["max_err"] <= TOL32
+    # the same workload in one pass (tpfa_residual_and_vjp, the bench's one_pass leg):
+    # bitwise the two calls' results, so the comparisons above cover it
+    r1, gp1, gm1 = gpu.residual_and_vjp(geo.grid, geo.fluid, dev(k32), dev(dp), dev(w32), **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r) and torch.equal(gp1, gp) and torch.equal(gm1, gm)
 
 
 def test_fullsize_ensemble(gpu, orc):
