@@ -772,7 +772,7 @@ def main():
         out["pitched"] = res
         log(f"pitched: {res}")
 
-    # this box's bandwidth ceiling on the Jacobian kernels' access pattern: the
+    # this device's bandwidth ceiling on the Jacobian kernels' access pattern: the
     # library's streaming probe (read p, k, seal; write eight outputs in the
     # output layout; coalesced, non-temporal), over the benchmark's cell count,
     # FP64 and FP32; the headline layout's probe is the ceiling
@@ -1023,7 +1023,7 @@ def main():
 
     rf = out.get("roofline")
     if rf is not None:
-        # the same kernel against this box's own streaming-copy rate, and the
+        # the same kernel against this device's own streaming-copy rate, and the
         # counter-measured HBM bytes per launch as a rate
         if out.get("copy_ceiling_GBps"):
             rf["frac_of_copy_ceiling"] = rf["achieved"] / out["copy_ceiling_GBps"]
