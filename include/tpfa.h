@@ -406,8 +406,8 @@ void tpfa_batch_destroy(tpfa_batch_t *batch);
    capture, tight serving loops, harnesses that forbid hipMalloc): the
    ensemble of tpfa_batch_create + tpfa_batch_run in one call that allocates
    nothing. The model table and each model's first work item are written into
-   a fixed-size device array of the library (at most 256 models, 256 * 416 +
-   257 * 8 bytes, about 108 KB; each GPU the library runs on holds its own
+   a fixed-size device array of the library (at most 256 models, 256 * 448 +
+   257 * 8 bytes, about 114 KB; each GPU the library runs on holds its own
    copy until the process ends) by small upload launches on `stream`, then
    one grouped launch (one workgroup per work item, as
    TPFA_SCHEDULE_GROUPED) runs every model: the kernels and the results are
