@@ -9,7 +9,10 @@ forms and the backward-Euler J and J v against the oracle, and random uneven
 ensembles (either schedule, graph or direct launch) against the members'
 single-grid launches, bitwise. The row-range launch is repeated with the
 outputs' padding writable (pad_writes): equal owned rows, zeros in the padding
-under the tile's lanes, everything else untouched."""
+under the tile's lanes, everything else untouched; and with r and J in the
+sliced layout: equal owned rows, zeros in the owned rows' lanes beyond nx,
+everything else untouched. The one-pass residual + VJP equals the residual and
+VJP calls bitwise under the same random launches."""
 import numpy as np
 import pytest
 import torch
@@ -93,6 +96,18 @@ def test_random_launches_against_oracle(gpu, orc, c):
     assert bool((rp[:, y0:y1, g.nx:cov] == 0).all()) and bool((Jp[..., y0:y1, g.nx:cov] == 0).all())
     assert torch.isnan(rp[:, y0:y1, cov:]).all() and torch.isnan(Jp[..., y0:y1, cov:]).all()
     assert torch.isnan(rp[:, :y0]).all() and torch.isnan(rp[:, y1:]).all()
+    # the same row-range launch with r and J in the sliced layout: the owned
+    # rows' values bitwise, their lanes beyond nx zero, other rows untouched
+    nz_, ny_, S = gpu.sliced_shape(g)[:3]
+    Js = torch.full(gpu.sliced_shape(g), float("nan"), dtype=r.dtype, device="cuda")
+    gpu.jacobian(g, geo.fluid, kp, pp, seal=sp, ry=geo.ry, rz=geo.rz, rows=(y0, y1), J_out=Js,
+                 sliced=True, **launch, **kw)
+    torch.cuda.synchronize()
+    flat = Js.permute(3, 0, 1, 2, 4).reshape(8, nz_, ny_, S * 64)
+    assert torch.equal(flat[0, :, y0:y1, :g.nx], r[:, y0:y1])
+    assert torch.equal(flat[1:, :, y0:y1, :g.nx], J[:, :, y0:y1])
+    assert bool((flat[:, :, y0:y1, g.nx:] == 0).all())
+    assert torch.isnan(flat[:, :, :y0]).all() and torch.isnan(flat[:, :, y1:]).all()
     rep = compare_full(orc, g, geo.fluid, kwide, pw, r.double().cpu().numpy(),
                        J.double().cpu().numpy(), tol=tol, tau=tau, ry=geo.ry, rz=geo.rz,
                        seal=geo.seal)
@@ -126,8 +141,13 @@ def test_random_vjp_and_10_flux_against_oracle(gpu, orc, c, op):
     args = (g, geo.fluid, pad(k, ldx), pad(pin, ldx))
     kw.update(seal=pad(geo.seal, ldx), ry=geo.ry, rz=geo.rz, **launch)
     if op == "vjp":
-        gp, gm = gpu.residual_vjp(*args, pad(wq, ldx), **kw)
+        wd = pad(wq, ldx)
+        gp, gm = gpu.residual_vjp(*args, wd, **kw)
+        # one pass: bitwise the residual and VJP calls
+        r1, gp1, gm1 = gpu.residual_and_vjp(*args, wd, **kw)
+        r0 = gpu.residual(*args, **kw)
         torch.cuda.synchronize()
+        assert torch.equal(r1, r0) and torch.equal(gp1, gp) and torch.equal(gm1, gm)
         rep = compare_vjp(orc, g, geo.fluid, kwide, pw, np.asarray(wq, np.float64),
                           gp.double().cpu().numpy(), gm.double().cpu().numpy(), tol=tol, tau=tau,
                           ry=geo.ry, rz=geo.rz, seal=geo.seal)
