@@ -216,14 +216,15 @@ int tpfa_residual_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                       tpfa_precision_t prec, const void *w, void *grad_p,
                       void *grad_logk, const tpfa_launch_t *launch, void *stream);
 
-/* The residual r[ncell] and the vector-Jacobian product of tpfa_residual_vjp
-   in one pass over the grid: the value and the gradient of w.r (the adjoint
-   of a linear functional of the residual, Sec. 3 residual and its
-   derivatives). r (required) is bitwise the r of tpfa_residual, grad_p and
-   grad_logk (either may be NULL, not both) bitwise those of
-   tpfa_residual_vjp. It reads p, k, seal and w once and evaluates each
-   face's flux and derivative terms once for both results. Permeability form
-   with ry, rz ratios only (TPFA_ERR_UNSUPPORTED otherwise). */
+/* The residual r[ncell] (Algorithm 1, Eqs. 3-5) and the vector-Jacobian
+   product of tpfa_residual_vjp in one pass over the grid: the value and the
+   gradient of w.r, as an adjoint method needs them for a linear functional of
+   the residual. r (required) is bitwise the r of tpfa_residual; grad_p and
+   grad_logk (either may be NULL, not both) are bitwise those of
+   tpfa_residual_vjp. One kernel reads p, k, seal and w once, and each
+   face's flux serves both results (the two calls read the inputs twice and
+   form each face's flux in both kernels). Permeability form with ry, rz
+   ratios only (TPFA_ERR_UNSUPPORTED otherwise). */
 int tpfa_residual_and_vjp(const tpfa_grid_t *grid, const tpfa_fluid_t *fluid,
                           const tpfa_rock_t *rock, const tpfa_state_t *state,
                           tpfa_precision_t prec, const void *w, void *r, void *grad_p,
