@@ -1222,7 +1222,26 @@ __device__ __forceinline__ void march_tile(const Args &a, int bx, int by, int kb
   if (kb + 1 < t.nz) t.load(c1, kb + 1);
   d0 = props(c0.p, t.rk(kb), a);
   z0 = t.first_zface(c0, d0);
-  if constexpr (T::SHARE) {
+  if constexpr (T::SHARE && sizeof(S) == 4) {
+    // FP32 residual modes: two planes per iteration with the register roles
+    // swapped in the second, so that the halo cells, densities and z faces
+    // need no copies between planes and the own column's three planes rotate
+    // once per two planes (45 -> 55 VGPRs, still 8 waves per SIMD; the FP64
+    // kernels would lose a wave per SIMD)
+    Pending<S> pd{};
+    int k = kb;
+    for (; k + 1 < t.ke; k += 2) {
+      t.step_share(k, c0, d0, c1, d1, c2, h0, h1, h2, z0, z1, pd);
+      t.step_share(k + 1, c1, d1, c2, d0, c0, h1, h0, h2, z1, z0, pd);
+      const Cell<S> c = c0;
+      c0 = c2;
+      c1 = c;
+    }
+    if (k < t.ke) t.step_share(k, c0, d0, c1, d1, c2, h0, h1, h2, z0, z1, pd);
+    // the last plane's upper-cell fluxes
+    __syncthreads();
+    t.finish(t.ke - 1, ((t.ke - 1 - kb) & 1) * T::HW, pd);
+  } else if constexpr (T::SHARE) {
     Pending<S> pd{};
     for (int k = kb; k < t.ke; ++k) {
       t.step_share(k, c0, d0, c1, d1, c2, h0, h1, h2, z0, z1, pd);
