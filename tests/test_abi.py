@@ -35,6 +35,24 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(L.SIGNATURES), "binding signatures out of sync with the header"
 
 
+def test_constants_match_the_header():
+    """Every #define and enumerator value of include/tpfa.h that the binding
+    mirrors equals the binding's constant."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    found = {}
+    for name, val in re.findall(r"#define\s+(TPFA_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text):
+        found[name] = int(val)
+    for name, val in re.findall(r"\b(TPFA_[A-Z0-9_]+)\s*=\s*(-?\d+)", text):
+        found[name] = int(val)
+    mirrored = {n: getattr(L, n) for n in dir(L) if n.startswith("TPFA_") and n in found}
+    assert len(mirrored) >= 25, sorted(mirrored)
+    for n, v in mirrored.items():
+        assert found[n] == v, (n, found[n], v)
+    missing = sorted(n for n in found if n.startswith(("TPFA_LAUNCH_", "TPFA_ERR_", "TPFA_OP_"))
+                     and not hasattr(L, n))
+    assert not missing, missing
+
+
 def test_introspection(lib):
     assert lib.tpfa_version() // 10000 == L.ABI_MAJOR
     # the header's version is the one the library was built with
