@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <limits>
 #include <mutex>
+#include <type_traits>
 
 #include "tpfa_tile.h"
 
@@ -330,31 +331,33 @@ hipError_t launch_static_grouped(tpfa_precision_t prec, int mode, int tiles, voi
 // arithmetic and without their halo, in the access pattern that measured
 // fastest for it on MI355X among tile marches (64 x 8 and 128 x 8 column
 // blocks, one or two cells per lane) and grid-stride loops (one or two cells
-// per lane, 8k or 32k workgroups): each 512-thread workgroup owns a 128 x 8
-// block of columns, two consecutive x cells per lane (16-byte FP64 accesses),
-// and marches it through a chunk of 32 planes; per plane each lane reads p, k
-// and the seal bytes of its cells and writes eight output planes,
+// per lane, 8k or 32k workgroups). Each 512-thread workgroup owns a block of
+// columns and marches it through a chunk of 32 planes; per plane each lane
+// reads p, k and the seal bytes of its cells and writes eight outputs,
 // out[q][c] = p[c] + (q + seal[c]) k[c] (so that no load is dead), with
-// non-temporal stores. Rows of odd pitch take one cell per access. The eight
-// outputs go to eight planes, or to the runs of the sliced r + J layout
-// (`slices` > 0: slice i / 64 of row j holds eight runs of 64 cells).
+// non-temporal stores. The eight outputs go to eight planes (128 x 8 blocks,
+// two consecutive x cells per lane: 16-byte FP64 accesses; rows of odd pitch
+// take one cell per access), or to the runs of the sliced r + J layout
+// (`slices` > 0: slice i / 64 of row j holds eight runs of 64 cells; 64 x 8
+// blocks, one cell per lane, which measured 4% faster there than two).
 // ----------------------------------------------------------------------------
 constexpr int kProbeTx = 128, kProbeTy = 8, kProbeChunk = 32;
 
 template <class S>
 using vec2_t = S __attribute__((ext_vector_type(2)));
 
-template <class S, bool PAIR>
+// CELLS x cells per lane: 64 CELLS x 8 column blocks of 512 lanes
+template <class S, int CELLS, bool PAIR>
 __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
     stream_probe_kernel(int nx, int ny, int nz, int ldx, int ntx, int nty, int slices,
                         const S *__restrict__ p, const S *__restrict__ k,
                         const uint8_t *__restrict__ seal, S *__restrict__ out) {
   const uint32_t b = blockIdx.x, r1 = b / (uint32_t)ntx, r2 = r1 / (uint32_t)nty;
   const int lanes = kProbeTx / 2;
-  const int i = (int)(b - r1 * ntx) * kProbeTx + 2 * (int)(threadIdx.x % lanes);
+  const int i = (int)(b - r1 * ntx) * lanes * CELLS + CELLS * (int)(threadIdx.x % lanes);
   const int j = (int)(r1 - r2 * nty) * kProbeTy + (int)(threadIdx.x / lanes);
   if (i >= nx || j >= ny) return;
-  const bool two = i + 1 < nx;
+  const bool two = CELLS == 2 && i + 1 < nx;
   const int kb = (int)r2 * kProbeChunk, ke = min(kb + kProbeChunk, nz);
   const size_t plane = (size_t)ldx * ny;
   // output: plane stride, run stride and the cell's offset in its plane
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
+      for (int e = 0; e < CELLS; ++e) {
         if (e == 1 && !two) break;
         const S pc = p[c + e], kc = k[c + e];
         const int sc = seal[c + e];
@@ -392,8 +395,11 @@ __global__ void __launch_bounds__(kProbeTx / 2 * kProbeTy)
 hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, const void *p,
                                const void *k, const uint8_t *seal, void *out, bool sliced,
                                hipStream_t st) {
+  // planes: two cells per lane; sliced: one (each lane's eight stores then
+  // fall in eight whole 64-cell runs of one slice)
   const int slices = sliced ? (int)((g.nx + 63) / 64) : 0;
-  const int ntx = (int)((g.nx + kProbeTx - 1) / kProbeTx);
+  const int64_t tx = sliced ? kProbeTx / 2 : kProbeTx;
+  const int ntx = (int)((g.nx + tx - 1) / tx);
   const int nty = (int)((g.ny + kProbeTy - 1) / kProbeTy);
   const int64_t nzc = (g.nz + kProbeChunk - 1) / kProbeChunk;
   const int64_t blocks = (int64_t)ntx * nty * nzc;
@@ -406,25 +412,22 @@ hipError_t launch_stream_probe(tpfa_precision_t prec, const tpfa_grid_t &g, cons
     if (reinterpret_cast<uintptr_t>(q) % (2 * elem) != 0) pair = false;
   const dim3 grid((unsigned)blocks), block(kProbeTx / 2 * kProbeTy);
   const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
-  if (prec == TPFA_FP64) {
-    const double *pp = static_cast<const double *>(p), *kk = static_cast<const double *>(k);
-    double *oo = static_cast<double *>(out);
-    if (pair)
-      stream_probe_kernel<double, true>
+  auto run = [&](const auto *pp, const auto *kk, auto *oo) {
+    using S = std::remove_cv_t<std::remove_pointer_t<decltype(oo)>>;
+    if (sliced)
+      stream_probe_kernel<S, 1, false>
+          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
+    else if (pair)
+      stream_probe_kernel<S, 2, true>
           <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
     else
-      stream_probe_kernel<double, false>
+      stream_probe_kernel<S, 2, false>
           <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
-  } else {
-    const float *pp = static_cast<const float *>(p), *kk = static_cast<const float *>(k);
-    float *oo = static_cast<float *>(out);
-    if (pair)
-      stream_probe_kernel<float, true>
-          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
-    else
-      stream_probe_kernel<float, false>
-          <<<grid, block, 0, st>>>(nx, ny, nz, ldx, ntx, nty, slices, pp, kk, seal, oo);
-  }
+  };
+  if (prec == TPFA_FP64)
+    run(static_cast<const double *>(p), static_cast<const double *>(k), static_cast<double *>(out));
+  else
+    run(static_cast<const float *>(p), static_cast<const float *>(k), static_cast<float *>(out));
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ def test_probe_values(gpu, dtype, shape):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("shape", [(1, 1, 1), (64, 8, 32), (65, 9, 33), (130, 5, 3)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (64, 8, 32), (65, 9, 33), (130, 5, 3), (100, 37, 70),
+                                   (500, 61, 40)])
 def test_probe_sliced_values(gpu, dtype, shape):
     g = geomodel.Grid(*shape)
     rng = np.random.default_rng(sum(shape) + 1)
