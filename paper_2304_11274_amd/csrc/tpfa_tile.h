@@ -379,8 +379,28 @@ constexpr int plane_lds_bytes() {
 // Bytes of LDS one tile needs: two buffers of the (TX+2) x (TY+2) plane of
 // p, k (or t_x), mobility, seal, plus w / v for the product modes, t_ne and
 // t_se for the 10-flux stencil, t_y for the transmissibility form and k_y for
-// the per-direction form; or the shared-face layout; after the FP32 form's
-// per-plane constants.
+// the per-direction form, and the shared Jacobian faces; or the shared-face
+// layout of the residual modes; after the FP32 form's per-plane constants.
+// The FP32 Jacobian of the ratio form (and its backward-Euler variant) on
+// 512-thread tiles also evaluates each in-plane face once, in its lower cell:
+// F, dF/dp_Lo and dF/dp_Up go to LDS (one buffer of three values per
+// direction) and the upper cell reads them after a second barrier in the
+// plane. The face keeps the operands and operation order of the two-sided
+// form, so the outputs are bitwise the same, with fewer VALU instructions
+// (512x512x256, sliced outputs: 0.546 -> 0.535 ms). Only where the tile's LDS
+// still lets four workgroups share a CU (64x8, 128x4, 32x16): the 256-thread
+// tiles keep the two-sided form because the ensemble kernels size their LDS
+// for the largest of them and six more plane arrays would cost those kernels
+// a wave per SIMD, and the 256x2 and 512x1 tiles because theirs would.
+template <class S, int MODE, int TX, int TY>
+constexpr bool jacobian_shares() {
+  constexpr int HW = (TX + 2) * (TY + 2);
+  return sizeof(S) == 4 && TX * TY == 512 && base_mode(MODE) == MODE_JACOBIAN &&
+         !has_trans(MODE) && !has_k3(MODE) &&
+         4 * (plane_lds_bytes<S>() + 2 * HW * (3 * (int)sizeof(S) + 1) + 6 * HW * (int)sizeof(S)) <=
+             kMaxLds;
+}
+
 template <class S, int MODE, int TX, int TY>
 constexpr int tile_lds_bytes() {
   constexpr int HW = TX > 0 ? (TX + 2) * (TY + 2) : kDynHW;
@@ -390,7 +410,8 @@ constexpr int tile_lds_bytes() {
                          (has_trans(MODE) || has_k3(MODE) ? 1 : 0);
   return plane_lds_bytes<S>() + (tile_shares<S, MODE, TX, TY>()
                                      ? share_lds_bytes<S, MODE, TX, TY>()
-                                     : 2 * HW * ((int)sizeof(S) * arrays + 1));
+                                     : 2 * HW * ((int)sizeof(S) * arrays + 1)) +
+         (jacobian_shares<S, MODE, TX, TY>() ? 6 * HW * (int)sizeof(S) : 0);
 }
 
 // Lower-cell faces a halo cell evaluates for the tile in the shared-face form.
@@ -677,6 +698,7 @@ struct Tile {
   static constexpr bool K3 = has_k3(MODE);      // per-direction permeability arrays
   static constexpr bool YF = TIN || K3;         // a y-face field is staged (t_y or k_y)
   static constexpr bool SHARE = tile_shares<S, MODE, TX, TY>();
+  static constexpr bool JSHARE = jacobian_shares<S, MODE, TX, TY>();
   static constexpr int NT = DYN ? 256 : TX * TY;  // threads
   static constexpr int NH = 2 * (TX + TY) + (R10 ? 4 : 0);  // halo ring (corners: 10-flux only)
   static constexpr int HC = DYN ? 1 : (NH + NT - 1) / NT;  // halo cells staged per thread
@@ -695,6 +717,7 @@ struct Tile {
   S *s_yf;  // y-face field, two-sided layout only: t_y (transmissibility input; t_x is
             // staged in s_k) or k_y (per-direction form; k_x is staged in s_k)
   uint8_t *s_s;
+  S *s_jx, *s_jy;  // shared Jacobian faces: F, dLo, dUp of each slot's +x / +y face
   double *s_hk;  // FP32 form: hydrostatic part of the z-face potential, planes kb-1 .. ke
   float *s_rk;   // FP32 form: reference density of planes kb-1 .. ke
   size_t plane;
@@ -740,7 +763,9 @@ struct Tile {
     s_tn = s_w + (NEEDW ? 2 * HW : 0);
     s_ts = s_tn + (R10 ? 2 * HW : 0);
     s_yf = s_ts + (R10 ? 2 * HW : 0);
-    s_s = reinterpret_cast<uint8_t *>(s_yf + (YF ? 2 * HW : 0));
+    s_jx = s_yf + (YF ? 2 * HW : 0);
+    s_jy = s_jx + 3 * HW;
+    s_s = reinterpret_cast<uint8_t *>(s_jx + (JSHARE ? 6 * HW : 0));
     s_fx = s_l + 2 * HW;
     s_fy = s_fx + 2 * HW;
     s_fne = s_fy + 2 * HW;
@@ -823,7 +848,7 @@ struct Tile {
         role = c == 0 ? kNE : c == 2 ? kSE : 0u;
         need = c == 0 ? kNeedTn : c == 2 ? kNeedTs : 0u;
       }
-      hr[q] = SHARE ? role : 0u;
+      hr[q] = SHARE || JSHARE ? role : 0u;
       hn[q] = need;
       hl[q] = l;
       hv[q] = l >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
@@ -939,6 +964,22 @@ struct Tile {
     return f;
   }
 
+  // Shared Jacobian faces: F, dLo, dUp of the face of slot l in the three
+  // arrays of its direction. One buffer: a plane's faces are written after its
+  // staging barrier and read before the next plane's.
+  __device__ __forceinline__ void put_face(S *s_j, int l, const Face<S> &x) const {
+    s_j[l] = x.F;
+    s_j[HW + l] = x.dLo;
+    s_j[2 * HW + l] = x.dUp;
+  }
+  __device__ __forceinline__ Face<S> get_face(const S *s_j, int l) const {
+    Face<S> x{};
+    x.F = s_j[l];
+    x.dLo = s_j[HW + l];
+    x.dUp = s_j[2 * HW + l];
+    return x;
+  }
+
   // One plane k. c0/d0: own cell at k; c1: own cell at k+1 (loaded), d1 is
   // computed here; c2 receives the prefetch of k+2. h0: halo cell at k, h1
   // receives the halo cell at k+1. zm: face (k-1, k); zp receives face (k, k+1).
@@ -968,10 +1009,12 @@ struct Tile {
       s_tn[b + ol] = c0.tn;
       s_ts[b + ol] = c0.ts;
     }
+    S hlam[HC];
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
       if (hl[q] < 0) continue;
       const Props<S> dh = props(h0[q].p, rkk, a);
+      hlam[q] = dh.lam;
       const int l = b + hl[q];
       s_p[l] = h0[q].p;
       s_k[l] = TIN ? h0[q].tx : h0[q].k;
@@ -1015,6 +1058,33 @@ struct Tile {
           vjp_face_own<false, WR>(c0.k, s_k[q], open, c0.p, s_p[q], d0.lam, s_l[q], dw, cf,
                                   vo[axis], vo[2 + axis], A2, &f[n].F);
       }
+    } else if constexpr (JSHARE) {
+      // the +x and +y faces, whose lower cell is the own cell, for the own
+      // cell and for its +x / +y neighbour (the -x / -y faces are read back
+      // after the barrier below)
+#pragma unroll
+      for (int n = 1; n < 4; n += 2) {
+        const int axis = n >> 1;
+        const int q = b + sl[n];
+        f[n] = face_h<true, false>(a, axis == 0 ? A2x : A2y, c0.k, s_k[q],
+                                   (c0.s & (1u << axis)) == 0u, c0.p, s_p[q], d0.lam, s_l[q]);
+      }
+      put_face(s_jx, ol, f[1]);
+      put_face(s_jy, ol, f[3]);
+      // faces entering the tile from the -x / -y side of the halo ring
+#pragma unroll
+      for (int q = 0; q < HC; ++q) {
+        const uint32_t role = hr[q];
+        if (role == 0u) continue;
+        const int l = b + hl[q];
+        const Cell<S> &h = h0[q];
+        if (role & kPX)
+          put_face(s_jx, hl[q], face_h<true, false>(a, A2x, h.k, s_k[l + 1], (h.s & 1u) == 0u,
+                                                    h.p, s_p[l + 1], hlam[q], s_l[l + 1]));
+        if (role & kPY)
+          put_face(s_jy, hl[q], face_h<true, false>(a, A2y, h.k, s_k[l + Wv], (h.s & 2u) == 0u,
+                                                    h.p, s_p[l + Wv], hlam[q], s_l[l + Wv]));
+      }
     } else {
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
@@ -1050,6 +1120,11 @@ struct Tile {
     zp.w = c0.w;
     f[5] = zp;
     wn[5] = c1.w;
+    if constexpr (JSHARE) {
+      __syncthreads();
+      f[0] = get_face(s_jx, ol - 1);
+      f[2] = get_face(s_jy, ol - Wv);
+    }
 
     // the four in-plane diagonal faces of the 10-flux stencil: transmissibility
     // given (tne on the face's left end for (i,j)-(i+1,j+1), tse for

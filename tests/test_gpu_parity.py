@@ -402,6 +402,39 @@ def test_shared_face_residual_bitwise(gpu, orc, shape, prec):
             assert np.array_equal(r, r_ref), (tile, kz)
 
 
+# ---------------------------------------------------------------------------
+# The FP32 Jacobian on the 64x8, 128x4 and 32x16 tiles evaluates each in-plane
+# face once, in its lower cell, and hands F and both derivatives to the upper
+# cell through LDS; the other tiles evaluate each face from both sides. Both
+# give the same r and J bit for bit, in the ratio form and the backward-Euler
+# Jacobian, for every tile shape and z-chunk.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(70, 9, 37), (129, 13, 3), (17, 33, 5), (1, 6, 4), (5, 1, 9)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_shared_face_fp32_jacobian_bitwise(gpu, orc, shape):
+    geo = small(shape, seed=29)
+    pref_h, dp, k32, _, _ = fp32_inputs(orc, geo)
+    rng = np.random.default_rng(sum(shape))
+    phi = rng.uniform(0.1, 0.3, geo.grid.shape).astype(np.float32)
+    dpn = (dp - rng.uniform(0.0, 1e4, geo.grid.shape)).astype(np.float32)
+    acc = dict(phi=dev(phi), p_prev=dev(dpn), dt=86400.0, cr=1e-9)
+    k, p = dev(k32), dev(dp)
+    kw = dict(seal=dev(geo.seal), pref=dev(pref_h), ry=geo.ry, rz=geo.rz)
+    print(f"shared-face fp32 jacobian {shape}", flush=True)
+    ref = None
+    for tile in range(len(gpu.tile_shapes())):
+        for kz in (0, 1, 5):
+            out = [host(x) for x in gpu.jacobian(geo.grid, geo.fluid, k, p, tile=tile,
+                                                 kz_chunk=kz, **kw)]
+            out += [host(x) for x in gpu.jacobian_be(geo.grid, geo.fluid, k, p, acc, tile=tile,
+                                                     kz_chunk=kz, **kw)]
+            if ref is None:
+                ref = out
+            else:
+                assert all(np.array_equal(x, y) for x, y in zip(out, ref)), (tile, kz)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_ensemble_residual_mode_matches_single_launches(gpu, orc, prec):
     models = geomodel.ensemble(n_models=9, scale=0.15, base_seed=4100)
