@@ -147,6 +147,11 @@ def test_sliced_fp64_jacobian_defaults():
     odd = rl(geomodel.Grid(520, 500, 512), "jacobian", F64, sliced=True)
     assert (odd["tile"], odd["kz_chunk"], odd["order"]) == (3, 64, "natural"), odd
     assert rl(G512, "jacobian", F32, sliced=True)["order"] == "bands"
+    # the FP32 sliced Jacobian of the ratio form also takes 64-plane chunks,
+    # its plane layout 32
+    big32 = geomodel.Grid(512, 512, 512)
+    assert rl(big32, "jacobian", F32, sliced=True)["kz_chunk"] == 64
+    assert rl(big32, "jacobian", F32)["kz_chunk"] == 32
     assert rl(G512, "jacobian", F64, tile=3, sliced=True)["order"] == "natural"
 
 
