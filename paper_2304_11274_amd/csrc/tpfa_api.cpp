@@ -146,15 +146,16 @@ int default_tile(const tpfa_grid_t &g, tpfa::Mode mode, tpfa_precision_t prec, i
 }
 
 // z planes per workgroup: 32 for the residual-only modes and the FP64
-// Jacobians (0.7% faster than 16 there; 64 with sliced outputs, 0.4% faster
-// than 32 on 512x512x256) and for the FP32 Jacobian of the ratio form (1%
-// faster; 64 with sliced outputs, 1% faster than 32, while 16, 24 and 48 were
-// slower), 16 for the other products (the FP32 backward-Euler and
-// per-direction Jacobians ran 0.6-1.3% slower with 32).
+// Jacobians (0.7% faster than 16 there; 128 with sliced outputs: on
+// 512x512x256 64 was 0.4% faster than 32 and 128 0.35% faster than 64, 256 no
+// faster) and for the FP32 Jacobian of the ratio form (1% faster; 64 with
+// sliced outputs, 1% faster than 32, while 16, 24 and 48 were slower), 16 for
+// the other products (the FP32 backward-Euler and per-direction Jacobians ran
+// 0.6-1.3% slower with 32).
 int default_kz(tpfa::Mode mode, tpfa_precision_t prec, int form, bool sliced) {
   const int b = tpfa::base_mode(mode);
   if (b == tpfa::MODE_RESIDUAL || mode == tpfa::MODE_RES10) return 32;
-  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64) return sliced ? 64 : 32;
+  if (b == tpfa::MODE_JACOBIAN && prec == TPFA_FP64) return sliced ? 128 : 32;
   if (mode == tpfa::MODE_JACOBIAN && form == 0) return sliced ? 64 : 32;
   return 16;
 }

@@ -136,16 +136,16 @@ def test_pad_writes_flag_is_kept():
 
 
 def test_sliced_fp64_jacobian_defaults():
-    """Sliced FP64 Jacobians on large grids: 64-plane chunks and the y-fast
+    """Sliced FP64 Jacobians on large grids: 128-plane chunks and the y-fast
     order where the tile rows are a multiple of 8; the plane layout keeps 32
-    planes and the natural order. (512 planes: a launch large enough that the
-    small-grid re-chunking keeps the default with any residency.)"""
-    s = rl(geomodel.Grid(512, 512, 512), "jacobian", F64, sliced=True)
-    assert (s["tile"], s["kz_chunk"], s["order"]) == (3, 64, "yfast"), s
+    planes and the natural order. (1024 planes: a launch large enough that
+    the small-grid re-chunking keeps the default with any residency.)"""
+    s = rl(geomodel.Grid(512, 512, 1024), "jacobian", F64, sliced=True)
+    assert (s["tile"], s["kz_chunk"], s["order"]) == (3, 128, "yfast"), s
     p = rl(G512, "jacobian", F64)
     assert (p["tile"], p["kz_chunk"], p["order"]) == (3, 32, "natural"), p
-    odd = rl(geomodel.Grid(520, 500, 512), "jacobian", F64, sliced=True)
-    assert (odd["tile"], odd["kz_chunk"], odd["order"]) == (3, 64, "natural"), odd
+    odd = rl(geomodel.Grid(520, 500, 1024), "jacobian", F64, sliced=True)
+    assert (odd["tile"], odd["kz_chunk"], odd["order"]) == (3, 128, "natural"), odd
     assert rl(G512, "jacobian", F32, sliced=True)["order"] == "bands"
     # the FP32 sliced Jacobian of the ratio form also takes 64-plane chunks,
     # its plane layout 32
