@@ -31,6 +31,11 @@ def test_benchmark_launches():
     assert rl(G512, "jacobian_be", F32)["kz_chunk"] == 16
     assert rl(G512, "residual")["shape"] == (64, 4)   # shared faces, more LDS
     assert rl(G512, "residual", F32)["shape"] == (64, 8)
+    # the FP32 residual of the ratio form takes 64-plane chunks, the FP64 one 32
+    # (a launch large enough that the small-grid re-chunking keeps the default)
+    big_r = geomodel.Grid(512, 512, 2048)
+    assert rl(big_r, "residual", F32)["kz_chunk"] == 64
+    assert rl(big_r, "residual")["kz_chunk"] == 32
     for op in ("vjp", "jvp", "jvp_be"):
         r = rl(G512, op)
         assert (r["shape"], r["kz_chunk"], r["xcd_remap"]) == ((64, 4), 16, False), op
